@@ -1,0 +1,253 @@
+"""Python face of the FP64 CPU oracle (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg import
+this module; the product package never does.  The arithmetic lives in
+ile_oracle.c (plain C, FP64, no FMA contraction); the numpy code here builds
+the physically consistent injection instance and the direct form of the
+likelihood used to pin it, both written from the paper:
+
+* Eq. (1): ln L = sum_k <h_k|d_k> - <h_k|h_k>/2 (the printed bracket of
+  Eq. (1) is misplaced; this is the reading consistent with Eq. (7));
+* Eq. (2) with a white noise spectrum: <a|b> = sum_i conj(a_i) b_i;
+* Eq. (8): Q_k,lm(s) = <h_lm shifted by s | d_k>, U = <h_lm|h_l'm'>,
+  V = <h_lm^*|h_l'm'>.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libile_oracle.so")
+_lib = None
+
+_dp = C.POINTER(C.c_double)
+_i64p = C.POINTER(C.c_int64)
+
+
+class OrcConfig(C.Structure):
+    _fields_ = [("n_det", C.c_int32), ("n_lm", C.c_int32),
+                ("modes", C.POINTER(C.c_int32)), ("srate_hz", C.c_double),
+                ("n_t", C.c_int32), ("d_ref_mpc", C.c_double),
+                ("gmst_rad", C.c_double), ("earth_radius_m", C.c_double),
+                ("t0_s", C.c_double), ("n_q", C.c_int64)]
+
+
+class OrcDetector(C.Structure):
+    _fields_ = [("lat_deg", C.c_double), ("lon_deg", C.c_double),
+                ("xarm_az_deg", C.c_double)]
+
+
+class OrcResult(C.Structure):
+    _fields_ = [("ln_L_marg", C.c_double), ("n_eff", C.c_double),
+                ("n_eff_kish", C.c_double), ("sigma", C.c_double),
+                ("max_lnL", C.c_double), ("n_samples", C.c_int64)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _build
+            _build.build()
+        _lib = C.CDLL(_LIB_PATH)
+        _lib.orc_delay.restype = C.c_double
+        _lib.orc_logmeanexp.restype = C.c_double
+        _lib.orc_eval.restype = C.c_int64
+        _lib.orc_lnL_series.restype = C.c_int
+        _lib.orc_lnL_series_at.restype = C.c_int
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(_dp)
+
+
+# ------------------------------------------------------------- geometry
+def detector_frame(det, R=6378.0e3):
+    r = np.zeros(3)
+    D = np.zeros(9)
+    d = OrcDetector(*det)
+    lib().orc_detector_frame(C.byref(d), C.c_double(R), _p(r), _p(D))
+    return r, D.reshape(3, 3)
+
+
+def antenna(D, ra, dec, psi, gmst=0.0):
+    D = np.ascontiguousarray(D, np.float64).reshape(9)
+    fp, fx = C.c_double(), C.c_double()
+    lib().orc_antenna(_p(D), C.c_double(ra), C.c_double(dec), C.c_double(psi),
+                      C.c_double(gmst), C.byref(fp), C.byref(fx))
+    return fp.value, fx.value
+
+
+def delay(r, ra, dec, gmst=0.0):
+    r = np.ascontiguousarray(r, np.float64)
+    return lib().orc_delay(_p(r), C.c_double(ra), C.c_double(dec),
+                           C.c_double(gmst))
+
+
+def sylm(l, m, theta, phi):
+    re, im = C.c_double(), C.c_double()
+    lib().orc_sylm(int(l), int(m), C.c_double(theta), C.c_double(phi),
+                   C.byref(re), C.byref(im))
+    return complex(re.value, im.value)
+
+
+# ------------------------------------------------------------ likelihood
+class Ctx:
+    """Holds one instance in the oracle's C structures."""
+
+    def __init__(self, inst):
+        self.inst = inst
+        self.modes = np.ascontiguousarray(np.array(inst.modes, np.int32).reshape(-1))
+        self.cfg = OrcConfig(inst.n_det, inst.n_lm,
+                             self.modes.ctypes.data_as(C.POINTER(C.c_int32)),
+                             inst.srate_hz, inst.n_t, inst.d_ref_mpc,
+                             inst.gmst_rad, inst.earth_radius_m, inst.t0_s,
+                             inst.n_q)
+        self.dets = (OrcDetector * inst.n_det)(*[OrcDetector(*d) for d in inst.dets])
+        self.Q = np.ascontiguousarray(inst.Q, np.complex128).view(np.float64)
+        self.U = np.ascontiguousarray(inst.U, np.complex128).view(np.float64)
+        self.V = np.ascontiguousarray(inst.V, np.complex128).view(np.float64)
+
+    def window_position(self, theta):
+        th = np.ascontiguousarray(theta, np.float64)
+        x = np.zeros(self.inst.n_det)
+        lib().orc_window_position(C.byref(self.cfg), self.dets, _p(th), _p(x))
+        return x
+
+    def lnL_series(self, theta, s_start=None):
+        th = np.ascontiguousarray(theta, np.float64)
+        out = np.zeros(self.inst.n_t)
+        if s_start is None:
+            rc = lib().orc_lnL_series(C.byref(self.cfg), _p(self.Q), _p(self.U),
+                                      _p(self.V), self.dets, _p(th), _p(out))
+        else:
+            s = np.ascontiguousarray(s_start, np.int64)
+            rc = lib().orc_lnL_series_at(C.byref(self.cfg), _p(self.Q),
+                                         _p(self.U), _p(self.V), self.dets,
+                                         _p(th), s.ctypes.data_as(_i64p), _p(out))
+        if rc != 0:
+            raise ValueError("window outside Q or invalid sample")
+        return out
+
+    def eval(self, samples, n_threads=0):
+        s = np.ascontiguousarray(samples, np.float64)
+        n = s.shape[1]
+        out = np.zeros(n)
+        lib().orc_eval(C.byref(self.cfg), _p(self.Q), _p(self.U), _p(self.V),
+                       self.dets, _p(s), C.c_int64(n), _p(out), int(n_threads))
+        return out
+
+
+def logmeanexp(x):
+    x = np.ascontiguousarray(x, np.float64)
+    return lib().orc_logmeanexp(_p(x), C.c_int64(x.size))
+
+
+def integrate(lnLmargT, ln_p, ln_q):
+    a = np.ascontiguousarray(lnLmargT, np.float64)
+    b = np.ascontiguousarray(ln_p, np.float64)
+    c = np.ascontiguousarray(ln_q, np.float64)
+    r = OrcResult()
+    lib().orc_integrate(_p(a), _p(b), _p(c), C.c_int64(a.size), C.byref(r))
+    return dict(ln_L_marg=r.ln_L_marg, n_eff=r.n_eff, n_eff_kish=r.n_eff_kish,
+                sigma=r.sigma, max_lnL=r.max_lnL, n_samples=r.n_samples)
+
+
+# ------------------------------------------------------------ sampling
+def philox4x32_10(ctr, key):
+    c = (C.c_uint32 * 4)(*ctr)
+    k = (C.c_uint32 * 2)(*key)
+    o = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return list(o)
+
+
+def prior_draw(seed, first, n, d_min=10.0, d_max=1000.0, t_ref_max=0.01):
+    s = np.zeros((7, n))
+    lp = np.zeros(n)
+    lib().orc_prior_draw(C.c_uint64(seed), C.c_int64(first), C.c_int64(n),
+                         C.c_double(d_min), C.c_double(d_max),
+                         C.c_double(t_ref_max), _p(s), C.c_int64(n), _p(lp))
+    return s, lp
+
+
+# ------------------------------------------------- injection (pins only)
+def mode_factors(inst, theta):
+    """(F_k = F+ + i Fx per detector, -2Y_lm(iota, phi) per mode)."""
+    F = np.zeros(inst.n_det, np.complex128)
+    for k, d in enumerate(inst.dets):
+        _, D = detector_frame(d, inst.earth_radius_m)
+        fp, fx = antenna(D, theta[0], theta[1], theta[2], inst.gmst_rad)
+        F[k] = fp + 1j * fx
+    iota = np.arccos(theta[4])
+    Y = np.array([sylm(l, m, iota, theta[3]) for (l, m) in inst.modes])
+    return F, Y
+
+
+def detector_response(inst, h_lm, theta, lag):
+    """h_k[i] = Re(F_k (Dref/D) sum_lm Y_lm h_lm[i - lag_k]) (Eqs. (5), (6)
+    and the detector response below Eq. (6), white-noise discrete form with
+    circular shifts)."""
+    F, Y = mode_factors(inst, theta)
+    kappa = inst.d_ref_mpc / theta[5]
+    out = np.zeros((inst.n_det, h_lm.shape[1]))
+    for k in range(inst.n_det):
+        z = np.zeros(h_lm.shape[1], np.complex128)
+        for a in range(inst.n_lm):
+            z += Y[a] * np.roll(h_lm[a], int(lag[k]))
+        out[k] = (F[k] * kappa * z).real
+    return out
+
+
+def inner(a, b):
+    """Eq. (2) for white noise, discrete: sum_i conj(a_i) b_i."""
+    return np.vdot(a, b)
+
+
+def direct_lnL(data, model):
+    """Eq. (1) as read: sum_k -1/2 (<h_k - d_k|h_k - d_k> - <d_k|d_k>)."""
+    tot = 0.0
+    for k in range(data.shape[0]):
+        r = model[k] - data[k]
+        tot += -0.5 * (inner(r, r).real - inner(data[k], data[k]).real)
+    return tot
+
+
+def injection_instance(base, h_lm, theta_inj, noise_sigma=0.0, rng=None):
+    """Physically consistent instance: the data d_k is the response to
+    theta_inj (zero noise unless noise_sigma > 0), and Q, U, V are the
+    white-noise inner products of Eq. (8) with circular shifts.
+
+    Q index s of the instance corresponds to arrival lag s - n_q/2 samples
+    after the start of h_lm, matching t0 = -(n_q/2) dt.
+    Returns (instance, data, injected lags)."""
+    import copy
+    inst = copy.copy(base)
+    n = h_lm.shape[1]
+    dt = 1.0 / inst.srate_hz
+    t0 = -(n // 2) * dt
+    lags = []
+    for k, d in enumerate(inst.dets):
+        r, _ = detector_frame(d, inst.earth_radius_m)
+        tau = delay(r, theta_inj[0], theta_inj[1], inst.gmst_rad)
+        x = (theta_inj[6] + tau - t0) / dt
+        lags.append(int(np.floor(x + 0.5)))
+    lags = np.array(lags)
+    data = detector_response(inst, h_lm, theta_inj, lags)
+    if noise_sigma > 0:
+        data = data + noise_sigma * rng.standard_normal(data.shape)
+    A = h_lm.T  # [i, lm]
+    U = np.stack([A.conj().T @ A for _ in range(inst.n_det)])
+    V = np.stack([A.T @ A for _ in range(inst.n_det)])
+    Q = np.zeros((inst.n_det, inst.n_lm, n), np.complex128)
+    for k in range(inst.n_det):
+        D = np.fft.fft(data[k])
+        for a in range(inst.n_lm):
+            # Q[s] = sum_i conj(h[(i - s) mod n]) d[i]: circular correlation
+            Q[k, a] = np.fft.ifft(np.conj(np.fft.fft(h_lm[a])) * D)
+    inst.Q, inst.U, inst.V = Q, U, V
+    return inst, data, lags

@@ -1,0 +1,179 @@
+"""Seeded synthetic inputs for the ILE hot path.
+
+This module is the one source of inputs shared by the HIP path and the CPU
+oracle.  It holds none of the method's arithmetic (no antenna patterns, no
+harmonics, no delays, no likelihood): only stand-in series for Q_k,lm, Gram
+matrices for U_k and V_k, and extrinsic samples drawn from the prior.  It
+imports nothing from the rest of the package.
+
+The paper measures on zero-noise injections made with waveform models that
+are not available here (Sec. III.A); the stand-ins keep the shapes of its
+workloads: 2-3 L-shaped detectors, 4096 or 16384 Hz series, l=2..4 modes,
+p(D) ~ D^2 up to 1 Gpc, blocks of extrinsic samples.
+
+Q stand-in (one per detector k and mode a):
+    Q[i] = A_a exp(-u^2 / 2 sigma_t^2) exp(i (phi_ka + 2 pi (f0 u + fdot u^2/2)))
+           + n_i,   u = (i - i_k) dt,  n_i ~ CN(0, 1)
+with sigma_t = 4 ms, f0 = 60 Hz, fdot = 4000 Hz/s, A_a = 20 * 0.3**a (a = the
+position of the mode in MODE_ORDER), i_k = n_q/2 + delta_k where delta_k is a
+seeded integer offset within +-8 ms (a stand-in for unequal arrival times).
+U_k = A^H A / n_v, V_k = A^T A / n_v from one seeded complex Gaussian
+matrix A (n_v = 64 rows), scaled so trace(U_k)/n_lm = mean_a A_a^2; using the
+same A makes V complex-symmetric and the quadratic form non-negative.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+C_LIGHT = 299792458.0
+EARTH_RADIUS_M = 6378.0e3
+
+# (lat deg, lon deg, x-arm azimuth deg counter-clockwise from local East)
+DETECTORS = {
+    "D1": (46.455, -119.408, 126.0),
+    "D2": (30.563, -90.774, 198.0),
+    "D3": (43.631, 10.504, 71.0),
+}
+
+# Canonical mode order; configurations take prefixes of it (5, 9, 13, 21).
+MODE_ORDER = [
+    (2, 2), (2, -2), (2, 1), (2, -1), (2, 0),
+    (3, 3), (3, -3), (3, 2), (3, -2),
+    (4, 4), (4, -4), (4, 3), (4, -3),
+    (3, 1), (3, -1), (3, 0), (4, 2), (4, -2), (4, 1), (4, -1), (4, 0),
+]
+
+D_REF_MPC = 100.0
+D_MIN_MPC = 10.0
+D_MAX_MPC = 1000.0
+T_REF_MAX_S = 0.010
+
+
+@dataclass
+class Instance:
+    """One intrinsic point: Q, U, V and the static configuration."""
+    dets: list            # [(lat, lon, az)]
+    modes: list           # [(l, m)]
+    srate_hz: float
+    n_t: int
+    Q: np.ndarray         # complex128 [n_det][n_lm][n_q]
+    U: np.ndarray         # complex128 [n_det][n_lm][n_lm]
+    V: np.ndarray         # complex128 [n_det][n_lm][n_lm]
+    d_ref_mpc: float = D_REF_MPC
+    gmst_rad: float = 0.0
+    earth_radius_m: float = EARTH_RADIUS_M
+    t_ref_max_s: float = T_REF_MAX_S
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_det(self):
+        return len(self.dets)
+
+    @property
+    def n_lm(self):
+        return len(self.modes)
+
+    @property
+    def n_q(self):
+        return self.Q.shape[-1]
+
+    @property
+    def t0_s(self):
+        """Time of Q[0] relative to the geocentre event time."""
+        return -(self.n_q // 2) / self.srate_hz
+
+
+def make_instance(det_names, n_lm, n_q, srate_hz, n_t, seed, *,
+                  noise=True, n_v=64):
+    """Stand-in Q, U, V for one intrinsic point (recipe in the module doc)."""
+    rng = np.random.default_rng(seed)
+    dets = [DETECTORS[d] for d in det_names]
+    modes = MODE_ORDER[:n_lm]
+    n_det = len(dets)
+    dt = 1.0 / srate_hz
+    amp = 20.0 * 0.3 ** np.arange(n_lm)
+    i = np.arange(n_q)
+    Q = np.empty((n_det, n_lm, n_q), np.complex128)
+    max_off = int(0.008 / dt)
+    for k in range(n_det):
+        ik = n_q // 2 + int(rng.integers(-max_off, max_off + 1))
+        u = (i - ik) * dt
+        env = np.exp(-u * u / (2 * 0.004 ** 2))
+        chirp = 2 * np.pi * (60.0 * u + 0.5 * 4000.0 * u * u)
+        for a in range(n_lm):
+            ph = rng.uniform(0, 2 * np.pi)
+            Q[k, a] = amp[a] * env * np.exp(1j * (ph + chirp))
+            if noise:
+                Q[k, a] += (rng.standard_normal(n_q) +
+                            1j * rng.standard_normal(n_q)) / math.sqrt(2.0)
+    U = np.empty((n_det, n_lm, n_lm), np.complex128)
+    V = np.empty((n_det, n_lm, n_lm), np.complex128)
+    target = float(np.mean(amp ** 2))
+    for k in range(n_det):
+        A = (rng.standard_normal((n_v, n_lm)) +
+             1j * rng.standard_normal((n_v, n_lm))) / math.sqrt(2.0)
+        Uk = A.conj().T @ A / n_v
+        Vk = A.T @ A / n_v
+        s = target / (np.trace(Uk).real / n_lm)
+        U[k] = 0.5 * (Uk + Uk.conj().T) * s      # exactly Hermitian
+        V[k] = 0.5 * (Vk + Vk.T) * s             # exactly symmetric
+    return Instance(dets=dets, modes=modes, srate_hz=float(srate_hz),
+                    n_t=int(n_t), Q=Q, U=U, V=V,
+                    meta=dict(seed=seed, det_names=list(det_names)))
+
+
+def prior_samples(n, seed, *, d_min=D_MIN_MPC, d_max=D_MAX_MPC,
+                  t_ref_max=T_REF_MAX_S):
+    """Extrinsic samples from the prior, SoA [7][n], and their log density.
+
+    Prior: ra ~ U[0, 2pi); sin(dec) ~ U[-1, 1]; psi ~ U[0, pi);
+    phi ~ U[0, 2pi); cos(iota) ~ U[-1, 1]; p(D) ~ D^2 on [d_min, d_max];
+    t_ref ~ U[-t_ref_max, t_ref_max].  ln p is the density in the
+    coordinates (ra, dec, psi, phi, cos iota, D, t_ref).
+    """
+    rng = np.random.default_rng(seed)
+    s = np.empty((7, n), np.float64)
+    s[0] = rng.uniform(0, 2 * np.pi, n)
+    s[1] = np.arcsin(rng.uniform(-1, 1, n))
+    s[2] = rng.uniform(0, np.pi, n)
+    s[3] = rng.uniform(0, 2 * np.pi, n)
+    s[4] = rng.uniform(-1, 1, n)
+    v3 = d_max ** 3 - d_min ** 3
+    s[5] = np.cbrt(d_min ** 3 + rng.uniform(0, 1, n) * v3)
+    s[6] = rng.uniform(-t_ref_max, t_ref_max, n)
+    ln_p = (-np.log(2 * np.pi) + np.log(np.cos(s[1]) / 2) - np.log(np.pi)
+            - np.log(2 * np.pi) - np.log(2.0) + np.log(3 * s[5] ** 2 / v3)
+            - np.log(2 * t_ref_max))
+    return s, ln_p
+
+
+# ------------------------------------------------------------- workloads
+def config1(seed=None):
+    """Plain ILE, one point: D1+D2, l=2 (5 modes), 4096 points at 4096 Hz,
+    201 bins, 1e4 prior samples."""
+    seed = 1001 if seed is None else seed
+    return make_instance(["D1", "D2"], 5, 4096, 4096.0, 201, seed)
+
+
+def config2(seed=None):
+    """Plain ILE at scale: D1+D2+D3, l=2..4 (21 modes), 16384 points at
+    16384 Hz, 1601 bins, 1e6 prior samples."""
+    seed = 2001 if seed is None else seed
+    return make_instance(["D1", "D2", "D3"], 21, 16384, 16384.0, 1601, seed)
+
+
+CONFIG_SAMPLES = {1: (10_000, 1002), 2: (1_000_000, 2002)}
+
+
+def batched_point(p, *, n_q=16384, srate_hz=16384.0):
+    """Point p of the batched workload: 3 detectors, n_lm in {5, 9, 13, 21}
+    and n_t = 2h+1 with h ~ U{100..800}, both chosen by the point's seed."""
+    seed = 100_000 + p
+    rng = np.random.default_rng(seed)
+    n_lm = int(rng.choice([5, 9, 13, 21]))
+    n_t = 2 * int(rng.integers(100, 801)) + 1
+    return make_instance(["D1", "D2", "D3"], n_lm, n_q, srate_hz, n_t,
+                         seed + 7_000_000)
