@@ -1,0 +1,197 @@
+/*
+ * ile.h -- C ABI of libile, the MI355X (gfx950) implementation of the
+ * extrinsic-marginalized likelihood of RIFT's ILE step, after Wysocki,
+ * O'Shaughnessy, Fang and Lange, "Accelerating parameter inference with
+ * graphics processing units", arXiv:1902.04934, Sec. II.A-II.C.
+ *
+ * For one intrinsic point the caller supplies the precomputed inner-product
+ * series Q_k,lm(t) and the mode-overlap matrices U_k, V_k of Eq. (8); for a
+ * block of extrinsic samples theta_alpha the library evaluates Eq. (7) on a
+ * grid of n_t time bins, marginalizes over time (Eq. (9)) and reduces the
+ * importance-weighted samples to ln L_marg (Eq. (4)) and n_eff (Sec. II.C).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Sample layout: SoA double samples[7][N], parameter rows
+ *   0 ra [rad], 1 dec [rad], 2 psi [rad], 3 phi [rad], 4 cos(iota),
+ *   5 D [Mpc], 6 t_ref [s]  (bin-grid centre, geocentre time).
+ * Detector response: F_k = F+ + i Fx with the antenna patterns of an
+ *   L-shaped detector (x-arm azimuth counted counter-clockwise from local
+ *   East, y-arm 90 degrees further, spherical Earth of radius
+ *   earth_radius_m); the paper prints F+ - i Fx beside Eq. (7), but only
+ *   F+ + i Fx makes Eq. (7) equal Eq. (1) for h = h+ - i hx (Eq. (5)).
+ * Harmonics: -2Y_lm(iota, phi) in the Wigner-d form; modes are any (l, m)
+ *   with 2 <= l <= 8, |m| <= l.
+ * Time: Q[i] is the value at detector time t0 + i/srate (t0 given at
+ *   set_data).  Sample alpha and bin j (0 <= j < n_t, n_t odd) mean the
+ *   geocentre time t_ref + (j - (n_t-1)/2)/srate; detector k reads
+ *   Q_k,lm[s_k + j] with s_k = floor((t_ref + tau_k - t0) srate + 1/2)
+ *   - (n_t-1)/2 and tau_k = -n.r_k/c (n towards the source).
+ * Likelihood per bin (Eq. (7)):
+ *   L_alpha,j = sum_k Re sum_lm conj(c_k,lm) Q_k,lm[s_k + j] - q_alpha,
+ *   c_k,lm = (d_ref/D) F_k Y_lm,
+ *   q_alpha = (d_ref/D)^2/4 sum_k [ |F_k|^2 Y^H U_k Y + Re(F_k^2 Y^T V_k Y) ].
+ * Time marginalization (Eq. (9)) with T = n_t/srate, rectangle rule:
+ *   lnLmargT_alpha = log( (1/n_t) sum_j exp(L_alpha,j) ).
+ * Importance sampling (Eq. (4), Sec. II.C): ln w = lnLmargT + ln p - ln q,
+ *   ln_L_marg = log(mean w), n_eff = sum w / max w,
+ *   n_eff_kish = (sum w)^2 / sum w^2,
+ *   sigma_ln_L = sqrt(sum w^2 / (sum w)^2 - 1/N)  (relative error of mean w).
+ *
+ * Precision: FP64 evaluates everything in double.  FP32 and BF16 run the
+ * bulk Q contraction in float (BF16: hi/lo bfloat16 split of Q and of the
+ * coefficients on the matrix cores, float accumulation); the quadratic term,
+ * the time log-sum-exp and the sample reduction stay in double.
+ *
+ * Ownership and threading: the caller owns every buffer it passes; the
+ * library copies Q/U/V at set_data and keeps no caller pointer.  A context
+ * owns its device memory and one stream (the caller's, if given).  A
+ * context is not thread-safe; distinct contexts are independent.
+ *
+ * Errors: every entry point returns an ile_status; nothing throws or aborts
+ * across the ABI.  Host-pointer entry points leave outputs untouched on
+ * error.  Device-pointer (_dev) entry points are asynchronous on the
+ * context's stream: invalid samples there produce NaN outputs and a sticky
+ * ILE_E_RANGE that ile_sync reports.  ile_last_error gives a message for the
+ * last failing call on that context (valid until the next call on it).
+ */
+#ifndef ILE_H
+#define ILE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ile_ctx ile_ctx;
+
+typedef enum {
+    ILE_OK = 0,
+    ILE_E_ARG = 1,         /* bad argument (null pointer, size, even n_t ...) */
+    ILE_E_STATE = 2,       /* call out of order (eval before set_data)         */
+    ILE_E_RANGE = 3,       /* sample or window outside its declared range     */
+    ILE_E_NUMERIC = 4,     /* non-finite Q/U/V, or U not Hermitian            */
+    ILE_E_DEVICE = 5,      /* HIP runtime error or no usable GPU              */
+    ILE_E_NOMEM = 6,       /* device allocation failed                        */
+    ILE_E_UNSUPPORTED = 7  /* valid request this build does not support       */
+} ile_status;
+
+typedef enum { ILE_FP64 = 0, ILE_FP32 = 1, ILE_BF16 = 2 } ile_precision;
+
+typedef struct {
+    double lat_deg, lon_deg, xarm_az_deg;
+} ile_detector;
+
+typedef struct {
+    int32_t l, m;
+} ile_mode;
+
+#define ILE_MAX_DET 4
+#define ILE_MAX_LM 32
+
+typedef struct {
+    int32_t n_det;            /* 1 .. ILE_MAX_DET                            */
+    int32_t n_lm;             /* 1 .. ILE_MAX_LM                             */
+    const ile_mode *modes;    /* [n_lm], copied                              */
+    double srate_hz;          /* sampling rate of Q                          */
+    int32_t n_t;              /* odd number of time bins, 1 .. 65535         */
+    double d_ref_mpc;         /* fiducial distance of Eq. (6)                */
+    double gmst_rad;          /* Greenwich sidereal angle (F time-independent) */
+    double earth_radius_m;    /* site radius                                 */
+    double t_ref_max_s;       /* |t_ref| bound checked at eval               */
+    ile_precision precision;  /* bulk contraction precision                  */
+    int32_t device;           /* HIP device ordinal                          */
+    void *stream;             /* hipStream_t to use, or NULL for a new one   */
+} ile_config;
+
+typedef struct {
+    double ln_L_marg;
+    double n_eff;
+    double n_eff_kish;
+    double sigma_ln_L;
+    double max_ln_L;          /* max over samples of lnLmargT                */
+    int64_t n_samples;
+} ile_result;
+
+/* Create a context (allocates nothing large).  Fails with ILE_E_ARG on a
+ * bad config, ILE_E_DEVICE when no GPU is usable.  *out is NULL on error. */
+ile_status ile_create(const ile_config *cfg, ile_ctx **out);
+
+/* Q: host double [n_det][n_lm][n_q][2] (re, im); U, V: host double
+ * [n_det][n_lm][n_lm][2]; dets: [n_det].  t0_s: time of Q[0] relative to
+ * the geocentre event time.  Copies the data to the device (converting Q to
+ * the context precision).  ILE_E_NUMERIC if anything is non-finite or U_k
+ * is not Hermitian to 1e-12 relative; ILE_E_RANGE if a sample with
+ * |t_ref| <= t_ref_max could read outside [0, n_q). */
+ile_status ile_set_data(ile_ctx *ctx, const double *Q, int64_t n_q,
+                        double t0_s, const double *U, const double *V,
+                        const ile_detector *dets);
+
+/* ln L_margT for N host samples into host lnL_margT[N].  ILE_E_RANGE if any
+ * sample has D <= 0, |cos iota| > 1, |t_ref| > t_ref_max or a non-finite
+ * value (message names the first).  N = 0 is a no-op. */
+ile_status ile_eval(ile_ctx *ctx, const double *samples, int64_t N,
+                    double *lnL_margT);
+
+/* Eval plus the importance-sampling reduction; ln_p and ln_q are host
+ * double [N] (log prior and log proposal density of each sample). */
+ile_status ile_integrate(ile_ctx *ctx, const double *samples,
+                         const double *ln_p, const double *ln_q, int64_t N,
+                         ile_result *out);
+
+/* Debug: the per-bin values L_alpha,j into host lnL[N][n_t]; same kernels
+ * as ile_eval. */
+ile_status ile_eval_series(ile_ctx *ctx, const double *samples, int64_t N,
+                           double *lnL);
+
+/* Device-pointer forms of the above (stream-ordered, asynchronous).
+ * ile_integrate_dev writes the 6 result fields as doubles to the device
+ * buffer result_dev[6] (n_samples as a double). */
+ile_status ile_eval_dev(ile_ctx *ctx, const double *samples_dev, int64_t N,
+                        double *lnL_margT_dev);
+ile_status ile_integrate_dev(ile_ctx *ctx, const double *samples_dev,
+                             const double *ln_p_dev, const double *ln_q_dev,
+                             int64_t N, double *result_dev);
+
+/* Device prior draw (Philox4x32-10, Salmon et al. SC'11): sample i of
+ * stream `seed` uses counters (i mod 2^32, i / 2^32, b, 0x494C4531), b =
+ * 0..3, key (seed mod 2^32, seed / 2^32); parameter p takes words 2p, 2p+1
+ * and forms the 53-bit uniform ((w0>>5) 2^26 + (w1>>6) + 1/2) 2^-53.
+ * Prior: ra, psi, phi uniform; sin(dec), cos(iota) uniform; p(D) ~ D^2 on
+ * [d_min, d_max]; t_ref uniform in [-t_ref_max, t_ref_max].  Writes device
+ * samples_dev[7][ld] (columns first .. first+N-1 of the stream go to
+ * columns 0 .. N-1) and ln_p_dev[N] (may be NULL). */
+ile_status ile_draw_prior_dev(ile_ctx *ctx, uint64_t seed, int64_t first,
+                              int64_t N, double d_min, double d_max,
+                              double *samples_dev, int64_t ld,
+                              double *ln_p_dev);
+
+/* Whole hot path on the device: draw N prior samples (as ile_draw_prior_dev
+ * with first = 0) in chunks of `chunk`, evaluate, reduce; only the result
+ * crosses to the host.  chunk <= 0 means one chunk. */
+ile_status ile_run_prior(ile_ctx *ctx, uint64_t seed, int64_t N,
+                         int64_t chunk, double d_min, double d_max,
+                         ile_result *out);
+
+/* Wait for the context's stream; report a sticky device-side error. */
+ile_status ile_sync(ile_ctx *ctx);
+
+typedef enum {
+    ILE_OPT_SORT = 0,  /* 1: order samples by window position before the
+                          contraction (default), 0: keep input order */
+} ile_option;
+ile_status ile_set_option(ile_ctx *ctx, ile_option opt, int64_t value);
+
+/* Average duration in ms of the last launch of the contraction kernel
+ * (HIP events around it on the context's stream); 0 if none. */
+double ile_last_kernel_ms(const ile_ctx *ctx);
+
+void ile_destroy(ile_ctx *ctx);
+const char *ile_last_error(const ile_ctx *ctx);
+const char *ile_status_string(ile_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ILE_H */

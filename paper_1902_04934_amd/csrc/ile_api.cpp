@@ -1,0 +1,648 @@
+// ile_api.cpp -- host side of libile: contexts, argument and range checks,
+// device buffers and the launch sequence of the hot path.  The C ABI is
+// declared (with its conventions) in include/ile.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ile.h"
+#include "ile_internal.h"
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kC = 299792458.0;
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct ile_ctx {
+    ile_config cfg{};
+    std::vector<ile_mode> modes;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    bool have_data = false;
+    ile_geom g{};
+    uint32_t n_buckets = 1;
+    int sort = 1;
+    ile_tune tune{16, 256};
+    DevBuf Q, U, V;
+    DevBuf smp, out, lnp, lnq, shifts, keys, perm, hist, scan_tmp, errflag,
+        red_tmp, parts, res, series;
+    std::vector<hipEvent_t> ev;   // pairs around contraction launches
+    int n_ev_used = 0;
+    double last_ms = 0.0;
+};
+
+namespace {
+
+ile_status fail(ile_ctx *c, ile_status s, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                       \
+    do {                                                                         \
+        hipError_t e_ = (expr);                                                  \
+        if (e_ != hipSuccess)                                                    \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? ILE_E_NOMEM : ILE_E_DEVICE, \
+                        "%s: %s", #expr, hipGetErrorString(e_));                 \
+    } while (0)
+
+ile_status ensure(ile_ctx *c, DevBuf &b, size_t bytes)
+{
+    if (b.bytes >= bytes && b.p) return ILE_OK;
+    if (b.p) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return fail(c, ILE_E_DEVICE, "sync: %s", hipGetErrorString(e));
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = std::max<size_t>(bytes, 256);
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return fail(c, ILE_E_NOMEM, "hipMalloc(%zu): %s", want, hipGetErrorString(e));
+    }
+    b.bytes = want;
+    return ILE_OK;
+}
+
+void release(DevBuf &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+double fact(int n)
+{
+    double f = 1.0;
+    for (int i = 2; i <= n; i++) f *= i;
+    return f;
+}
+
+// Wigner-d expansion of -2Y_lm (Goldberg et al. 1967) into the term table of
+// the kernels: sqrt((2l+1)/4pi) sum_k (-1)^k sqrt((l+m)!(l-m)!(l+2)!(l-2)!)
+// / ((l+m-k)!(l-2-k)! k! (k+2-m)!) cos^{2l+m-2-2k} sin^{2k+2-m}.
+bool build_ylm_table(ile_geom &g, const std::vector<ile_mode> &modes)
+{
+    int nt = 0;
+    for (size_t a = 0; a < modes.size(); a++) {
+        int l = modes[a].l, m = modes[a].m;
+        int kmin = std::max(0, m - 2), kmax = std::min(l + m, l - 2);
+        g.mode_m[a] = m;
+        g.mode_first[a] = nt;
+        g.mode_nterm[a] = 0;
+        double norm = std::sqrt((2.0 * l + 1.0) / (4.0 * kPi)) *
+                      std::sqrt(fact(l + m) * fact(l - m) * fact(l + 2) * fact(l - 2));
+        for (int k = kmin; k <= kmax; k++) {
+            if (nt >= ILE_MAX_TERMS) return false;
+            double a_k = norm / (fact(l + m - k) * fact(l - 2 - k) * fact(k) * fact(k + 2 - m));
+            g.term_a[nt] = (k % 2 == 0) ? a_k : -a_k;
+            g.term_pc[nt] = (signed char)(2 * l + m - 2 - 2 * k);
+            g.term_ps[nt] = (signed char)(2 * k + 2 - m);
+            nt++;
+            g.mode_nterm[a]++;
+        }
+    }
+    return true;
+}
+
+void detector_frame(const ile_detector &d, double R, double r[3], double D[9])
+{
+    const double lat = d.lat_deg * kPi / 180.0, lon = d.lon_deg * kPi / 180.0;
+    const double az = d.xarm_az_deg * kPi / 180.0;
+    const double e[3] = {-std::sin(lon), std::cos(lon), 0.0};
+    const double n[3] = {-std::sin(lat) * std::cos(lon), -std::sin(lat) * std::sin(lon),
+                         std::cos(lat)};
+    double x[3], y[3];
+    for (int i = 0; i < 3; i++) {
+        x[i] = std::cos(az) * e[i] + std::sin(az) * n[i];
+        y[i] = -std::sin(az) * e[i] + std::cos(az) * n[i];
+    }
+    r[0] = R * std::cos(lat) * std::cos(lon);
+    r[1] = R * std::cos(lat) * std::sin(lon);
+    r[2] = R * std::sin(lat);
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) D[3 * i + j] = 0.5 * (x[i] * x[j] - y[i] * y[j]);
+}
+
+bool sample_valid(const ile_ctx *c, const double *s, int64_t N, int64_t i)
+{
+    double th[7];
+    for (int p = 0; p < 7; p++) {
+        th[p] = s[p * N + i];
+        if (!std::isfinite(th[p])) return false;
+    }
+    return th[5] > 0.0 && th[4] >= -1.0 && th[4] <= 1.0 &&
+           std::fabs(th[6]) <= c->cfg.t_ref_max_s;
+}
+
+ile_status check_samples(ile_ctx *c, const double *s, int64_t N)
+{
+    for (int64_t i = 0; i < N; i++)
+        if (!sample_valid(c, s, N, i))
+            return fail(c, ILE_E_RANGE,
+                        "sample %lld out of range (need finite values, D > 0, "
+                        "|cos iota| <= 1, |t_ref| <= %g)",
+                        (long long)i, c->cfg.t_ref_max_s);
+    return ILE_OK;
+}
+
+ile_status ensure_work(ile_ctx *c, int64_t N)
+{
+    ile_status s;
+    const size_t n = (size_t)std::max<int64_t>(N, 1);
+    if ((s = ensure(c, c->shifts, n * c->g.n_det * sizeof(int32_t)))) return s;
+    if ((s = ensure(c, c->keys, n * sizeof(uint32_t)))) return s;
+    if ((s = ensure(c, c->perm, n * sizeof(int32_t)))) return s;
+    if ((s = ensure(c, c->hist, (size_t)c->n_buckets * sizeof(uint32_t)))) return s;
+    if ((s = ensure(c, c->scan_tmp, (size_t)ile_scan_tmp_words(c->n_buckets) * 4 + 16))) return s;
+    if ((s = ensure(c, c->errflag, 16))) return s;
+    if ((s = ensure(c, c->red_tmp, 4 * (size_t)ile_reduce_blocks() * sizeof(double)))) return s;
+    if ((s = ensure(c, c->res, 8 * sizeof(double)))) return s;
+    return ILE_OK;
+}
+
+hipEvent_t next_event(ile_ctx *c)
+{
+    if ((int)c->ev.size() <= c->n_ev_used) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev.push_back(e);
+    }
+    return c->ev[c->n_ev_used++];
+}
+
+// The hot path on device data: window starts and ordering, then the fused
+// contraction / time marginalization.  Stream-ordered.
+ile_status run_eval(ile_ctx *c, const double *smp, int64_t N, double *out,
+                    double *series)
+{
+    if (N <= 0) return ILE_OK;
+    if (N > 0x7fffffff) return fail(c, ILE_E_ARG, "N = %lld exceeds 2^31-1", (long long)N);
+    ile_status s = ensure_work(c, N);
+    if (s) return s;
+    hipStream_t st = c->stream;
+    uint32_t *hist = (uint32_t *)c->hist.p;
+    HIP_TRY(c, ile_launch_fill_u32(hist, 0u, c->n_buckets, st));
+    HIP_TRY(c, ile_launch_prep(c->g, smp, N, (int32_t *)c->shifts.p, (uint32_t *)c->keys.p,
+                               hist, c->n_buckets, (int32_t *)c->errflag.p, st));
+    if (c->sort) {
+        HIP_TRY(c, ile_launch_scan(hist, c->n_buckets, (uint32_t *)c->scan_tmp.p, st));
+        HIP_TRY(c, ile_launch_scatter((const uint32_t *)c->keys.p, N, hist,
+                                      (int32_t *)c->perm.p, st));
+    } else {
+        HIP_TRY(c, ile_launch_identity((int32_t *)c->perm.p, N, st));
+    }
+    hipEvent_t e0 = next_event(c), e1 = next_event(c);
+    if (!e0 || !e1) return fail(c, ILE_E_DEVICE, "hipEventCreate failed");
+    HIP_TRY(c, hipEventRecord(e0, st));
+    HIP_TRY(c, ile_launch_contract(c->g, c->cfg.precision, c->tune, smp, N,
+                                   (const int32_t *)c->perm.p,
+                                   (const int32_t *)c->shifts.p, c->Q.p,
+                                   (const double *)c->U.p, (const double *)c->V.p,
+                                   out, series, st));
+    HIP_TRY(c, hipEventRecord(e1, st));
+    return ILE_OK;
+}
+
+void begin_call(ile_ctx *c)
+{
+    c->err.clear();
+    c->n_ev_used = 0;
+}
+
+// Wait for the stream, collect kernel times and the sticky error flag.
+ile_status finish_call(ile_ctx *c)
+{
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    int n = 0;
+    for (int i = 0; i + 1 < c->n_ev_used; i += 2) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]) == hipSuccess) {
+            tot += ms;
+            n++;
+        }
+    }
+    if (n) c->last_ms = tot / n;
+    int32_t flag = 0;
+    if (c->errflag.p) {
+        HIP_TRY(c, hipMemcpy(&flag, c->errflag.p, sizeof(flag), hipMemcpyDeviceToHost));
+        if (flag) {
+            HIP_TRY(c, hipMemset(c->errflag.p, 0, sizeof(int32_t)));
+            return fail(c, ILE_E_RANGE,
+                        "a device-side sample was out of range (its output is NaN)");
+        }
+    }
+    return ILE_OK;
+}
+
+ile_status check_ready(ile_ctx *c)
+{
+    if (!c) return ILE_E_ARG;
+    if (!c->have_data) return fail(c, ILE_E_STATE, "ile_set_data has not been called");
+    HIP_TRY(c, hipSetDevice(c->cfg.device));
+    begin_call(c);
+    return ILE_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char *ile_status_string(ile_status s)
+{
+    switch (s) {
+    case ILE_OK: return "ok";
+    case ILE_E_ARG: return "invalid argument";
+    case ILE_E_STATE: return "invalid state";
+    case ILE_E_RANGE: return "out of range";
+    case ILE_E_NUMERIC: return "non-finite or inconsistent data";
+    case ILE_E_DEVICE: return "device error";
+    case ILE_E_NOMEM: return "out of device memory";
+    case ILE_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *ile_last_error(const ile_ctx *c)
+{
+    return c ? c->err.c_str() : "null context";
+}
+
+ile_status ile_create(const ile_config *cfg, ile_ctx **out)
+{
+    if (!out) return ILE_E_ARG;
+    *out = nullptr;
+    if (!cfg) return ILE_E_ARG;
+    if (cfg->n_det < 1 || cfg->n_det > ILE_MAX_DET || cfg->n_lm < 1 ||
+        cfg->n_lm > ILE_MAX_LM || !cfg->modes || !(cfg->srate_hz > 0) ||
+        cfg->n_t < 1 || cfg->n_t > 65535 || cfg->n_t % 2 == 0 ||
+        !(cfg->d_ref_mpc > 0) || !std::isfinite(cfg->gmst_rad) ||
+        !(cfg->earth_radius_m > 0) || !(cfg->t_ref_max_s >= 0) ||
+        (cfg->precision != ILE_FP64 && cfg->precision != ILE_FP32 &&
+         cfg->precision != ILE_BF16))
+        return ILE_E_ARG;
+    for (int a = 0; a < cfg->n_lm; a++) {
+        int l = cfg->modes[a].l, m = cfg->modes[a].m;
+        if (l < 2 || l > ILE_LMAX || m < -l || m > l) return ILE_E_ARG;
+    }
+    if (cfg->precision == ILE_BF16) return ILE_E_UNSUPPORTED;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return ILE_E_DEVICE;
+    if (cfg->device < 0 || cfg->device >= ndev) return ILE_E_ARG;
+    ile_ctx *c = new (std::nothrow) ile_ctx();
+    if (!c) return ILE_E_NOMEM;
+    c->cfg = *cfg;
+    c->modes.assign(cfg->modes, cfg->modes + cfg->n_lm);
+    c->cfg.modes = c->modes.data();
+    if (hipSetDevice(cfg->device) != hipSuccess) {
+        delete c;
+        return ILE_E_DEVICE;
+    }
+    if (cfg->stream) {
+        c->stream = (hipStream_t)cfg->stream;
+    } else {
+        if (hipStreamCreate(&c->stream) != hipSuccess) {
+            delete c;
+            return ILE_E_DEVICE;
+        }
+        c->own_stream = true;
+    }
+    ile_geom &g = c->g;
+    g.n_det = cfg->n_det;
+    g.n_lm = cfg->n_lm;
+    g.n_t = cfg->n_t;
+    g.half = (cfg->n_t - 1) / 2;
+    g.dt = 1.0 / cfg->srate_hz;
+    g.d_ref = cfg->d_ref_mpc;
+    g.gmst = cfg->gmst_rad;
+    g.t_ref_max = cfg->t_ref_max_s;
+    if (!build_ylm_table(g, c->modes)) {
+        ile_destroy(c);
+        return ILE_E_UNSUPPORTED;
+    }
+    *out = c;
+    return ILE_OK;
+}
+
+ile_status ile_set_data(ile_ctx *c, const double *Q, int64_t n_q, double t0_s,
+                        const double *U, const double *V, const ile_detector *dets)
+{
+    if (!c) return ILE_E_ARG;
+    begin_call(c);
+    if (!Q || !U || !V || !dets) return fail(c, ILE_E_ARG, "null pointer");
+    const int nd = c->cfg.n_det, nl = c->cfg.n_lm;
+    if (n_q < c->cfg.n_t || n_q > (int64_t)0x7fffffff / 2)
+        return fail(c, ILE_E_ARG, "n_q = %lld invalid", (long long)n_q);
+    if (!std::isfinite(t0_s)) return fail(c, ILE_E_ARG, "t0 not finite");
+    const size_t nQ = (size_t)nd * nl * n_q, nUV = (size_t)nd * nl * nl;
+    for (size_t i = 0; i < 2 * nQ; i++)
+        if (!std::isfinite(Q[i])) return fail(c, ILE_E_NUMERIC, "Q[%zu] not finite", i / 2);
+    for (size_t i = 0; i < 2 * nUV; i++)
+        if (!std::isfinite(U[i]) || !std::isfinite(V[i]))
+            return fail(c, ILE_E_NUMERIC, "U or V entry %zu not finite", i / 2);
+    for (int k = 0; k < nd; k++) {
+        double mx = 0.0;
+        for (int i = 0; i < nl * nl; i++) {
+            const double *u = U + 2 * ((size_t)k * nl * nl + i);
+            mx = std::max(mx, std::hypot(u[0], u[1]));
+        }
+        for (int a = 0; a < nl; a++)
+            for (int b = 0; b < nl; b++) {
+                const double *uab = U + 2 * (((size_t)k * nl + a) * nl + b);
+                const double *uba = U + 2 * (((size_t)k * nl + b) * nl + a);
+                if (std::fabs(uab[0] - uba[0]) > 1e-12 * mx ||
+                    std::fabs(uab[1] + uba[1]) > 1e-12 * mx)
+                    return fail(c, ILE_E_NUMERIC, "U[%d] not Hermitian at (%d,%d)", k, a, b);
+            }
+    }
+    ile_geom &g = c->g;
+    for (int k = 0; k < nd; k++) {
+        const ile_detector &d = dets[k];
+        if (!std::isfinite(d.lat_deg) || !std::isfinite(d.lon_deg) ||
+            !std::isfinite(d.xarm_az_deg) || std::fabs(d.lat_deg) > 90.0)
+            return fail(c, ILE_E_ARG, "detector %d invalid", k);
+        detector_frame(d, c->cfg.earth_radius_m, g.r[k], g.D[k]);
+    }
+    g.n_q = (int)n_q;
+    g.s_max = (int)(n_q - c->cfg.n_t);
+    g.t0 = t0_s;
+    // every window reachable with |t_ref| <= t_ref_max must lie in Q
+    const double reach = c->cfg.t_ref_max_s + c->cfg.earth_radius_m / kC;
+    const double xlo = (-reach - t0_s) / g.dt, xhi = (reach - t0_s) / g.dt;
+    const int64_t slo = (int64_t)std::floor(xlo + 0.5) - g.half - 1;
+    const int64_t shi = (int64_t)std::floor(xhi + 0.5) - g.half + 1;
+    if (slo < 0 || shi > g.s_max)
+        return fail(c, ILE_E_RANGE,
+                    "Q too short: windows reach indices [%lld, %lld] but Q has %lld",
+                    (long long)slo, (long long)(shi + c->cfg.n_t - 1), (long long)n_q);
+    // ordering key: cells of 2^shift samples over [slo, shi], <= 21 bits
+    const int64_t width = shi - slo + 1;
+    g.key_dims = std::min(nd, 3);
+    int shift = 4, bits = 0;
+    for (;;) {
+        int64_t cells = (width + (1 << shift) - 1) >> shift;
+        bits = 0;
+        while ((1ll << bits) < cells) bits++;
+        if (bits * g.key_dims <= 21) break;
+        shift++;
+    }
+    g.key_shift = shift;
+    g.key_bits = bits;
+    for (int d = 0; d < 3; d++) g.key_lo[d] = (int)slo;
+    c->n_buckets = (1u << (bits * g.key_dims)) + 1u;
+
+    ile_status s;
+    HIP_TRY(c, hipSetDevice(c->cfg.device));
+    int lds_max = 0;
+    HIP_TRY(c, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                     c->cfg.device));
+    const size_t lds_need = ile_contract_lds_bytes(g, c->cfg.precision, c->tune);
+    if (lds_need > (size_t)lds_max)
+        return fail(c, ILE_E_UNSUPPORTED,
+                    "contraction needs %zu bytes of LDS per workgroup, device has %d",
+                    lds_need, lds_max);
+    const size_t qe = c->cfg.precision == ILE_FP64 ? 16 : 8;
+    if ((s = ensure(c, c->Q, nQ * qe))) return s;
+    if ((s = ensure(c, c->U, nUV * 16))) return s;
+    if ((s = ensure(c, c->V, nUV * 16))) return s;
+    if (c->cfg.precision == ILE_FP64) {
+        HIP_TRY(c, hipMemcpy(c->Q.p, Q, nQ * 16, hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> f(2 * nQ);
+        for (size_t i = 0; i < 2 * nQ; i++) f[i] = (float)Q[i];
+        HIP_TRY(c, hipMemcpy(c->Q.p, f.data(), nQ * 8, hipMemcpyHostToDevice));
+    }
+    HIP_TRY(c, hipMemcpy(c->U.p, U, nUV * 16, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->V.p, V, nUV * 16, hipMemcpyHostToDevice));
+    if ((s = ensure_work(c, 1))) return s;
+    HIP_TRY(c, hipMemset(c->errflag.p, 0, 16));
+    c->have_data = true;
+    return ILE_OK;
+}
+
+ile_status ile_eval_dev(ile_ctx *c, const double *smp, int64_t N, double *out)
+{
+    ile_status s = check_ready(c);
+    if (s) return s;
+    if (N < 0 || (N > 0 && (!smp || !out))) return fail(c, ILE_E_ARG, "bad N or pointer");
+    return run_eval(c, smp, N, out, nullptr);
+}
+
+static ile_status eval_host(ile_ctx *c, const double *samples, int64_t N,
+                            double *out, bool series)
+{
+    ile_status s = check_ready(c);
+    if (s) return s;
+    if (N < 0 || (N > 0 && (!samples || !out))) return fail(c, ILE_E_ARG, "bad N or pointer");
+    if (N == 0) return ILE_OK;
+    if ((s = check_samples(c, samples, N))) return s;
+    if ((s = ensure(c, c->smp, (size_t)N * 7 * sizeof(double)))) return s;
+    if ((s = ensure(c, c->out, (size_t)N * sizeof(double)))) return s;
+    size_t ser_bytes = series ? (size_t)N * c->cfg.n_t * sizeof(double) : 0;
+    if (series && (s = ensure(c, c->series, ser_bytes))) return s;
+    HIP_TRY(c, hipMemcpyAsync(c->smp.p, samples, (size_t)N * 7 * sizeof(double),
+                              hipMemcpyHostToDevice, c->stream));
+    if ((s = run_eval(c, (const double *)c->smp.p, N, (double *)c->out.p,
+                      series ? (double *)c->series.p : nullptr)))
+        return s;
+    if ((s = finish_call(c))) return s;
+    if (series)
+        HIP_TRY(c, hipMemcpy(out, c->series.p, ser_bytes, hipMemcpyDeviceToHost));
+    else
+        HIP_TRY(c, hipMemcpy(out, c->out.p, (size_t)N * sizeof(double),
+                             hipMemcpyDeviceToHost));
+    return ILE_OK;
+}
+
+ile_status ile_eval(ile_ctx *c, const double *samples, int64_t N, double *out)
+{
+    return eval_host(c, samples, N, out, false);
+}
+
+ile_status ile_eval_series(ile_ctx *c, const double *samples, int64_t N, double *out)
+{
+    return eval_host(c, samples, N, out, true);
+}
+
+static ile_status integrate_dev_impl(ile_ctx *c, const double *smp, const double *lp,
+                                     const double *lq, int64_t N, double *res)
+{
+    ile_status s;
+    if ((s = ensure(c, c->out, (size_t)std::max<int64_t>(N, 1) * sizeof(double)))) return s;
+    if ((s = ensure(c, c->parts, 8 * sizeof(double)))) return s;
+    if ((s = run_eval(c, smp, N, (double *)c->out.p, nullptr))) return s;
+    HIP_TRY(c, ile_launch_reduce((const double *)c->out.p, lp, lq, N,
+                                 (double *)c->red_tmp.p, (double *)c->parts.p, c->stream));
+    HIP_TRY(c, ile_launch_finish((const double *)c->parts.p, 1, res, c->stream));
+    return ILE_OK;
+}
+
+ile_status ile_integrate_dev(ile_ctx *c, const double *smp, const double *lp,
+                             const double *lq, int64_t N, double *res)
+{
+    ile_status s = check_ready(c);
+    if (s) return s;
+    if (N < 0 || !res || (N > 0 && !smp)) return fail(c, ILE_E_ARG, "bad N or pointer");
+    if ((s = ensure_work(c, N))) return s;
+    return integrate_dev_impl(c, smp, lp, lq, N, res);
+}
+
+static void copy_result(const double *r, ile_result *out)
+{
+    out->ln_L_marg = r[0];
+    out->n_eff = r[1];
+    out->n_eff_kish = r[2];
+    out->sigma_ln_L = r[3];
+    out->max_ln_L = r[4];
+    out->n_samples = (int64_t)r[5];
+}
+
+ile_status ile_integrate(ile_ctx *c, const double *samples, const double *ln_p,
+                         const double *ln_q, int64_t N, ile_result *out)
+{
+    ile_status s = check_ready(c);
+    if (s) return s;
+    if (N < 0 || !out || (N > 0 && (!samples || !ln_p || !ln_q)))
+        return fail(c, ILE_E_ARG, "bad N or pointer");
+    if ((s = check_samples(c, samples, N))) return s;
+    for (int64_t i = 0; i < N; i++)
+        if (std::isnan(ln_p[i]) || std::isnan(ln_q[i]) || ln_q[i] == -INFINITY ||
+            ln_p[i] == INFINITY)
+            return fail(c, ILE_E_RANGE, "ln_p/ln_q of sample %lld invalid", (long long)i);
+    const size_t n = (size_t)std::max<int64_t>(N, 1);
+    if ((s = ensure(c, c->smp, n * 7 * sizeof(double)))) return s;
+    if ((s = ensure(c, c->lnp, n * sizeof(double)))) return s;
+    if ((s = ensure(c, c->lnq, n * sizeof(double)))) return s;
+    if ((s = ensure_work(c, N))) return s;
+    if (N > 0) {
+        HIP_TRY(c, hipMemcpyAsync(c->smp.p, samples, (size_t)N * 7 * sizeof(double),
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->lnp.p, ln_p, (size_t)N * sizeof(double),
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->lnq.p, ln_q, (size_t)N * sizeof(double),
+                                  hipMemcpyHostToDevice, c->stream));
+    }
+    if ((s = integrate_dev_impl(c, (const double *)c->smp.p, (const double *)c->lnp.p,
+                                (const double *)c->lnq.p, N, (double *)c->res.p)))
+        return s;
+    if ((s = finish_call(c))) return s;
+    double r[6];
+    HIP_TRY(c, hipMemcpy(r, c->res.p, sizeof(r), hipMemcpyDeviceToHost));
+    copy_result(r, out);
+    return ILE_OK;
+}
+
+ile_status ile_draw_prior_dev(ile_ctx *c, uint64_t seed, int64_t first, int64_t N,
+                              double d_min, double d_max, double *smp, int64_t ld,
+                              double *ln_p)
+{
+    if (!c) return ILE_E_ARG;
+    begin_call(c);
+    if (N < 0 || first < 0 || (N > 0 && !smp) || ld < N || !(d_min > 0) ||
+        !(d_max > d_min) || !std::isfinite(d_max))
+        return fail(c, ILE_E_ARG, "bad prior-draw arguments");
+    HIP_TRY(c, hipSetDevice(c->cfg.device));
+    HIP_TRY(c, ile_launch_prior(seed, first, N, d_min, d_max, c->cfg.t_ref_max_s, smp,
+                                ld, ln_p, c->stream));
+    return ILE_OK;
+}
+
+ile_status ile_run_prior(ile_ctx *c, uint64_t seed, int64_t N, int64_t chunk,
+                         double d_min, double d_max, ile_result *out)
+{
+    ile_status s = check_ready(c);
+    if (s) return s;
+    if (N <= 0 || !out || !(d_min > 0) || !(d_max > d_min) || !std::isfinite(d_max))
+        return fail(c, ILE_E_ARG, "bad run arguments");
+    if (chunk <= 0 || chunk > N) chunk = N;
+    const int64_t n_chunks = (N + chunk - 1) / chunk;
+    if (n_chunks > 1 << 20) return fail(c, ILE_E_ARG, "too many chunks");
+    if ((s = ensure(c, c->smp, (size_t)chunk * 7 * sizeof(double)))) return s;
+    if ((s = ensure(c, c->out, (size_t)chunk * sizeof(double)))) return s;
+    if ((s = ensure(c, c->parts, (size_t)n_chunks * 5 * sizeof(double)))) return s;
+    if ((s = ensure_work(c, chunk))) return s;
+    // the proposal is the prior: ln p - ln q = 0, so no density is needed
+    for (int64_t ci = 0; ci < n_chunks; ci++) {
+        const int64_t first = ci * chunk, n = std::min(chunk, N - first);
+        HIP_TRY(c, ile_launch_prior(seed, first, n, d_min, d_max, c->cfg.t_ref_max_s,
+                                    (double *)c->smp.p, n, nullptr, c->stream));
+        if ((s = run_eval(c, (const double *)c->smp.p, n, (double *)c->out.p, nullptr)))
+            return s;
+        HIP_TRY(c, ile_launch_reduce((const double *)c->out.p, nullptr, nullptr, n,
+                                     (double *)c->red_tmp.p,
+                                     (double *)c->parts.p + 5 * ci, c->stream));
+    }
+    HIP_TRY(c, ile_launch_finish((const double *)c->parts.p, (int)n_chunks,
+                                 (double *)c->res.p, c->stream));
+    if ((s = finish_call(c))) return s;
+    double r[6];
+    HIP_TRY(c, hipMemcpy(r, c->res.p, sizeof(r), hipMemcpyDeviceToHost));
+    copy_result(r, out);
+    return ILE_OK;
+}
+
+ile_status ile_sync(ile_ctx *c)
+{
+    if (!c) return ILE_E_ARG;
+    ile_status s = finish_call(c);
+    c->n_ev_used = 0;
+    return s;
+}
+
+ile_status ile_set_option(ile_ctx *c, ile_option opt, int64_t v)
+{
+    if (!c) return ILE_E_ARG;
+    begin_call(c);
+    switch (opt) {
+    case ILE_OPT_SORT:
+        if (v != 0 && v != 1) return fail(c, ILE_E_ARG, "sort must be 0 or 1");
+        c->sort = (int)v;
+        return ILE_OK;
+    }
+    return fail(c, ILE_E_ARG, "unknown option %d", (int)opt);
+}
+
+double ile_last_kernel_ms(const ile_ctx *c) { return c ? c->last_ms : 0.0; }
+
+void ile_destroy(ile_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->cfg.device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (DevBuf *b : {&c->Q, &c->U, &c->V, &c->smp, &c->out, &c->lnp, &c->lnq,
+                      &c->shifts, &c->keys, &c->perm, &c->hist, &c->scan_tmp,
+                      &c->errflag, &c->red_tmp, &c->parts, &c->res, &c->series})
+        release(*b);
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+}  // extern "C"

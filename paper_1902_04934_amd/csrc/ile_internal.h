@@ -1,0 +1,75 @@
+// ile_internal.h -- device-side parameter blocks and launch wrappers shared
+// by the HIP kernels (ile_kernels.hip) and the C-ABI host code (ile_api.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ile.h"
+
+#define ILE_NPAR 7
+#define ILE_MAX_TERMS 160   // Wigner-d terms over all modes (l <= 6, <= 32 modes)
+#define ILE_LMAX 6
+
+// Everything the kernels need about one intrinsic point and the detector
+// network, passed by value as a kernel argument.
+struct ile_geom {
+    int n_det, n_lm, n_t, half;      // half = (n_t - 1) / 2
+    int n_q;                         // length of each Q series
+    int s_max;                       // largest valid window start, n_q - n_t
+    double t0;                       // time of Q[0]
+    double dt;                       // 1 / srate
+    double d_ref, gmst, t_ref_max;
+    double r[ILE_MAX_DET][3];        // site vectors [m]
+    double D[ILE_MAX_DET][9];        // detector tensors
+    // ordering key: Morton code of the window starts of up to 3 detectors
+    int key_lo[3];
+    int key_shift;                   // log2 of the cell width in samples
+    int key_bits;                    // bits per axis
+    int key_dims;                    // detectors used in the key
+    // -2Y_lm as sums of a_t cos(i/2)^pc_t sin(i/2)^ps_t, times e^{i m phi}
+    int mode_m[ILE_MAX_LM];
+    int mode_first[ILE_MAX_LM];
+    int mode_nterm[ILE_MAX_LM];
+    double term_a[ILE_MAX_TERMS];
+    signed char term_pc[ILE_MAX_TERMS];
+    signed char term_ps[ILE_MAX_TERMS];
+};
+
+// Tuning of the contraction kernel.
+struct ile_tune {
+    int tile_samples;   // samples per workgroup tile
+    int threads;        // threads per workgroup (= positions per G block)
+};
+
+// Launch wrappers (ile_kernels.hip).  All are asynchronous on `st`.
+hipError_t ile_launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
+hipError_t ile_launch_prep(const ile_geom &g, const double *smp, int64_t N,
+                           int32_t *shifts, uint32_t *keys, uint32_t *hist,
+                           uint32_t n_buckets, int32_t *err, hipStream_t st);
+hipError_t ile_launch_scan(uint32_t *v, int64_t n, uint32_t *tmp, hipStream_t st);
+int64_t ile_scan_tmp_words(int64_t n);
+hipError_t ile_launch_scatter(const uint32_t *keys, int64_t N, uint32_t *offs,
+                              int32_t *perm, hipStream_t st);
+hipError_t ile_launch_identity(int32_t *perm, int64_t N, hipStream_t st);
+hipError_t ile_launch_contract(const ile_geom &g, ile_precision prec,
+                               const ile_tune &tu, const double *smp, int64_t N,
+                               const int32_t *perm, const int32_t *shifts,
+                               const void *Q, const double *U, const double *V,
+                               double *out, double *series, hipStream_t st);
+size_t ile_contract_lds_bytes(const ile_geom &g, ile_precision prec,
+                              const ile_tune &tu);
+hipError_t ile_launch_prior(uint64_t seed, int64_t first, int64_t N,
+                            double d_min, double d_max, double t_ref_max,
+                            double *smp, int64_t ld, double *ln_p, hipStream_t st);
+// Importance-sampling reduction of N values into a 5-double partial
+// {M, S1, S2, n, maxL} with S1 = sum e^{lnw-M}, S2 = sum e^{2(lnw-M)}.
+int ile_reduce_blocks();
+hipError_t ile_launch_reduce(const double *lnL, const double *ln_p,
+                             const double *ln_q, int64_t N, double *tmp,
+                             double *partial, hipStream_t st);
+// Merge n_part partials (fixed order) and finish into result[6].
+hipError_t ile_launch_finish(const double *partials, int n_part, double *result,
+                             hipStream_t st);
+hipError_t ile_launch_to_bf16_split(const double *Q, int64_t n, void *dst,
+                                    hipStream_t st);

@@ -1,0 +1,849 @@
+// ile_kernels.hip -- gfx950 kernels of the ILE likelihood hot path.
+//
+// Paper: arXiv:1902.04934.  Sec. II.A defines the per-sample likelihood
+// (Eq. (7), matrix form Eq. (10)) and its time marginalization (Eq. (9));
+// Sec. II.B describes the GPU step whose most costly part is the contraction
+// of Q over detector-dependent time windows; Sec. II.C the Monte Carlo
+// accuracy measure.
+//
+// Pipeline for a block of N samples:
+//   k_prep     window starts s_k per (sample, detector), validity, ordering key
+//   k_scan*    counting sort of the samples by key (cells of nearby windows)
+//   k_contract per tile of TS samples: F, Y, coefficients and quadratic term
+//              in LDS; per time chunk and detector the partial
+//              G[alpha][p] = sum_lm Re(conj(c) Q[p]) over the union of the
+//              tile's windows (each Q value loaded once feeds TS samples),
+//              realigned through LDS to L[alpha][j]; online FP64
+//              log-sum-exp over bins; deterministic tree at the end.
+//   k_red*     FP64 importance-sampling partials {M, S1, S2, n, maxL}.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "ile_internal.h"
+
+namespace {
+
+constexpr double kC = 299792458.0;
+constexpr double kTwoPi = 6.283185307179586476925;
+constexpr double kPi = 3.141592653589793238463;
+
+template <typename T> struct vec2;
+template <> struct vec2<double> { using type = double2; };
+template <> struct vec2<float> { using type = float2; };
+
+// ---------------------------------------------------------------- geometry
+// Arrival delay at site k relative to the geocentre, tau = -n.r/c, with n
+// the unit vector towards the source (Sec. II.A, detector response).  Same
+// operation order as written, no contraction, so that the window rounding
+// agrees with an independent evaluation except within 1e-9 of a tie.
+__device__ inline double delay_dev(const ile_geom &g, int k, double ra,
+                                   double dec)
+{
+#pragma clang fp contract(off)
+    double h = ra - g.gmst;
+    double n0 = cos(dec) * cos(h);
+    double n1 = cos(dec) * sin(h);
+    double n2 = sin(dec);
+    double nr = n0 * g.r[k][0] + n1 * g.r[k][1] + n2 * g.r[k][2];
+    return -nr / kC;
+}
+
+// Antenna patterns from the detector tensor: polarization basis X, Y of a
+// source at hour angle h = ra - gmst, declination dec, rotated by psi;
+// F+ = X.D.X - Y.D.Y, Fx = X.D.Y + Y.D.X.
+__device__ inline void antenna_dev(const ile_geom &g, int k, double ra,
+                                   double dec, double psi, double &fp,
+                                   double &fx)
+{
+    double sh, ch, sd, cd, sp, cp;
+    sincos(ra - g.gmst, &sh, &ch);
+    sincos(dec, &sd, &cd);
+    sincos(psi, &sp, &cp);
+    const double eE[3] = {-sh, ch, 0.0};
+    const double eN[3] = {-sd * ch, -sd * sh, cd};
+    double X[3], Y[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        X[i] = -cp * eE[i] + sp * eN[i];
+        Y[i] = sp * eE[i] + cp * eN[i];
+    }
+    double DX[3], DY[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        DX[i] = g.D[k][3 * i] * X[0] + g.D[k][3 * i + 1] * X[1] + g.D[k][3 * i + 2] * X[2];
+        DY[i] = g.D[k][3 * i] * Y[0] + g.D[k][3 * i + 1] * Y[1] + g.D[k][3 * i + 2] * Y[2];
+    }
+    fp = (X[0] * DX[0] + X[1] * DX[1] + X[2] * DX[2]) -
+         (Y[0] * DY[0] + Y[1] * DY[1] + Y[2] * DY[2]);
+    fx = (X[0] * DY[0] + X[1] * DY[1] + X[2] * DY[2]) +
+         (Y[0] * DX[0] + Y[1] * DX[1] + Y[2] * DX[2]);
+}
+
+__device__ inline double ipow(double x, int n)
+{
+    double r = 1.0;
+    for (int i = 0; i < n; i++) r *= x;
+    return r;
+}
+
+// -2Y_lm(iota, phi) of mode a from the per-mode Wigner-d term table.
+__device__ inline double2 sylm_dev(const ile_geom &g, int a, double cos_iota,
+                                   double phi)
+{
+    double c = sqrt(0.5 * (1.0 + cos_iota));   // cos(iota/2)
+    double s = sqrt(0.5 * (1.0 - cos_iota));   // sin(iota/2)
+    double sum = 0.0;
+    const int t0 = g.mode_first[a], nt = g.mode_nterm[a];
+    for (int t = t0; t < t0 + nt; t++)
+        sum += g.term_a[t] * ipow(c, g.term_pc[t]) * ipow(s, g.term_ps[t]);
+    double sm, cm;
+    sincos((double)g.mode_m[a] * phi, &sm, &cm);
+    return make_double2(sum * cm, sum * sm);
+}
+
+__host__ __device__ inline size_t prologue_scratch_bytes(int ts, int nd, int nl)
+{
+    // s_th[7][ts], s_Y[ts][nl], s_F[ts][nd] (complex), s_qp[ts][nd*nl]
+    return sizeof(double) * (size_t)ts * (7 + 2 * nl + 2 * nd + nd * nl);
+}
+
+__device__ inline bool sample_ok(const ile_geom &g, const double th[7])
+{
+    bool fin = true;
+#pragma unroll
+    for (int p = 0; p < 7; p++) fin = fin && isfinite(th[p]);
+    return fin && th[5] > 0.0 && th[4] >= -1.0 && th[4] <= 1.0 &&
+           fabs(th[6]) <= g.t_ref_max;
+}
+
+// ------------------------------------------------------------------ prep
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_prep(ile_geom g,
+                                              const double *__restrict__ smp,
+                                              int64_t N, int32_t *shifts,
+                                              uint32_t *keys, uint32_t *hist,
+                                              uint32_t n_buckets, int32_t *err)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double th[7];
+#pragma unroll
+    for (int p = 0; p < 7; p++) th[p] = smp[p * N + i];
+    bool ok = sample_ok(g, th);
+    int s[ILE_MAX_DET];
+    for (int k = 0; k < g.n_det; k++) {
+        s[k] = 0;
+        if (ok) {
+            double tau = delay_dev(g, k, th[0], th[1]);
+            double x;
+            {
+#pragma clang fp contract(off)
+                x = (th[6] + tau - g.t0) / g.dt;
+            }
+            double xs = floor(x + 0.5) - (double)g.half;
+            if (xs >= 0.0 && xs <= (double)g.s_max)
+                s[k] = (int)xs;
+            else
+                ok = false;
+        }
+    }
+    uint32_t key = n_buckets - 1;   // invalid samples sort last
+    if (ok) {
+        key = 0;
+        for (int d = 0; d < g.key_dims; d++) {
+            int c = (s[d] - g.key_lo[d]) >> g.key_shift;
+            c = c < 0 ? 0 : c;
+            c = c > (1 << g.key_bits) - 1 ? (1 << g.key_bits) - 1 : c;
+            for (int b = 0; b < g.key_bits; b++)
+                key |= (uint32_t)((c >> b) & 1) << (b * g.key_dims + d);
+        }
+    } else {
+        atomicOr(err, 1);
+    }
+    for (int k = 0; k < g.n_det; k++) shifts[(int64_t)k * N + i] = ok ? s[k] : -1;
+    keys[i] = key;
+    atomicAdd(&hist[key], 1u);
+}
+
+// Exclusive scan of n uint32 in place: blocks of 1024 threads x 4 values.
+constexpr int kScanT = 1024;
+constexpr int kScanPer = 4;
+constexpr int kScanBlock = kScanT * kScanPer;
+
+__device__ inline uint32_t block_exscan(uint32_t v, uint32_t *sh, uint32_t &total)
+{
+    // Hillis-Steele over 1024 values in LDS
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanT; off <<= 1) {
+        uint32_t a = t >= off ? sh[t - off] : 0u;
+        __syncthreads();
+        sh[t] += a;
+        __syncthreads();
+    }
+    uint32_t incl = sh[t];
+    total = sh[kScanT - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kScanT) void k_scan_local(uint32_t *v, int64_t n,
+                                                       uint32_t *bsum)
+{
+    __shared__ uint32_t sh[kScanT];
+    int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanPer;
+    uint32_t x[kScanPer], run = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; j++) {
+        x[j] = base + j < n ? v[base + j] : 0u;
+        run += x[j];
+    }
+    uint32_t total;
+    uint32_t ex = block_exscan(run, sh, total);
+#pragma unroll
+    for (int j = 0; j < kScanPer; j++) {
+        if (base + j < n) v[base + j] = ex;
+        ex += x[j];
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanT) void k_scan_top(uint32_t *bsum, int nb)
+{
+    // nb <= kScanBlock: one block, 4 values per thread
+    __shared__ uint32_t sh[kScanT];
+    int base = threadIdx.x * kScanPer;
+    uint32_t x[kScanPer], run = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; j++) {
+        x[j] = base + j < nb ? bsum[base + j] : 0u;
+        run += x[j];
+    }
+    uint32_t total;
+    uint32_t ex = block_exscan(run, sh, total);
+#pragma unroll
+    for (int j = 0; j < kScanPer; j++) {
+        if (base + j < nb) bsum[base + j] = ex;
+        ex += x[j];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(uint32_t *v, int64_t n,
+                                                  const uint32_t *bsum)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] += bsum[i / kScanBlock];
+}
+
+__global__ __launch_bounds__(256) void k_scatter(const uint32_t *__restrict__ keys,
+                                                 int64_t N, uint32_t *offs,
+                                                 int32_t *perm)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    uint32_t pos = atomicAdd(&offs[keys[i]], 1u);
+    perm[pos] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_identity(int32_t *perm, int64_t N)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) perm[i] = (int32_t)i;
+}
+
+// ------------------------------------------------------------ contraction
+// One workgroup = one tile of TS samples (in sorted order), NT threads.
+// LDS: Gs[TS][NT] partial sums (also the prologue scratch), coefficient
+// table coefT[n_det][n_lm][TS] (dynamic), small per-sample arrays.
+template <typename TQ, int TS, int NT, bool DUMP>
+__global__ __launch_bounds__(NT) void k_contract(
+    ile_geom g, const double *__restrict__ smp, int64_t N,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ shifts,
+    const typename vec2<TQ>::type *__restrict__ Q,
+    const double2 *__restrict__ U, const double2 *__restrict__ V,
+    double *__restrict__ out, double *__restrict__ series)
+{
+    using T2 = typename vec2<TQ>::type;
+    constexpr int NW = NT / 64;
+    __shared__ __align__(16) TQ Gs[TS * NT];
+    __shared__ double s_q[TS];
+    __shared__ int s_idx[TS];      // sample index, -1 if the slot is empty
+    __shared__ int s_ok[TS];
+    __shared__ int s_d[ILE_MAX_DET][TS];
+    __shared__ int s_smin[ILE_MAX_DET], s_spread[ILE_MAX_DET];
+    __shared__ double s_red[NW][TS];
+    __shared__ double s_M[TS];
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
+    T2 *coefT = reinterpret_cast<T2 *>(dyn_lds);
+
+    const int tid = threadIdx.x;
+    const int nd = g.n_det, nl = g.n_lm, nq = g.n_q;
+    const int64_t base = (int64_t)blockIdx.x * TS;
+
+    // prologue scratch: inside Gs when it fits, else after the coefficients
+    const size_t scr_bytes = prologue_scratch_bytes(TS, nd, nl);
+    double *scr = scr_bytes <= sizeof(Gs)
+                      ? reinterpret_cast<double *>(Gs)
+                      : reinterpret_cast<double *>(coefT + (size_t)nd * nl * TS);
+    double *s_th = scr;                                  // [7][TS]
+    double2 *s_Y = reinterpret_cast<double2 *>(scr + 7 * TS);   // [TS][nl]
+    double2 *s_F = s_Y + TS * nl;                        // [TS][nd]
+    double *s_qp = reinterpret_cast<double *>(s_F + TS * nd);   // [TS][nd*nl]
+
+    // 1. samples of the tile
+    if (tid < TS) {
+        int64_t i = base + tid;
+        int idx = -1, ok = 0;
+        double th[7] = {0, 0, 0, 0, 0, 1, 0};
+        if (i < N) {
+            idx = perm[i];
+#pragma unroll
+            for (int p = 0; p < 7; p++) th[p] = smp[(int64_t)p * N + idx];
+            ok = sample_ok(g, th);
+            for (int k = 0; k < nd; k++) {
+                int s = shifts[(int64_t)k * N + idx];
+                ok = ok && s >= 0 && s <= g.s_max;
+                s_d[k][tid] = s;
+            }
+        }
+        s_idx[tid] = idx;
+        s_ok[tid] = ok;
+        if (!ok) {
+            th[0] = th[1] = th[2] = th[3] = th[4] = th[6] = 0.0;
+            th[5] = 1.0;
+            for (int k = 0; k < nd; k++) s_d[k][tid] = 0;
+        }
+#pragma unroll
+        for (int p = 0; p < 7; p++) s_th[p * TS + tid] = th[p];
+    }
+    __syncthreads();
+
+    // 2. harmonics and antenna patterns
+    for (int t = tid; t < TS * (nl + nd); t += NT) {
+        if (t < TS * nl) {
+            int al = t / nl, a = t - al * nl;
+            s_Y[al * nl + a] = sylm_dev(g, a, s_th[4 * TS + al], s_th[3 * TS + al]);
+        } else {
+            int u = t - TS * nl;
+            int al = u / nd, k = u - al * nd;
+            double fp, fx;
+            antenna_dev(g, k, s_th[0 * TS + al], s_th[1 * TS + al],
+                        s_th[2 * TS + al], fp, fx);
+            s_F[al * nd + k] = make_double2(fp, fx);   // F = F+ + i Fx
+        }
+    }
+    __syncthreads();
+
+    // 3. coefficients c = (d_ref/D) F_k Y_lm and rows of the quadratic term
+    for (int t = tid; t < TS * nd * nl; t += NT) {
+        int al = t / (nd * nl), r = t - al * (nd * nl);
+        int k = r / nl, a = r - k * nl;
+        double kap = s_ok[al] ? g.d_ref / s_th[5 * TS + al] : 0.0;
+        double2 F = s_F[al * nd + k];
+        double2 Ya = s_Y[al * nl + a];
+        double fyr = F.x * Ya.x - F.y * Ya.y, fyi = F.x * Ya.y + F.y * Ya.x;
+        T2 c;
+        c.x = (TQ)(kap * fyr);
+        c.y = (TQ)(kap * fyi);
+        coefT[(k * nl + a) * TS + al] = c;
+        // |F|^2 Re(conj(Y_a) (U Y)_a) + Re(F^2 Y_a (V Y)_a)
+        double uyr = 0, uyi = 0, vyr = 0, vyi = 0;
+        const double2 *Ur = U + ((int64_t)k * nl + a) * nl;
+        const double2 *Vr = V + ((int64_t)k * nl + a) * nl;
+        for (int b = 0; b < nl; b++) {
+            double2 Yb = s_Y[al * nl + b], u = Ur[b], v = Vr[b];
+            uyr += u.x * Yb.x - u.y * Yb.y;
+            uyi += u.x * Yb.y + u.y * Yb.x;
+            vyr += v.x * Yb.x - v.y * Yb.y;
+            vyi += v.x * Yb.y + v.y * Yb.x;
+        }
+        double f2 = F.x * F.x + F.y * F.y;
+        double F2r = F.x * F.x - F.y * F.y, F2i = 2.0 * F.x * F.y;
+        double yvr = Ya.x * vyr - Ya.y * vyi, yvi = Ya.x * vyi + Ya.y * vyr;
+        double row = f2 * (Ya.x * uyr + Ya.y * uyi) + (F2r * yvr - F2i * yvi);
+        s_qp[al * (nd * nl) + r] = row;
+    }
+    __syncthreads();
+
+    // 4. quadratic term per sample; per-detector window range of the tile
+    if (tid < TS) {
+        double sum = 0.0;
+        for (int r = 0; r < nd * nl; r++) sum += s_qp[tid * (nd * nl) + r];
+        double kap = s_ok[tid] ? g.d_ref / s_th[5 * TS + tid] : 0.0;
+        s_q[tid] = 0.25 * kap * kap * sum;
+    } else if (tid >= 64 && tid < 64 + nd) {
+        int k = tid - 64;
+        int lo = 0x7fffffff, hi = -1;
+        for (int al = 0; al < TS; al++)
+            if (s_ok[al]) {
+                lo = min(lo, s_d[k][al]);
+                hi = max(hi, s_d[k][al]);
+            }
+        if (hi < 0) lo = hi = 0;
+        s_smin[k] = lo;
+        s_spread[k] = hi - lo;
+    }
+    __syncthreads();
+    if (tid < TS)
+        for (int k = 0; k < nd; k++) s_d[k][tid] = s_ok[tid] ? s_d[k][tid] - s_smin[k] : 0;
+    __syncthreads();
+
+    int smax_all = 0;
+    for (int k = 0; k < nd; k++) smax_all = max(smax_all, s_spread[k]);
+    int J = NT - smax_all;
+    if (J < 64) J = 64;
+
+    double m[TS], sacc[TS];
+#pragma unroll
+    for (int al = 0; al < TS; al++) {
+        m[al] = -INFINITY;
+        sacc[al] = 0.0;
+    }
+
+    for (int j0 = 0; j0 < g.n_t; j0 += J) {
+        const int Jc = min(J, g.n_t - j0);
+        // thread tid owns the bins j == tid (mod NT); its bin in this chunk
+        const int jrel = ((tid - j0) % NT + NT) % NT;
+        const bool has = jrel < Jc;
+        TQ L[TS];
+#pragma unroll
+        for (int al = 0; al < TS; al++) L[al] = (TQ)0;
+
+        for (int k = 0; k < nd; k++) {
+            const int Pk = s_smin[k] + j0;
+            const int Wk = Jc + s_spread[k];
+            const T2 *Qk = Q + (int64_t)k * nl * nq + Pk;
+            const T2 *cf = coefT + (k * nl) * TS;
+            for (int blk = 0; blk < Wk; blk += NT) {
+                const int p = blk + tid;
+                TQ acc[TS];
+#pragma unroll
+                for (int al = 0; al < TS; al++) acc[al] = (TQ)0;
+                if (p < Wk) {
+                    const T2 *qp = Qk + p;
+                    T2 qn = qp[0];
+                    for (int a = 0; a < nl; a++) {
+                        const T2 qv = qn;
+                        // next mode's value is in flight during this mode's FMAs
+                        if (a + 1 < nl) qn = qp[(int64_t)(a + 1) * nq];
+                        const T2 *ca = cf + a * TS;
+#pragma unroll
+                        for (int al = 0; al < TS; al++) {
+                            const T2 c = ca[al];
+                            acc[al] = fma(c.x, qv.x, fma(c.y, qv.y, acc[al]));
+                        }
+                    }
+                }
+#pragma unroll
+                for (int al = 0; al < TS; al++) Gs[al * NT + tid] = acc[al];
+                __syncthreads();
+                if (has) {
+#pragma unroll
+                    for (int al = 0; al < TS; al++) {
+                        const int ix = s_d[k][al] + jrel - blk;
+                        if ((unsigned)ix < (unsigned)NT) L[al] += Gs[al * NT + ix];
+                    }
+                }
+                __syncthreads();
+            }
+        }
+
+        if (has) {
+            const int j = j0 + jrel;
+#pragma unroll
+            for (int al = 0; al < TS; al++) {
+                if (!s_ok[al]) continue;
+                const double x = (double)L[al] - s_q[al];
+                if (DUMP) series[(int64_t)s_idx[al] * g.n_t + j] = x;
+                // online log-sum-exp; one exp per bin
+                const double e = exp(-fabs(x - m[al]));
+                if (x > m[al]) {
+                    sacc[al] = sacc[al] * e + 1.0;
+                    m[al] = x;
+                } else {
+                    sacc[al] += e;
+                }
+            }
+        }
+    }
+
+    // deterministic block reduction: max, then sum of s e^{m - M}
+    const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+    for (int al = 0; al < TS; al++) {
+        double v = m[al];
+        for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+        if (lane == 0) s_red[wv][al] = v;
+    }
+    __syncthreads();
+    if (tid < TS) {
+        double M = s_red[0][tid];
+        for (int w = 1; w < NW; w++) M = fmax(M, s_red[w][tid]);
+        s_M[tid] = M;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int al = 0; al < TS; al++) {
+        const double M = s_M[al];
+        double v = (m[al] == -INFINITY) ? 0.0 : sacc[al] * exp(m[al] - M);
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) s_red[wv][al] = v;
+    }
+    __syncthreads();
+    if (tid < TS && s_idx[tid] >= 0) {
+        double S = s_red[0][tid];
+        for (int w = 1; w < NW; w++) S += s_red[w][tid];
+        out[s_idx[tid]] = s_ok[tid] ? s_M[tid] + log(S) - log((double)g.n_t) : NAN;
+    }
+}
+
+// --------------------------------------------------------------- prior
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+__device__ inline double u53(uint32_t w0, uint32_t w1)
+{
+    return ((double)(w0 >> 5) * 67108864.0 + (double)(w1 >> 6) + 0.5) /
+           9007199254740992.0;
+}
+
+__global__ __launch_bounds__(256) void k_prior(uint64_t seed, int64_t first,
+                                               int64_t N, double d_min,
+                                               double d_max, double t_ref_max,
+                                               double *smp, int64_t ld,
+                                               double *ln_p)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    const uint64_t i = (uint64_t)(first + t);
+    uint32_t w[16];
+#pragma unroll
+    for (uint32_t b = 0; b < 4; b++) {
+        uint32_t c[4] = {(uint32_t)i, (uint32_t)(i >> 32), b, 0x494C4531u};
+        philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+        w[4 * b] = c[0];
+        w[4 * b + 1] = c[1];
+        w[4 * b + 2] = c[2];
+        w[4 * b + 3] = c[3];
+    }
+    {
+#pragma clang fp contract(off)
+    const double v3 = d_max * d_max * d_max - d_min * d_min * d_min;
+    const double ra = 2.0 * kPi * u53(w[0], w[1]);
+    const double dec = asin(2.0 * u53(w[2], w[3]) - 1.0);
+    const double psi = kPi * u53(w[4], w[5]);
+    const double phi = 2.0 * kPi * u53(w[6], w[7]);
+    const double ci = 2.0 * u53(w[8], w[9]) - 1.0;
+    const double D = cbrt(d_min * d_min * d_min + u53(w[10], w[11]) * v3);
+    const double tr = t_ref_max * (2.0 * u53(w[12], w[13]) - 1.0);
+    smp[0 * ld + t] = ra;
+    smp[1 * ld + t] = dec;
+    smp[2 * ld + t] = psi;
+    smp[3 * ld + t] = phi;
+    smp[4 * ld + t] = ci;
+    smp[5 * ld + t] = D;
+    smp[6 * ld + t] = tr;
+    if (ln_p)
+        ln_p[t] = -log(kTwoPi) + log(cos(dec) / 2.0) - log(kPi) - log(kTwoPi) -
+                  log(2.0) + log(3.0 * D * D / v3) - log(2.0 * t_ref_max);
+    }
+}
+
+// ------------------------------------------------------------- reduction
+constexpr int kRedBlocks = 256;
+constexpr int kRedT = 256;
+
+__device__ inline double lnw_at(const double *lnL, const double *lp,
+                                const double *lq, int64_t i)
+{
+    return lnL[i] + (lp ? lp[i] : 0.0) - (lq ? lq[i] : 0.0);
+}
+
+__global__ __launch_bounds__(kRedT) void k_red_max(const double *lnL,
+                                                   const double *lp,
+                                                   const double *lq, int64_t N,
+                                                   double *tmp)
+{
+    __shared__ double sm[kRedT], sl[kRedT];
+    double M = -INFINITY, ML = -INFINITY;
+    for (int64_t i = (int64_t)blockIdx.x * kRedT + threadIdx.x; i < N;
+         i += (int64_t)kRedBlocks * kRedT) {
+        double w = lnw_at(lnL, lp, lq, i);
+        M = w > M ? w : M;
+        ML = lnL[i] > ML ? lnL[i] : ML;
+    }
+    sm[threadIdx.x] = M;
+    sl[threadIdx.x] = ML;
+    __syncthreads();
+    for (int s = kRedT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+            sl[threadIdx.x] = fmax(sl[threadIdx.x], sl[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        tmp[blockIdx.x] = sm[0];
+        tmp[kRedBlocks + blockIdx.x] = sl[0];
+    }
+}
+
+__device__ inline double global_max(const double *tmp)
+{
+    double M = -INFINITY;
+    for (int b = 0; b < kRedBlocks; b++) M = fmax(M, tmp[b]);
+    return M;
+}
+
+__global__ __launch_bounds__(kRedT) void k_red_sum(const double *lnL,
+                                                   const double *lp,
+                                                   const double *lq, int64_t N,
+                                                   double *tmp)
+{
+    __shared__ double s1[kRedT], s2[kRedT];
+    __shared__ double sM;
+    if (threadIdx.x == 0) sM = global_max(tmp);
+    __syncthreads();
+    const double M = sM;
+    double a = 0.0, b = 0.0;
+    if (M != -INFINITY) {
+        for (int64_t i = (int64_t)blockIdx.x * kRedT + threadIdx.x; i < N;
+             i += (int64_t)kRedBlocks * kRedT) {
+            double e = exp(lnw_at(lnL, lp, lq, i) - M);
+            a += e;
+            b += e * e;
+        }
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = kRedT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            s1[threadIdx.x] += s1[threadIdx.x + s];
+            s2[threadIdx.x] += s2[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        tmp[2 * kRedBlocks + blockIdx.x] = s1[0];
+        tmp[3 * kRedBlocks + blockIdx.x] = s2[0];
+    }
+}
+
+__global__ __launch_bounds__(kRedT) void k_red_final(const double *tmp,
+                                                     int64_t N, double *partial)
+{
+    __shared__ double s1[kRedT], s2[kRedT], sl[kRedT];
+    const int t = threadIdx.x;   // kRedT == kRedBlocks
+    s1[t] = tmp[2 * kRedBlocks + t];
+    s2[t] = tmp[3 * kRedBlocks + t];
+    sl[t] = tmp[kRedBlocks + t];
+    __syncthreads();
+    for (int s = kRedT / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            s1[t] += s1[t + s];
+            s2[t] += s2[t + s];
+            sl[t] = fmax(sl[t], sl[t + s]);
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        partial[0] = global_max(tmp);
+        partial[1] = s1[0];
+        partial[2] = s2[0];
+        partial[3] = (double)N;
+        partial[4] = sl[0];
+    }
+}
+
+__global__ void k_finish(const double *parts, int n_part, double *res)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double M = -INFINITY, ML = -INFINITY, n = 0.0;
+    for (int i = 0; i < n_part; i++) {
+        M = fmax(M, parts[5 * i]);
+        ML = fmax(ML, parts[5 * i + 4]);
+        n += parts[5 * i + 3];
+    }
+    double S1 = 0.0, S2 = 0.0;
+    if (M != -INFINITY)
+        for (int i = 0; i < n_part; i++) {
+            if (parts[5 * i] == -INFINITY) continue;
+            double e = exp(parts[5 * i] - M);
+            S1 += parts[5 * i + 1] * e;
+            S2 += parts[5 * i + 2] * e * e;
+        }
+    if (M == -INFINITY || n == 0.0) {
+        res[0] = -INFINITY;
+        res[1] = 0.0;
+        res[2] = 0.0;
+        res[3] = NAN;
+    } else {
+        res[0] = M + log(S1) - log(n);
+        res[1] = S1;
+        res[2] = S1 * S1 / S2;
+        double var = S2 / (S1 * S1) - 1.0 / n;
+        res[3] = var > 0.0 ? sqrt(var) : 0.0;
+    }
+    res[4] = ML;
+    res[5] = n;
+}
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <typename TQ, int TS, int NT>
+hipError_t launch_contract_t(const ile_geom &g, const double *smp, int64_t N,
+                             const int32_t *perm, const int32_t *shifts,
+                             const void *Q, const double *U, const double *V,
+                             double *out, double *series, hipStream_t st)
+{
+    using T2 = typename vec2<TQ>::type;
+    size_t dyn = (size_t)g.n_det * g.n_lm * TS * sizeof(T2);
+    const size_t scr = prologue_scratch_bytes(TS, g.n_det, g.n_lm);
+    if (scr > (size_t)TS * NT * sizeof(TQ)) dyn += scr;
+    const unsigned grid = nblk(N, TS);
+    if (series)
+        hipLaunchKernelGGL((k_contract<TQ, TS, NT, true>), dim3(grid), dim3(NT), dyn, st,
+                           g, smp, N, perm, shifts, (const T2 *)Q,
+                           (const double2 *)U, (const double2 *)V, out, series);
+    else
+        hipLaunchKernelGGL((k_contract<TQ, TS, NT, false>), dim3(grid), dim3(NT), dyn, st,
+                           g, smp, N, perm, shifts, (const T2 *)Q,
+                           (const double2 *)U, (const double2 *)V, out, series);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+hipError_t ile_launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(nblk(n, 256)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t ile_launch_prep(const ile_geom &g, const double *smp, int64_t N,
+                           int32_t *shifts, uint32_t *keys, uint32_t *hist,
+                           uint32_t n_buckets, int32_t *err, hipStream_t st)
+{
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prep, dim3(nblk(N, 256)), dim3(256), 0, st, g, smp, N,
+                       shifts, keys, hist, n_buckets, err);
+    return hipGetLastError();
+}
+
+int64_t ile_scan_tmp_words(int64_t n) { return (n + kScanBlock - 1) / kScanBlock; }
+
+hipError_t ile_launch_scan(uint32_t *v, int64_t n, uint32_t *tmp, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = ile_scan_tmp_words(n);
+    if (nb > kScanBlock) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(kScanT), 0, st, v, n, tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanT), 0, st, tmp, (int)nb);
+    hipLaunchKernelGGL(k_scan_add, dim3(nblk(n, 256)), dim3(256), 0, st, v, n,
+                       (const uint32_t *)tmp);
+    return hipGetLastError();
+}
+
+hipError_t ile_launch_scatter(const uint32_t *keys, int64_t N, uint32_t *offs,
+                              int32_t *perm, hipStream_t st)
+{
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter, dim3(nblk(N, 256)), dim3(256), 0, st, keys, N,
+                       offs, perm);
+    return hipGetLastError();
+}
+
+hipError_t ile_launch_identity(int32_t *perm, int64_t N, hipStream_t st)
+{
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_identity, dim3(nblk(N, 256)), dim3(256), 0, st, perm, N);
+    return hipGetLastError();
+}
+
+size_t ile_contract_lds_bytes(const ile_geom &g, ile_precision prec,
+                              const ile_tune &tu)
+{
+    size_t e = prec == ILE_FP64 ? 8 : 4;
+    size_t gs = (size_t)tu.tile_samples * tu.threads * e;
+    size_t coef = (size_t)g.n_det * g.n_lm * tu.tile_samples * 2 * e;
+    size_t scr = prologue_scratch_bytes(tu.tile_samples, g.n_det, g.n_lm);
+    return gs + coef + (scr > gs ? scr : 0) + 4096;
+}
+
+hipError_t ile_launch_contract(const ile_geom &g, ile_precision prec,
+                               const ile_tune &tu, const double *smp, int64_t N,
+                               const int32_t *perm, const int32_t *shifts,
+                               const void *Q, const double *U, const double *V,
+                               double *out, double *series, hipStream_t st)
+{
+    if (N <= 0) return hipSuccess;
+    if (tu.tile_samples != 16 || tu.threads != 256) return hipErrorInvalidValue;
+    if (prec == ILE_FP64)
+        return launch_contract_t<double, 16, 256>(g, smp, N, perm, shifts, Q, U, V,
+                                                  out, series, st);
+    if (prec == ILE_FP32)
+        return launch_contract_t<float, 16, 256>(g, smp, N, perm, shifts, Q, U, V,
+                                                 out, series, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t ile_launch_prior(uint64_t seed, int64_t first, int64_t N,
+                            double d_min, double d_max, double t_ref_max,
+                            double *smp, int64_t ld, double *ln_p, hipStream_t st)
+{
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prior, dim3(nblk(N, 256)), dim3(256), 0, st, seed, first,
+                       N, d_min, d_max, t_ref_max, smp, ld, ln_p);
+    return hipGetLastError();
+}
+
+int ile_reduce_blocks() { return kRedBlocks; }
+
+hipError_t ile_launch_reduce(const double *lnL, const double *ln_p,
+                             const double *ln_q, int64_t N, double *tmp,
+                             double *partial, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_red_max, dim3(kRedBlocks), dim3(kRedT), 0, st, lnL, ln_p,
+                       ln_q, N, tmp);
+    hipLaunchKernelGGL(k_red_sum, dim3(kRedBlocks), dim3(kRedT), 0, st, lnL, ln_p,
+                       ln_q, N, tmp);
+    hipLaunchKernelGGL(k_red_final, dim3(1), dim3(kRedT), 0, st, (const double *)tmp,
+                       N, partial);
+    return hipGetLastError();
+}
+
+hipError_t ile_launch_finish(const double *partials, int n_part, double *result,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, partials, n_part, result);
+    return hipGetLastError();
+}
+
+hipError_t ile_launch_to_bf16_split(const double *, int64_t, void *, hipStream_t)
+{
+    return hipErrorNotSupported;
+}

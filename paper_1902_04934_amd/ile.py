@@ -1,0 +1,277 @@
+"""ctypes binding of libile (include/ile.h): argument marshalling only.
+
+Every step of the likelihood runs in the HIP library; this module converts
+numpy arrays and device tensors (anything with ``data_ptr()``, e.g. a torch
+tensor on the GPU) into the C ABI's plain pointers and raises ``IleError`` on
+a non-OK status.  The functions keep the C names; ``Context`` bundles them.
+Loading fails loudly when libile.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libile.so")
+
+ILE_OK, ILE_E_ARG, ILE_E_STATE, ILE_E_RANGE, ILE_E_NUMERIC, ILE_E_DEVICE, \
+    ILE_E_NOMEM, ILE_E_UNSUPPORTED = range(8)
+STATUS_NAMES = ["ILE_OK", "ILE_E_ARG", "ILE_E_STATE", "ILE_E_RANGE",
+                "ILE_E_NUMERIC", "ILE_E_DEVICE", "ILE_E_NOMEM",
+                "ILE_E_UNSUPPORTED"]
+PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
+ILE_OPT_SORT = 0
+
+
+class IleError(RuntimeError):
+    def __init__(self, status, message):
+        self.status = status
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"{name}: {message}")
+
+
+class Mode(C.Structure):
+    _fields_ = [("l", C.c_int32), ("m", C.c_int32)]
+
+
+class Detector(C.Structure):
+    _fields_ = [("lat_deg", C.c_double), ("lon_deg", C.c_double),
+                ("xarm_az_deg", C.c_double)]
+
+
+class Config(C.Structure):
+    _fields_ = [("n_det", C.c_int32), ("n_lm", C.c_int32),
+                ("modes", C.POINTER(Mode)), ("srate_hz", C.c_double),
+                ("n_t", C.c_int32), ("d_ref_mpc", C.c_double),
+                ("gmst_rad", C.c_double), ("earth_radius_m", C.c_double),
+                ("t_ref_max_s", C.c_double), ("precision", C.c_int),
+                ("device", C.c_int32), ("stream", C.c_void_p)]
+
+
+class Result(C.Structure):
+    _fields_ = [("ln_L_marg", C.c_double), ("n_eff", C.c_double),
+                ("n_eff_kish", C.c_double), ("sigma_ln_L", C.c_double),
+                ("max_ln_L", C.c_double), ("n_samples", C.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+_dp = C.POINTER(C.c_double)
+_vp = C.c_void_p
+
+
+def lib():
+    """Load libile.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build the HIP library first "
+                "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = C.CDLL(LIB_PATH)
+        L.ile_create.argtypes = [C.POINTER(Config), C.POINTER(_vp)]
+        L.ile_set_data.argtypes = [_vp, _dp, C.c_int64, C.c_double, _dp, _dp,
+                                   C.POINTER(Detector)]
+        L.ile_eval.argtypes = [_vp, _dp, C.c_int64, _dp]
+        L.ile_eval_series.argtypes = [_vp, _dp, C.c_int64, _dp]
+        L.ile_integrate.argtypes = [_vp, _dp, _dp, _dp, C.c_int64, C.POINTER(Result)]
+        L.ile_eval_dev.argtypes = [_vp, _vp, C.c_int64, _vp]
+        L.ile_integrate_dev.argtypes = [_vp, _vp, _vp, _vp, C.c_int64, _vp]
+        L.ile_draw_prior_dev.argtypes = [_vp, C.c_uint64, C.c_int64, C.c_int64,
+                                         C.c_double, C.c_double, _vp, C.c_int64, _vp]
+        L.ile_run_prior.argtypes = [_vp, C.c_uint64, C.c_int64, C.c_int64,
+                                    C.c_double, C.c_double, C.POINTER(Result)]
+        L.ile_sync.argtypes = [_vp]
+        L.ile_set_option.argtypes = [_vp, C.c_int, C.c_int64]
+        L.ile_last_kernel_ms.argtypes = [_vp]
+        L.ile_last_kernel_ms.restype = C.c_double
+        L.ile_destroy.argtypes = [_vp]
+        L.ile_destroy.restype = None
+        L.ile_last_error.argtypes = [_vp]
+        L.ile_last_error.restype = C.c_char_p
+        L.ile_status_string.argtypes = [C.c_int]
+        L.ile_status_string.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status, ctx=None):
+    if status != ILE_OK:
+        msg = ""
+        if ctx:
+            m = lib().ile_last_error(ctx)
+            msg = m.decode() if m else ""
+        if not msg:
+            msg = lib().ile_status_string(status).decode()
+        raise IleError(status, msg)
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def _dev(t):
+    return None if t is None else C.c_void_p(int(t.data_ptr()))
+
+
+# ----------------------------------------------------------- C-named calls
+def ile_create(dets, modes, srate_hz, n_t, *, d_ref_mpc=100.0, gmst_rad=0.0,
+               earth_radius_m=6378.0e3, t_ref_max_s=0.01, precision="fp64",
+               device=0, stream=None):
+    modes_arr = (Mode * len(modes))(*[Mode(int(l), int(m)) for (l, m) in modes])
+    cfg = Config(len(dets), len(modes), modes_arr, float(srate_hz), int(n_t),
+                 d_ref_mpc, gmst_rad, earth_radius_m, t_ref_max_s,
+                 PRECISION[precision], int(device),
+                 C.c_void_p(stream) if stream else None)
+    h = _vp()
+    _check(lib().ile_create(C.byref(cfg), C.byref(h)))
+    return h
+
+
+def ile_set_data(h, Q, t0_s, U, V, dets):
+    Qa = np.ascontiguousarray(Q, np.complex128)
+    n_q = Qa.shape[-1]
+    Qf, Qp = _f64(Qa.view(np.float64))
+    Uf, Up = _f64(np.ascontiguousarray(U, np.complex128).view(np.float64))
+    Vf, Vp = _f64(np.ascontiguousarray(V, np.complex128).view(np.float64))
+    darr = (Detector * len(dets))(*[Detector(*d) for d in dets])
+    _check(lib().ile_set_data(h, Qp, n_q, float(t0_s), Up, Vp, darr), h)
+
+
+def ile_eval(h, samples):
+    s, sp = _f64(samples)
+    n = s.shape[1]
+    out = np.empty(n)
+    _check(lib().ile_eval(h, sp, n, out.ctypes.data_as(_dp)), h)
+    return out
+
+
+def ile_eval_series(h, samples, n_t):
+    s, sp = _f64(samples)
+    n = s.shape[1]
+    out = np.empty((n, n_t))
+    _check(lib().ile_eval_series(h, sp, n, out.ctypes.data_as(_dp)), h)
+    return out
+
+
+def ile_integrate(h, samples, ln_p, ln_q):
+    s, sp = _f64(samples)
+    lp, lpp = _f64(ln_p)
+    lq, lqp = _f64(ln_q)
+    r = Result()
+    _check(lib().ile_integrate(h, sp, lpp, lqp, s.shape[1], C.byref(r)), h)
+    return r.as_dict()
+
+
+def ile_eval_dev(h, samples_dev, n, out_dev):
+    _check(lib().ile_eval_dev(h, _dev(samples_dev), int(n), _dev(out_dev)), h)
+
+
+def ile_integrate_dev(h, samples_dev, ln_p_dev, ln_q_dev, n, result_dev):
+    _check(lib().ile_integrate_dev(h, _dev(samples_dev), _dev(ln_p_dev),
+                                   _dev(ln_q_dev), int(n), _dev(result_dev)), h)
+
+
+def ile_draw_prior_dev(h, seed, first, n, d_min, d_max, samples_dev, ld,
+                       ln_p_dev=None):
+    _check(lib().ile_draw_prior_dev(h, int(seed), int(first), int(n), float(d_min),
+                                    float(d_max), _dev(samples_dev), int(ld),
+                                    _dev(ln_p_dev)), h)
+
+
+def ile_run_prior(h, seed, n, chunk, d_min=10.0, d_max=1000.0):
+    r = Result()
+    _check(lib().ile_run_prior(h, int(seed), int(n), int(chunk), float(d_min),
+                               float(d_max), C.byref(r)), h)
+    return r.as_dict()
+
+
+def ile_sync(h):
+    _check(lib().ile_sync(h), h)
+
+
+def ile_set_option(h, opt, value):
+    _check(lib().ile_set_option(h, int(opt), int(value)), h)
+
+
+def ile_last_kernel_ms(h):
+    return lib().ile_last_kernel_ms(h)
+
+
+def ile_destroy(h):
+    lib().ile_destroy(h)
+
+
+# -------------------------------------------------------------- Context
+class Context:
+    """One intrinsic point on one GPU: create + set_data, then evaluate."""
+
+    def __init__(self, inst, precision="fp64", device=0, stream=None, sort=True):
+        self.inst = inst
+        self.n_t = inst.n_t
+        self.h = ile_create(inst.dets, inst.modes, inst.srate_hz, inst.n_t,
+                            d_ref_mpc=inst.d_ref_mpc, gmst_rad=inst.gmst_rad,
+                            earth_radius_m=inst.earth_radius_m,
+                            t_ref_max_s=inst.t_ref_max_s, precision=precision,
+                            device=device, stream=stream)
+        try:
+            ile_set_data(self.h, inst.Q, inst.t0_s, inst.U, inst.V, inst.dets)
+            if not sort:
+                ile_set_option(self.h, ILE_OPT_SORT, 0)
+        except Exception:
+            self.close()
+            raise
+
+    def eval(self, samples):
+        return ile_eval(self.h, samples)
+
+    def eval_series(self, samples):
+        return ile_eval_series(self.h, samples, self.n_t)
+
+    def integrate(self, samples, ln_p, ln_q):
+        return ile_integrate(self.h, samples, ln_p, ln_q)
+
+    def eval_dev(self, samples_dev, n, out_dev):
+        ile_eval_dev(self.h, samples_dev, n, out_dev)
+
+    def integrate_dev(self, samples_dev, ln_p_dev, ln_q_dev, n, result_dev):
+        ile_integrate_dev(self.h, samples_dev, ln_p_dev, ln_q_dev, n, result_dev)
+
+    def draw_prior_dev(self, seed, first, n, samples_dev, ld, ln_p_dev=None,
+                       d_min=10.0, d_max=1000.0):
+        ile_draw_prior_dev(self.h, seed, first, n, d_min, d_max, samples_dev, ld,
+                           ln_p_dev)
+
+    def run_prior(self, seed, n, chunk=0, d_min=10.0, d_max=1000.0):
+        return ile_run_prior(self.h, seed, n, chunk, d_min, d_max)
+
+    def sync(self):
+        ile_sync(self.h)
+
+    def set_sort(self, on):
+        ile_set_option(self.h, ILE_OPT_SORT, 1 if on else 0)
+
+    def last_kernel_ms(self):
+        return ile_last_kernel_ms(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            ile_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
