@@ -63,6 +63,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--samples", type=int, default=None)
+    ap.add_argument("--engine", default=None, choices=["mfma", "valu"],
+                    help="contraction engine (default: matrix cores for FP64)")
+    ap.add_argument("--threads", type=int, default=None, choices=[256, 512])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
@@ -78,7 +81,8 @@ def main():
     inst = synth.config2()
     n_total, seed = synth.CONFIG_SAMPLES[2]
     n = args.samples or n_total
-    ctx = ile.Context(inst, precision=args.precision, device=0)
+    ctx = ile.Context(inst, precision=args.precision, device=0, engine=args.engine,
+                      threads=args.threads)
     torch.cuda.synchronize()
     if args.calib_copy:
         a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
@@ -113,7 +117,9 @@ def main():
                                "21 modes (l=2..4), Q 16384 complex points at 16384 Hz, "
                                f"{n} prior samples, {inst.n_t} time bins",
                    "n_samples": n, "n_t": inst.n_t, "n_det": inst.n_det,
-                   "n_lm": inst.n_lm, "precision": args.precision},
+                   "n_lm": inst.n_lm, "precision": args.precision,
+                   "engine": args.engine or ("mfma" if args.precision == "fp64" else "valu"),
+                   "threads": args.threads or 256},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                      "kernel": "k_contract", "kernel_ms": kernel_ms,

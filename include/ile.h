@@ -21,7 +21,7 @@
  *   earth_radius_m); the paper prints F+ - i Fx beside Eq. (7), but only
  *   F+ + i Fx makes Eq. (7) equal Eq. (1) for h = h+ - i hx (Eq. (5)).
  * Harmonics: -2Y_lm(iota, phi) in the Wigner-d form; modes are any (l, m)
- *   with 2 <= l <= 8, |m| <= l.
+ *   with 2 <= l <= 6, |m| <= l.
  * Time: Q[i] is the value at detector time t0 + i/srate (t0 given at
  *   set_data).  Sample alpha and bin j (0 <= j < n_t, n_t odd) mean the
  *   geocentre time t_ref + (j - (n_t-1)/2)/srate; detector k reads
@@ -178,8 +178,12 @@ ile_status ile_run_prior(ile_ctx *ctx, uint64_t seed, int64_t N,
 ile_status ile_sync(ile_ctx *ctx);
 
 typedef enum {
-    ILE_OPT_SORT = 0,  /* 1: order samples by window position before the
-                          contraction (default), 0: keep input order */
+    ILE_OPT_SORT = 0,    /* 1: order samples by window position before the
+                            contraction (default), 0: keep input order */
+    ILE_OPT_ENGINE = 1,  /* contraction engine: 1 = FP64 matrix cores (FP64
+                            default), 0 = vector FMA (the only FP32 engine) */
+    ILE_OPT_THREADS = 2  /* threads per workgroup = positions per block:
+                            256 (default) or 512 */
 } ile_option;
 ile_status ile_set_option(ile_ctx *ctx, ile_option opt, int64_t value);
 

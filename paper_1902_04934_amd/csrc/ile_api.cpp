@@ -37,7 +37,8 @@ struct ile_ctx {
     ile_geom g{};
     uint32_t n_buckets = 1;
     int sort = 1;
-    ile_tune tune{16, 256};
+    ile_tune tune{16, 256, 1};
+    int lds_max = 0;
     DevBuf Q, U, V;
     DevBuf smp, out, lnp, lnq, shifts, keys, perm, hist, scan_tmp, errflag,
         red_tmp, parts, res, series;
@@ -205,6 +206,11 @@ ile_status run_eval(ile_ctx *c, const double *smp, int64_t N, double *out,
     if (N > 0x7fffffff) return fail(c, ILE_E_ARG, "N = %lld exceeds 2^31-1", (long long)N);
     ile_status s = ensure_work(c, N);
     if (s) return s;
+    const size_t lds_need = ile_contract_lds_bytes(c->g, c->cfg.precision, c->tune);
+    if (lds_need > (size_t)c->lds_max)
+        return fail(c, ILE_E_UNSUPPORTED,
+                    "contraction needs %zu bytes of LDS per workgroup, device has %d",
+                    lds_need, c->lds_max);
     hipStream_t st = c->stream;
     uint32_t *hist = (uint32_t *)c->hist.p;
     HIP_TRY(c, ile_launch_fill_u32(hist, 0u, c->n_buckets, st));
@@ -325,6 +331,13 @@ ile_status ile_create(const ile_config *cfg, ile_ctx **out)
         delete c;
         return ILE_E_DEVICE;
     }
+    if (hipDeviceGetAttribute(&c->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                              cfg->device) != hipSuccess) {
+        delete c;
+        return ILE_E_DEVICE;
+    }
+    // FP64: matrix-core G phase; FP32: vector ALUs
+    c->tune.engine = cfg->precision == ILE_FP64 ? 1 : 0;
     if (cfg->stream) {
         c->stream = (hipStream_t)cfg->stream;
     } else {
@@ -420,24 +433,27 @@ ile_status ile_set_data(ile_ctx *c, const double *Q, int64_t n_q, double t0_s,
 
     ile_status s;
     HIP_TRY(c, hipSetDevice(c->cfg.device));
-    int lds_max = 0;
-    HIP_TRY(c, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock,
-                                     c->cfg.device));
-    const size_t lds_need = ile_contract_lds_bytes(g, c->cfg.precision, c->tune);
-    if (lds_need > (size_t)lds_max)
-        return fail(c, ILE_E_UNSUPPORTED,
-                    "contraction needs %zu bytes of LDS per workgroup, device has %d",
-                    lds_need, lds_max);
     const size_t qe = c->cfg.precision == ILE_FP64 ? 16 : 8;
     if ((s = ensure(c, c->Q, nQ * qe))) return s;
     if ((s = ensure(c, c->U, nUV * 16))) return s;
     if ((s = ensure(c, c->V, nUV * 16))) return s;
+    // device layout: planar rows per detector, row 2a = Re Q_a, 2a+1 = Im Q_a
     if (c->cfg.precision == ILE_FP64) {
-        HIP_TRY(c, hipMemcpy(c->Q.p, Q, nQ * 16, hipMemcpyHostToDevice));
+        std::vector<double> h(2 * nQ);
+        for (size_t ka = 0; ka < (size_t)nd * nl; ka++)
+            for (int64_t i = 0; i < n_q; i++) {
+                h[(2 * ka) * n_q + i] = Q[2 * (ka * n_q + i)];
+                h[(2 * ka + 1) * n_q + i] = Q[2 * (ka * n_q + i) + 1];
+            }
+        HIP_TRY(c, hipMemcpy(c->Q.p, h.data(), nQ * 16, hipMemcpyHostToDevice));
     } else {
-        std::vector<float> f(2 * nQ);
-        for (size_t i = 0; i < 2 * nQ; i++) f[i] = (float)Q[i];
-        HIP_TRY(c, hipMemcpy(c->Q.p, f.data(), nQ * 8, hipMemcpyHostToDevice));
+        std::vector<float> h(2 * nQ);
+        for (size_t ka = 0; ka < (size_t)nd * nl; ka++)
+            for (int64_t i = 0; i < n_q; i++) {
+                h[(2 * ka) * n_q + i] = (float)Q[2 * (ka * n_q + i)];
+                h[(2 * ka + 1) * n_q + i] = (float)Q[2 * (ka * n_q + i) + 1];
+            }
+        HIP_TRY(c, hipMemcpy(c->Q.p, h.data(), nQ * 8, hipMemcpyHostToDevice));
     }
     HIP_TRY(c, hipMemcpy(c->U.p, U, nUV * 16, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->V.p, V, nUV * 16, hipMemcpyHostToDevice));
@@ -620,12 +636,26 @@ ile_status ile_set_option(ile_ctx *c, ile_option opt, int64_t v)
 {
     if (!c) return ILE_E_ARG;
     begin_call(c);
+    ile_tune t = c->tune;
     switch (opt) {
     case ILE_OPT_SORT:
         if (v != 0 && v != 1) return fail(c, ILE_E_ARG, "sort must be 0 or 1");
         c->sort = (int)v;
         return ILE_OK;
+    case ILE_OPT_ENGINE:
+        if (v != 0 && v != 1) return fail(c, ILE_E_ARG, "engine must be 0 or 1");
+        t.engine = (int)v;
+        break;
+    case ILE_OPT_THREADS:
+        t.threads = (int)v;
+        break;
+    default:
+        return fail(c, ILE_E_ARG, "unknown option %d", (int)opt);
     }
+    if (!ile_tune_supported(c->cfg.precision, t))
+        return fail(c, ILE_E_UNSUPPORTED, "tuning not supported for this precision");
+    c->tune = t;
+    return ILE_OK;
     return fail(c, ILE_E_ARG, "unknown option %d", (int)opt);
 }
 

@@ -38,9 +38,11 @@ struct ile_geom {
 
 // Tuning of the contraction kernel.
 struct ile_tune {
-    int tile_samples;   // samples per workgroup tile
-    int threads;        // threads per workgroup (= positions per G block)
+    int tile_samples;   // samples per workgroup tile (16)
+    int threads;        // threads per workgroup (= positions per G block): 256 or 512
+    int engine;         // 0: FMA on the vector ALUs, 1: FP64 matrix cores
 };
+bool ile_tune_supported(ile_precision prec, const ile_tune &tu);
 
 // Launch wrappers (ile_kernels.hip).  All are asynchronous on `st`.
 hipError_t ile_launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);

@@ -27,9 +27,6 @@ constexpr double kC = 299792458.0;
 constexpr double kTwoPi = 6.283185307179586476925;
 constexpr double kPi = 3.141592653589793238463;
 
-template <typename T> struct vec2;
-template <> struct vec2<double> { using type = double2; };
-template <> struct vec2<float> { using type = float2; };
 
 // ---------------------------------------------------------------- geometry
 // Arrival delay at site k relative to the geocentre, tau = -n.r/c, with n
@@ -259,17 +256,90 @@ __global__ __launch_bounds__(256) void k_identity(int32_t *perm, int64_t N)
 
 // ------------------------------------------------------------ contraction
 // One workgroup = one tile of TS samples (in sorted order), NT threads.
-// LDS: Gs[TS][NT] partial sums (also the prologue scratch), coefficient
-// table coefT[n_det][n_lm][TS] (dynamic), small per-sample arrays.
-template <typename TQ, int TS, int NT, bool DUMP>
+// Q is stored planar per detector: row 2a holds Re Q_a, row 2a+1 Im Q_a,
+// so Re(conj(c_a) Q_a[p]) = sum over the two rows of C[row] * Qm[row][p].
+//
+// G phase per (chunk, detector), two engines:
+//   ENG_VALU: each thread owns one position p and accumulates G for all TS
+//             samples with FMAs; coefficients broadcast from LDS.
+//   ENG_MFMA: the G block is the real GEMM  C[TS x 2n_lm] * Qm[2n_lm x p]
+//             on v_mfma_f64_16x16x4 (TS = 16 = M); each wave owns N-tiles of
+//             16 positions, A (coefficients) from LDS, B (Q) from memory.
+// Realign: thread j of the chunk adds G[alpha][s_alpha,k - s_min,k + j] for
+// every sample; online FP64 log-sum-exp over the bins each thread owns.
+enum { ENG_VALU = 0, ENG_MFMA = 1 };
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// G block on the matrix cores: Gs[alpha][p] = sum_r A[alpha][r] Qm[r][P0 + p]
+// for p < W (<= NT), 16 samples.  v_mfma_f64_16x16x4 on gfx950 (checked
+// with a lane-layout probe): lane l supplies A[l%16][l/16] and B[l/16][l%16]
+// and receives D[l/16 + 4v][l%16], v = 0..3.
+// Wave wv computes the N-tiles wv, wv+NW, ... of 16 positions; rows r >= R
+// of the padded K dimension are zero in A and read as zero from Q; columns
+// past the end of Q are clamped (their results are never read).
+template <typename TQ, int NT>
+__device__ inline void mfma_gphase(TQ *Gs, const TQ *coefA, const TQ *Qk, int nq,
+                                   int R, int KS, int P0, int W, int lane, int wv)
+{
+    constexpr int NW = NT / 64, TPW = NT / 16 / NW;
+    const int ntile = (W + 15) >> 4;
+    const int row = lane >> 4, col = lane & 15;
+    v4d acc[TPW];
+    int pos[TPW];
+#pragma unroll
+    for (int u = 0; u < TPW; u++) {
+        acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+        pos[u] = min(P0 + 16 * (wv + NW * u) + col, nq - 1);
+    }
+    double a_cur = coefA[lane], b_cur[TPW];
+#pragma unroll
+    for (int u = 0; u < TPW; u++) b_cur[u] = row < R ? (double)Qk[(int64_t)row * nq + pos[u]] : 0.0;
+    for (int ks = 0; ks < KS; ks++) {
+        double a_nxt = 0.0, b_nxt[TPW];
+        const int rn = 4 * (ks + 1) + row;
+#pragma unroll
+        for (int u = 0; u < TPW; u++) b_nxt[u] = 0.0;
+        if (ks + 1 < KS) {
+            a_nxt = coefA[(ks + 1) * 64 + lane];
+#pragma unroll
+            for (int u = 0; u < TPW; u++)
+                if (rn < R) b_nxt[u] = (double)Qk[(int64_t)rn * nq + pos[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < TPW; u++)
+            if (wv + NW * u < ntile)
+                acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur, b_cur[u], acc[u], 0, 0, 0);
+        a_cur = a_nxt;
+#pragma unroll
+        for (int u = 0; u < TPW; u++) b_cur[u] = b_nxt[u];
+    }
+#pragma unroll
+    for (int u = 0; u < TPW; u++) {
+        const int t = wv + NW * u;
+        if (t < ntile) {
+#pragma unroll
+            for (int v = 0; v < 4; v++) Gs[(row + 4 * v) * NT + 16 * t + col] = (TQ)acc[u][v];
+        }
+    }
+}
+
+template <int ENG> __host__ __device__ inline size_t coef_bytes(int ts, int nd, int nl, size_t e)
+{
+    // VALU: complex [nd][nl][ts]; MFMA: real [nd][ks][64] with ks = ceil(2nl/4)
+    return ENG == ENG_VALU ? (size_t)nd * nl * ts * 2 * e
+                           : (size_t)nd * ((2 * nl + 3) / 4) * 64 * e;
+}
+
+template <typename TQ, int TS, int NT, int ENG, bool DUMP>
 __global__ __launch_bounds__(NT) void k_contract(
     ile_geom g, const double *__restrict__ smp, int64_t N,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ shifts,
-    const typename vec2<TQ>::type *__restrict__ Q,
-    const double2 *__restrict__ U, const double2 *__restrict__ V,
-    double *__restrict__ out, double *__restrict__ series)
+    const TQ *__restrict__ Q, const double2 *__restrict__ U,
+    const double2 *__restrict__ V, double *__restrict__ out,
+    double *__restrict__ series)
 {
-    using T2 = typename vec2<TQ>::type;
+    static_assert(ENG == ENG_VALU || (TS == 16 && NT % 64 == 0), "MFMA tile is 16 samples");
     constexpr int NW = NT / 64;
     __shared__ __align__(16) TQ Gs[TS * NT];
     __shared__ double s_q[TS];
@@ -280,17 +350,18 @@ __global__ __launch_bounds__(NT) void k_contract(
     __shared__ double s_red[NW][TS];
     __shared__ double s_M[TS];
     extern __shared__ __align__(16) unsigned char dyn_lds[];
-    T2 *coefT = reinterpret_cast<T2 *>(dyn_lds);
+    TQ *coef = reinterpret_cast<TQ *>(dyn_lds);
 
     const int tid = threadIdx.x;
     const int nd = g.n_det, nl = g.n_lm, nq = g.n_q;
+    const int R = 2 * nl, KS = (R + 3) / 4;
     const int64_t base = (int64_t)blockIdx.x * TS;
 
     // prologue scratch: inside Gs when it fits, else after the coefficients
     const size_t scr_bytes = prologue_scratch_bytes(TS, nd, nl);
     double *scr = scr_bytes <= sizeof(Gs)
                       ? reinterpret_cast<double *>(Gs)
-                      : reinterpret_cast<double *>(coefT + (size_t)nd * nl * TS);
+                      : reinterpret_cast<double *>(dyn_lds + coef_bytes<ENG>(TS, nd, nl, sizeof(TQ)));
     double *s_th = scr;                                  // [7][TS]
     double2 *s_Y = reinterpret_cast<double2 *>(scr + 7 * TS);   // [TS][nl]
     double2 *s_F = s_Y + TS * nl;                        // [TS][nd]
@@ -340,34 +411,46 @@ __global__ __launch_bounds__(NT) void k_contract(
     }
     __syncthreads();
 
-    // 3. coefficients c = (d_ref/D) F_k Y_lm and rows of the quadratic term
-    for (int t = tid; t < TS * nd * nl; t += NT) {
-        int al = t / (nd * nl), r = t - al * (nd * nl);
-        int k = r / nl, a = r - k * nl;
-        double kap = s_ok[al] ? g.d_ref / s_th[5 * TS + al] : 0.0;
-        double2 F = s_F[al * nd + k];
-        double2 Ya = s_Y[al * nl + a];
-        double fyr = F.x * Ya.x - F.y * Ya.y, fyi = F.x * Ya.y + F.y * Ya.x;
-        T2 c;
-        c.x = (TQ)(kap * fyr);
-        c.y = (TQ)(kap * fyi);
-        coefT[(k * nl + a) * TS + al] = c;
-        // |F|^2 Re(conj(Y_a) (U Y)_a) + Re(F^2 Y_a (V Y)_a)
-        double uyr = 0, uyi = 0, vyr = 0, vyi = 0;
-        const double2 *Ur = U + ((int64_t)k * nl + a) * nl;
-        const double2 *Vr = V + ((int64_t)k * nl + a) * nl;
-        for (int b = 0; b < nl; b++) {
-            double2 Yb = s_Y[al * nl + b], u = Ur[b], v = Vr[b];
-            uyr += u.x * Yb.x - u.y * Yb.y;
-            uyi += u.x * Yb.y + u.y * Yb.x;
-            vyr += v.x * Yb.x - v.y * Yb.y;
-            vyi += v.x * Yb.y + v.y * Yb.x;
+    // 3. coefficients c = (d_ref/D) F_k Y_lm and rows of the quadratic term;
+    //    modes a in [nl, 2 KS) are the zero padding of the MFMA K dimension
+    const int nlp = ENG == ENG_MFMA ? 2 * KS : nl;
+    for (int t = tid; t < TS * nd * nlp; t += NT) {
+        int al = t / (nd * nlp), r = t - al * (nd * nlp);
+        int k = r / nlp, a = r - k * nlp;
+        double cx = 0.0, cy = 0.0, row = 0.0;
+        if (a < nl) {
+            double kap = s_ok[al] ? g.d_ref / s_th[5 * TS + al] : 0.0;
+            double2 F = s_F[al * nd + k];
+            double2 Ya = s_Y[al * nl + a];
+            double fyr = F.x * Ya.x - F.y * Ya.y, fyi = F.x * Ya.y + F.y * Ya.x;
+            cx = kap * fyr;
+            cy = kap * fyi;
+            // |F|^2 Re(conj(Y_a) (U Y)_a) + Re(F^2 Y_a (V Y)_a)
+            double uyr = 0, uyi = 0, vyr = 0, vyi = 0;
+            const double2 *Ur = U + ((int64_t)k * nl + a) * nl;
+            const double2 *Vr = V + ((int64_t)k * nl + a) * nl;
+            for (int b = 0; b < nl; b++) {
+                double2 Yb = s_Y[al * nl + b], u = Ur[b], v = Vr[b];
+                uyr += u.x * Yb.x - u.y * Yb.y;
+                uyi += u.x * Yb.y + u.y * Yb.x;
+                vyr += v.x * Yb.x - v.y * Yb.y;
+                vyi += v.x * Yb.y + v.y * Yb.x;
+            }
+            double f2 = F.x * F.x + F.y * F.y;
+            double F2r = F.x * F.x - F.y * F.y, F2i = 2.0 * F.x * F.y;
+            double yvr = Ya.x * vyr - Ya.y * vyi, yvi = Ya.x * vyi + Ya.y * vyr;
+            row = f2 * (Ya.x * uyr + Ya.y * uyi) + (F2r * yvr - F2i * yvi);
+            s_qp[al * (nd * nl) + k * nl + a] = row;
         }
-        double f2 = F.x * F.x + F.y * F.y;
-        double F2r = F.x * F.x - F.y * F.y, F2i = 2.0 * F.x * F.y;
-        double yvr = Ya.x * vyr - Ya.y * vyi, yvi = Ya.x * vyi + Ya.y * vyr;
-        double row = f2 * (Ya.x * uyr + Ya.y * uyi) + (F2r * yvr - F2i * yvi);
-        s_qp[al * (nd * nl) + r] = row;
+        if (ENG == ENG_VALU) {
+            coef[((k * nl + a) * TS + al) * 2] = (TQ)cx;
+            coef[((k * nl + a) * TS + al) * 2 + 1] = (TQ)cy;
+        } else {
+            // A operand of k-step ks: lane = 16 * (row within the step) + alpha
+            const int r0 = 2 * a;
+            coef[(k * KS + (r0 >> 2)) * 64 + (r0 & 3) * 16 + al] = (TQ)cx;
+            coef[(k * KS + (r0 >> 2)) * 64 + ((r0 & 3) + 1) * 16 + al] = (TQ)cy;
+        }
     }
     __syncthreads();
 
@@ -405,6 +488,7 @@ __global__ __launch_bounds__(NT) void k_contract(
         m[al] = -INFINITY;
         sacc[al] = 0.0;
     }
+    const int lane = tid & 63, wv = tid >> 6;
 
     for (int j0 = 0; j0 < g.n_t; j0 += J) {
         const int Jc = min(J, g.n_t - j0);
@@ -418,30 +502,36 @@ __global__ __launch_bounds__(NT) void k_contract(
         for (int k = 0; k < nd; k++) {
             const int Pk = s_smin[k] + j0;
             const int Wk = Jc + s_spread[k];
-            const T2 *Qk = Q + (int64_t)k * nl * nq + Pk;
-            const T2 *cf = coefT + (k * nl) * TS;
+            const TQ *Qk = Q + (int64_t)k * R * nq;
             for (int blk = 0; blk < Wk; blk += NT) {
-                const int p = blk + tid;
-                TQ acc[TS];
+                if (ENG == ENG_VALU) {
+                    const int p = blk + tid;
+                    TQ acc[TS];
 #pragma unroll
-                for (int al = 0; al < TS; al++) acc[al] = (TQ)0;
-                if (p < Wk) {
-                    const T2 *qp = Qk + p;
-                    T2 qn = qp[0];
-                    for (int a = 0; a < nl; a++) {
-                        const T2 qv = qn;
-                        // next mode's value is in flight during this mode's FMAs
-                        if (a + 1 < nl) qn = qp[(int64_t)(a + 1) * nq];
-                        const T2 *ca = cf + a * TS;
+                    for (int al = 0; al < TS; al++) acc[al] = (TQ)0;
+                    if (p < Wk) {
+                        const TQ *qp = Qk + Pk + p;
+                        const TQ *cf = coef + (size_t)k * nl * TS * 2;
+                        TQ qnr = qp[0], qni = qp[nq];
+                        for (int a = 0; a < nl; a++) {
+                            const TQ qr = qnr, qi = qni;
+                            // next mode's values are in flight during this mode's FMAs
+                            if (a + 1 < nl) {
+                                qnr = qp[(int64_t)(2 * a + 2) * nq];
+                                qni = qp[(int64_t)(2 * a + 3) * nq];
+                            }
+                            const TQ *ca = cf + a * TS * 2;
 #pragma unroll
-                        for (int al = 0; al < TS; al++) {
-                            const T2 c = ca[al];
-                            acc[al] = fma(c.x, qv.x, fma(c.y, qv.y, acc[al]));
+                            for (int al = 0; al < TS; al++)
+                                acc[al] = fma(ca[2 * al], qr, fma(ca[2 * al + 1], qi, acc[al]));
                         }
                     }
-                }
 #pragma unroll
-                for (int al = 0; al < TS; al++) Gs[al * NT + tid] = acc[al];
+                    for (int al = 0; al < TS; al++) Gs[al * NT + tid] = acc[al];
+                } else {
+                    mfma_gphase<TQ, NT>(Gs, coef + (size_t)k * KS * 64, Qk, nq, R, KS,
+                                        Pk + blk, min(Wk - blk, NT), lane, wv);
+                }
                 __syncthreads();
                 if (has) {
 #pragma unroll
@@ -474,7 +564,6 @@ __global__ __launch_bounds__(NT) void k_contract(
     }
 
     // deterministic block reduction: max, then sum of s e^{m - M}
-    const int lane = tid & 63, wv = tid >> 6;
 #pragma unroll
     for (int al = 0; al < TS; al++) {
         double v = m[al];
@@ -712,24 +801,23 @@ __global__ void k_finish(const double *parts, int n_part, double *res)
 
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-template <typename TQ, int TS, int NT>
+template <typename TQ, int TS, int NT, int ENG>
 hipError_t launch_contract_t(const ile_geom &g, const double *smp, int64_t N,
                              const int32_t *perm, const int32_t *shifts,
                              const void *Q, const double *U, const double *V,
                              double *out, double *series, hipStream_t st)
 {
-    using T2 = typename vec2<TQ>::type;
-    size_t dyn = (size_t)g.n_det * g.n_lm * TS * sizeof(T2);
+    size_t dyn = coef_bytes<ENG>(TS, g.n_det, g.n_lm, sizeof(TQ));
     const size_t scr = prologue_scratch_bytes(TS, g.n_det, g.n_lm);
     if (scr > (size_t)TS * NT * sizeof(TQ)) dyn += scr;
     const unsigned grid = nblk(N, TS);
     if (series)
-        hipLaunchKernelGGL((k_contract<TQ, TS, NT, true>), dim3(grid), dim3(NT), dyn, st,
-                           g, smp, N, perm, shifts, (const T2 *)Q,
+        hipLaunchKernelGGL((k_contract<TQ, TS, NT, ENG, true>), dim3(grid), dim3(NT), dyn, st,
+                           g, smp, N, perm, shifts, (const TQ *)Q,
                            (const double2 *)U, (const double2 *)V, out, series);
     else
-        hipLaunchKernelGGL((k_contract<TQ, TS, NT, false>), dim3(grid), dim3(NT), dyn, st,
-                           g, smp, N, perm, shifts, (const T2 *)Q,
+        hipLaunchKernelGGL((k_contract<TQ, TS, NT, ENG, false>), dim3(grid), dim3(NT), dyn, st,
+                           g, smp, N, perm, shifts, (const TQ *)Q,
                            (const double2 *)U, (const double2 *)V, out, series);
     return hipGetLastError();
 }
@@ -787,11 +875,21 @@ hipError_t ile_launch_identity(int32_t *perm, int64_t N, hipStream_t st)
 size_t ile_contract_lds_bytes(const ile_geom &g, ile_precision prec,
                               const ile_tune &tu)
 {
-    size_t e = prec == ILE_FP64 ? 8 : 4;
-    size_t gs = (size_t)tu.tile_samples * tu.threads * e;
-    size_t coef = (size_t)g.n_det * g.n_lm * tu.tile_samples * 2 * e;
-    size_t scr = prologue_scratch_bytes(tu.tile_samples, g.n_det, g.n_lm);
+    const size_t e = prec == ILE_FP64 ? 8 : 4;
+    const size_t gs = (size_t)tu.tile_samples * tu.threads * e;
+    const size_t coef = tu.engine == ENG_MFMA
+                            ? coef_bytes<ENG_MFMA>(tu.tile_samples, g.n_det, g.n_lm, e)
+                            : coef_bytes<ENG_VALU>(tu.tile_samples, g.n_det, g.n_lm, e);
+    const size_t scr = prologue_scratch_bytes(tu.tile_samples, g.n_det, g.n_lm);
     return gs + coef + (scr > gs ? scr : 0) + 4096;
+}
+
+bool ile_tune_supported(ile_precision prec, const ile_tune &tu)
+{
+    if (tu.tile_samples != 16) return false;
+    if (tu.threads != 256 && tu.threads != 512) return false;
+    if (tu.engine == ENG_MFMA) return prec == ILE_FP64;
+    return tu.engine == ENG_VALU && (prec == ILE_FP64 || prec == ILE_FP32);
 }
 
 hipError_t ile_launch_contract(const ile_geom &g, ile_precision prec,
@@ -801,14 +899,20 @@ hipError_t ile_launch_contract(const ile_geom &g, ile_precision prec,
                                double *out, double *series, hipStream_t st)
 {
     if (N <= 0) return hipSuccess;
-    if (tu.tile_samples != 16 || tu.threads != 256) return hipErrorInvalidValue;
-    if (prec == ILE_FP64)
-        return launch_contract_t<double, 16, 256>(g, smp, N, perm, shifts, Q, U, V,
-                                                  out, series, st);
-    if (prec == ILE_FP32)
-        return launch_contract_t<float, 16, 256>(g, smp, N, perm, shifts, Q, U, V,
-                                                 out, series, st);
-    return hipErrorInvalidValue;
+    if (!ile_tune_supported(prec, tu)) return hipErrorInvalidValue;
+#define ILE_CONTRACT(TQ, NT, ENG) \
+    return launch_contract_t<TQ, 16, NT, ENG>(g, smp, N, perm, shifts, Q, U, V, out, series, st)
+    if (prec == ILE_FP64) {
+        if (tu.engine == ENG_MFMA) {
+            if (tu.threads == 512) ILE_CONTRACT(double, 512, ENG_MFMA);
+            ILE_CONTRACT(double, 256, ENG_MFMA);
+        }
+        if (tu.threads == 512) ILE_CONTRACT(double, 512, ENG_VALU);
+        ILE_CONTRACT(double, 256, ENG_VALU);
+    }
+    if (tu.threads == 512) ILE_CONTRACT(float, 512, ENG_VALU);
+    ILE_CONTRACT(float, 256, ENG_VALU);
+#undef ILE_CONTRACT
 }
 
 hipError_t ile_launch_prior(uint64_t seed, int64_t first, int64_t N,

@@ -23,6 +23,8 @@ STATUS_NAMES = ["ILE_OK", "ILE_E_ARG", "ILE_E_STATE", "ILE_E_RANGE",
                 "ILE_E_UNSUPPORTED"]
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
 ILE_OPT_SORT = 0
+ILE_OPT_ENGINE = 1
+ILE_OPT_THREADS = 2
 
 
 class IleError(RuntimeError):
@@ -211,7 +213,8 @@ def ile_destroy(h):
 class Context:
     """One intrinsic point on one GPU: create + set_data, then evaluate."""
 
-    def __init__(self, inst, precision="fp64", device=0, stream=None, sort=True):
+    def __init__(self, inst, precision="fp64", device=0, stream=None, sort=True,
+                 engine=None, threads=None):
         self.inst = inst
         self.n_t = inst.n_t
         self.h = ile_create(inst.dets, inst.modes, inst.srate_hz, inst.n_t,
@@ -223,6 +226,10 @@ class Context:
             ile_set_data(self.h, inst.Q, inst.t0_s, inst.U, inst.V, inst.dets)
             if not sort:
                 ile_set_option(self.h, ILE_OPT_SORT, 0)
+            if engine is not None:
+                ile_set_option(self.h, ILE_OPT_ENGINE, {"valu": 0, "mfma": 1}[engine])
+            if threads is not None:
+                ile_set_option(self.h, ILE_OPT_THREADS, threads)
         except Exception:
             self.close()
             raise

@@ -103,19 +103,26 @@ def test_config1_fp64_all_samples(torch, c1, sort):
     print(f"config1 sort={sort}: max |d lnLmargT| = {err:.3e}")
 
 
-@pytest.mark.parametrize("sort", [True, False])
-def test_config2_shape_fp64(torch, c2_small, sort):
+@pytest.mark.parametrize("sort,engine,threads", [
+    (True, "mfma", 256), (False, "mfma", 256), (True, "mfma", 512), (False, "mfma", 512),
+    (True, "valu", 256), (False, "valu", 512)])
+def test_config2_shape_fp64(torch, c2_small, sort, engine, threads):
     from oracle import oracle as O
     inst, s, lp, want = c2_small
-    with ile.Context(inst, sort=sort) as ctx:
+    with ile.Context(inst, sort=sort, engine=engine, threads=threads) as ctx:
         got = ctx.eval(s)
     err = check_margT(got, want, s, O.Ctx(inst), inst)
-    print(f"config2 shape, 3001 samples, sort={sort}: max err {err:.3e}")
+    print(f"config2 shape, 3001 samples, sort={sort} {engine} {threads}: max err {err:.3e}")
 
 
-def test_sorted_and_unsorted_bit_identical(torch, c2_small):
+@pytest.mark.parametrize("engine,threads", [("mfma", 256), ("mfma", 512), ("valu", 256)])
+def test_sorted_and_unsorted_bit_identical(torch, c2_small, engine, threads):
+    """A sample's result does not depend on which tile it lands in: at a
+    fixed workgroup width the bins a thread owns, and so the order of the
+    log-sum-exp, are fixed; repeated runs are bit-identical too."""
     inst, s, _, _ = c2_small
-    with ile.Context(inst, sort=True) as a, ile.Context(inst, sort=False) as b:
+    with ile.Context(inst, sort=True, engine=engine, threads=threads) as a, \
+            ile.Context(inst, sort=False, engine=engine, threads=threads) as b:
         x, y = a.eval(s), b.eval(s)
         x2 = a.eval(s)
     assert np.array_equal(x, y)
