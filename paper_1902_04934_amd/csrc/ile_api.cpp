@@ -433,27 +433,34 @@ ile_status ile_set_data(ile_ctx *c, const double *Q, int64_t n_q, double t0_s,
 
     ile_status s;
     HIP_TRY(c, hipSetDevice(c->cfg.device));
-    const size_t qe = c->cfg.precision == ILE_FP64 ? 16 : 8;
-    if ((s = ensure(c, c->Q, nQ * qe))) return s;
+    // device layout: planar rows per detector, row 2a = Re Q_a, 2a+1 = Im Q_a,
+    // padded with zero rows to 4 * ksp_of(n_lm) (the matrix-core K steps)
+    const size_t rp = (size_t)4 * ksp_of(nl);
+    const size_t nQd = (size_t)nd * rp * n_q;
+    const size_t qe = c->cfg.precision == ILE_FP64 ? 8 : 4;
+    if ((s = ensure(c, c->Q, nQd * qe))) return s;
     if ((s = ensure(c, c->U, nUV * 16))) return s;
     if ((s = ensure(c, c->V, nUV * 16))) return s;
-    // device layout: planar rows per detector, row 2a = Re Q_a, 2a+1 = Im Q_a
     if (c->cfg.precision == ILE_FP64) {
-        std::vector<double> h(2 * nQ);
-        for (size_t ka = 0; ka < (size_t)nd * nl; ka++)
-            for (int64_t i = 0; i < n_q; i++) {
-                h[(2 * ka) * n_q + i] = Q[2 * (ka * n_q + i)];
-                h[(2 * ka + 1) * n_q + i] = Q[2 * (ka * n_q + i) + 1];
-            }
-        HIP_TRY(c, hipMemcpy(c->Q.p, h.data(), nQ * 16, hipMemcpyHostToDevice));
+        std::vector<double> h(nQd, 0.0);
+        for (int k = 0; k < nd; k++)
+            for (int a = 0; a < nl; a++)
+                for (int64_t i = 0; i < n_q; i++) {
+                    const double *q = Q + 2 * (((size_t)k * nl + a) * n_q + i);
+                    h[((size_t)k * rp + 2 * a) * n_q + i] = q[0];
+                    h[((size_t)k * rp + 2 * a + 1) * n_q + i] = q[1];
+                }
+        HIP_TRY(c, hipMemcpy(c->Q.p, h.data(), nQd * 8, hipMemcpyHostToDevice));
     } else {
-        std::vector<float> h(2 * nQ);
-        for (size_t ka = 0; ka < (size_t)nd * nl; ka++)
-            for (int64_t i = 0; i < n_q; i++) {
-                h[(2 * ka) * n_q + i] = (float)Q[2 * (ka * n_q + i)];
-                h[(2 * ka + 1) * n_q + i] = (float)Q[2 * (ka * n_q + i) + 1];
-            }
-        HIP_TRY(c, hipMemcpy(c->Q.p, h.data(), nQ * 8, hipMemcpyHostToDevice));
+        std::vector<float> h(nQd, 0.0f);
+        for (int k = 0; k < nd; k++)
+            for (int a = 0; a < nl; a++)
+                for (int64_t i = 0; i < n_q; i++) {
+                    const double *q = Q + 2 * (((size_t)k * nl + a) * n_q + i);
+                    h[((size_t)k * rp + 2 * a) * n_q + i] = (float)q[0];
+                    h[((size_t)k * rp + 2 * a + 1) * n_q + i] = (float)q[1];
+                }
+        HIP_TRY(c, hipMemcpy(c->Q.p, h.data(), nQd * 4, hipMemcpyHostToDevice));
     }
     HIP_TRY(c, hipMemcpy(c->U.p, U, nUV * 16, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->V.p, V, nUV * 16, hipMemcpyHostToDevice));

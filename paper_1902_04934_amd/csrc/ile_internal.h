@@ -36,6 +36,11 @@ struct ile_geom {
     signed char term_ps[ILE_MAX_TERMS];
 };
 
+// K steps of the matrix-core contraction (4 real rows = 2 modes each),
+// rounded up to a multiple of 3; the device Q holds 4 * ksp_of(n_lm) rows
+// per detector (rows 2a and 2a+1 = Re, Im of mode a, the rest zero).
+__host__ __device__ inline int ksp_of(int n_lm) { return 3 * (((2 * n_lm + 3) / 4 + 2) / 3); }
+
 // Tuning of the contraction kernel.
 struct ile_tune {
     int tile_samples;   // samples per workgroup tile (16)

@@ -274,61 +274,96 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // G block on the matrix cores: Gs[alpha][p] = sum_r A[alpha][r] Qm[r][P0 + p]
 // for p < W (<= NT), 16 samples.  v_mfma_f64_16x16x4 on gfx950 (checked
 // with a lane-layout probe): lane l supplies A[l%16][l/16] and B[l/16][l%16]
-// and receives D[l/16 + 4v][l%16], v = 0..3.
-// Wave wv computes the N-tiles wv, wv+NW, ... of 16 positions; rows r >= R
-// of the padded K dimension are zero in A and read as zero from Q; columns
-// past the end of Q are clamped (their results are never read).
+// and receives D[l/16 + 4v][l%16], v = 0..3.  Wave wv computes the N-tiles
+// wv, wv+NW, ... (NU of them, wave-uniform) of 16 positions.  Q rows are
+// padded with zeros to 4 KSP in memory (KSP = k-steps rounded up to a
+// multiple of 3), so every lane loads a valid row; columns past the end of
+// Q are clamped (their results are never read).
+template <typename TQ, int NT, int NU>
+__device__ inline void mfma_tiles(TQ *Gs, const TQ *coefA, const TQ *Qk, int nq,
+                                  int KSP, int P0, int lane, int wv)
+{
+    constexpr int NW = NT / 64;
+    const int row = lane >> 4, col = lane & 15;
+    v4d acc[NU];
+    const TQ *qb[NU];
+#pragma unroll
+    for (int u = 0; u < NU; u++) {
+        acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+        qb[u] = Qk + (int64_t)row * nq + min(P0 + 16 * (wv + NW * u) + col, nq - 1);
+    }
+    const int64_t step = 4 * (int64_t)nq;
+    // KSP is a multiple of 3 (zero-padded coefficients and Q rows): three
+    // operand buffers, each reloaded right after its MFMAs consumed it, so
+    // every load is in flight for two k-steps and the loop body has no
+    // branches (prefetch indices past the end are clamped and unused)
+    double a0 = coefA[lane], a1 = coefA[64 + lane], a2, b0[NU], b1[NU], b2[NU];
+#pragma unroll
+    for (int u = 0; u < NU; u++) {
+        b0[u] = (double)qb[u][0];
+        b1[u] = (double)qb[u][step];
+    }
+    // sched_barrier(0) keeps the compiler from folding the prefetch back
+    // next to its use
+    for (int ks = 0; ks < KSP; ks += 3) {
+        const int k3 = min(ks + 3, KSP - 1), k4 = min(ks + 4, KSP - 1);
+        a2 = coefA[(ks + 2) * 64 + lane];
+#pragma unroll
+        for (int u = 0; u < NU; u++) b2[u] = (double)qb[u][(ks + 2) * step];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < NU; u++)
+            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0[u], acc[u], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        a0 = coefA[k3 * 64 + lane];
+#pragma unroll
+        for (int u = 0; u < NU; u++) b0[u] = (double)qb[u][k3 * step];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < NU; u++)
+            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1[u], acc[u], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        a1 = coefA[k4 * 64 + lane];
+#pragma unroll
+        for (int u = 0; u < NU; u++) b1[u] = (double)qb[u][k4 * step];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < NU; u++)
+            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b2[u], acc[u], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int u = 0; u < NU; u++) {
+        const int t = wv + NW * u;
+#pragma unroll
+        for (int v = 0; v < 4; v++) Gs[(row + 4 * v) * NT + 16 * t + col] = (TQ)acc[u][v];
+    }
+}
+
 template <typename TQ, int NT>
 __device__ inline void mfma_gphase(TQ *Gs, const TQ *coefA, const TQ *Qk, int nq,
-                                   int R, int KS, int P0, int W, int lane, int wv)
+                                   int KSP, int P0, int W, int lane)
 {
     constexpr int NW = NT / 64, TPW = NT / 16 / NW;
+    static_assert(TPW == 4, "four N-tiles per wave");
+    // wave index in an SGPR so the tile count below is known to be uniform
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ntile = (W + 15) >> 4;
-    const int row = lane >> 4, col = lane & 15;
-    v4d acc[TPW];
-    int pos[TPW];
-#pragma unroll
-    for (int u = 0; u < TPW; u++) {
-        acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
-        pos[u] = min(P0 + 16 * (wv + NW * u) + col, nq - 1);
-    }
-    double a_cur = coefA[lane], b_cur[TPW];
-#pragma unroll
-    for (int u = 0; u < TPW; u++) b_cur[u] = row < R ? (double)Qk[(int64_t)row * nq + pos[u]] : 0.0;
-    for (int ks = 0; ks < KS; ks++) {
-        double a_nxt = 0.0, b_nxt[TPW];
-        const int rn = 4 * (ks + 1) + row;
-#pragma unroll
-        for (int u = 0; u < TPW; u++) b_nxt[u] = 0.0;
-        if (ks + 1 < KS) {
-            a_nxt = coefA[(ks + 1) * 64 + lane];
-#pragma unroll
-            for (int u = 0; u < TPW; u++)
-                if (rn < R) b_nxt[u] = (double)Qk[(int64_t)rn * nq + pos[u]];
-        }
-#pragma unroll
-        for (int u = 0; u < TPW; u++)
-            if (wv + NW * u < ntile)
-                acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur, b_cur[u], acc[u], 0, 0, 0);
-        a_cur = a_nxt;
-#pragma unroll
-        for (int u = 0; u < TPW; u++) b_cur[u] = b_nxt[u];
-    }
-#pragma unroll
-    for (int u = 0; u < TPW; u++) {
-        const int t = wv + NW * u;
-        if (t < ntile) {
-#pragma unroll
-            for (int v = 0; v < 4; v++) Gs[(row + 4 * v) * NT + 16 * t + col] = (TQ)acc[u][v];
-        }
+    int nu = ntile > wv ? (ntile - wv + NW - 1) / NW : 0;
+    nu = __builtin_amdgcn_readfirstlane(nu < TPW ? nu : TPW);
+    switch (nu) {
+    case 4: mfma_tiles<TQ, NT, 4>(Gs, coefA, Qk, nq, KSP, P0, lane, wv); break;
+    case 3: mfma_tiles<TQ, NT, 3>(Gs, coefA, Qk, nq, KSP, P0, lane, wv); break;
+    case 2: mfma_tiles<TQ, NT, 2>(Gs, coefA, Qk, nq, KSP, P0, lane, wv); break;
+    case 1: mfma_tiles<TQ, NT, 1>(Gs, coefA, Qk, nq, KSP, P0, lane, wv); break;
+    default: break;
     }
 }
 
 template <int ENG> __host__ __device__ inline size_t coef_bytes(int ts, int nd, int nl, size_t e)
 {
-    // VALU: complex [nd][nl][ts]; MFMA: real [nd][ks][64] with ks = ceil(2nl/4)
-    return ENG == ENG_VALU ? (size_t)nd * nl * ts * 2 * e
-                           : (size_t)nd * ((2 * nl + 3) / 4) * 64 * e;
+    // VALU: complex [nd][nl][ts]; MFMA: real [nd][KSP][64]
+    return ENG == ENG_VALU ? (size_t)nd * nl * ts * 2 * e : (size_t)nd * ksp_of(nl) * 64 * e;
 }
 
 template <typename TQ, int TS, int NT, int ENG, bool DUMP>
@@ -354,7 +389,7 @@ __global__ __launch_bounds__(NT) void k_contract(
 
     const int tid = threadIdx.x;
     const int nd = g.n_det, nl = g.n_lm, nq = g.n_q;
-    const int R = 2 * nl, KS = (R + 3) / 4;
+    const int KSP = ksp_of(nl), RP = 4 * KSP;   // k-steps and Q rows per detector (padded)
     const int64_t base = (int64_t)blockIdx.x * TS;
 
     // prologue scratch: inside Gs when it fits, else after the coefficients
@@ -413,7 +448,7 @@ __global__ __launch_bounds__(NT) void k_contract(
 
     // 3. coefficients c = (d_ref/D) F_k Y_lm and rows of the quadratic term;
     //    modes a in [nl, 2 KS) are the zero padding of the MFMA K dimension
-    const int nlp = ENG == ENG_MFMA ? 2 * KS : nl;
+    const int nlp = ENG == ENG_MFMA ? 2 * KSP : nl;
     for (int t = tid; t < TS * nd * nlp; t += NT) {
         int al = t / (nd * nlp), r = t - al * (nd * nlp);
         int k = r / nlp, a = r - k * nlp;
@@ -448,8 +483,8 @@ __global__ __launch_bounds__(NT) void k_contract(
         } else {
             // A operand of k-step ks: lane = 16 * (row within the step) + alpha
             const int r0 = 2 * a;
-            coef[(k * KS + (r0 >> 2)) * 64 + (r0 & 3) * 16 + al] = (TQ)cx;
-            coef[(k * KS + (r0 >> 2)) * 64 + ((r0 & 3) + 1) * 16 + al] = (TQ)cy;
+            coef[(k * KSP + (r0 >> 2)) * 64 + (r0 & 3) * 16 + al] = (TQ)cx;
+            coef[(k * KSP + (r0 >> 2)) * 64 + ((r0 & 3) + 1) * 16 + al] = (TQ)cy;
         }
     }
     __syncthreads();
@@ -502,7 +537,7 @@ __global__ __launch_bounds__(NT) void k_contract(
         for (int k = 0; k < nd; k++) {
             const int Pk = s_smin[k] + j0;
             const int Wk = Jc + s_spread[k];
-            const TQ *Qk = Q + (int64_t)k * R * nq;
+            const TQ *Qk = Q + (int64_t)k * RP * nq;
             for (int blk = 0; blk < Wk; blk += NT) {
                 if (ENG == ENG_VALU) {
                     const int p = blk + tid;
@@ -529,15 +564,17 @@ __global__ __launch_bounds__(NT) void k_contract(
 #pragma unroll
                     for (int al = 0; al < TS; al++) Gs[al * NT + tid] = acc[al];
                 } else {
-                    mfma_gphase<TQ, NT>(Gs, coef + (size_t)k * KS * 64, Qk, nq, R, KS,
-                                        Pk + blk, min(Wk - blk, NT), lane, wv);
+                    mfma_gphase<TQ, NT>(Gs, coef + (size_t)k * KSP * 64, Qk, nq, KSP,
+                                        Pk + blk, min(Wk - blk, NT), lane);
                 }
                 __syncthreads();
                 if (has) {
 #pragma unroll
                     for (int al = 0; al < TS; al++) {
                         const int ix = s_d[k][al] + jrel - blk;
-                        if ((unsigned)ix < (unsigned)NT) L[al] += Gs[al * NT + ix];
+                        const bool in = (unsigned)ix < (unsigned)NT;
+                        const TQ v = Gs[al * NT + (in ? ix : 0)];
+                        L[al] += in ? v : (TQ)0;
                     }
                 }
                 __syncthreads();
@@ -546,19 +583,20 @@ __global__ __launch_bounds__(NT) void k_contract(
 
         if (has) {
             const int j = j0 + jrel;
+            if (DUMP) {
+                for (int al = 0; al < TS; al++)
+                    if (s_ok[al]) series[(int64_t)s_idx[al] * g.n_t + j] = (double)L[al] - s_q[al];
+            }
+            // online log-sum-exp of the contraction alone: q_alpha is constant
+            // over bins and is subtracted at the end; one exp per bin
 #pragma unroll
             for (int al = 0; al < TS; al++) {
-                if (!s_ok[al]) continue;
-                const double x = (double)L[al] - s_q[al];
-                if (DUMP) series[(int64_t)s_idx[al] * g.n_t + j] = x;
-                // online log-sum-exp; one exp per bin
-                const double e = exp(-fabs(x - m[al]));
-                if (x > m[al]) {
-                    sacc[al] = sacc[al] * e + 1.0;
-                    m[al] = x;
-                } else {
-                    sacc[al] += e;
-                }
+                const double x = (double)L[al];
+                const double d = x - m[al];
+                const double e = exp(-fabs(d));
+                const bool gt = d > 0.0;
+                sacc[al] = gt ? fma(sacc[al], e, 1.0) : sacc[al] + e;
+                m[al] = gt ? x : m[al];
             }
         }
     }
@@ -588,7 +626,7 @@ __global__ __launch_bounds__(NT) void k_contract(
     if (tid < TS && s_idx[tid] >= 0) {
         double S = s_red[0][tid];
         for (int w = 1; w < NW; w++) S += s_red[w][tid];
-        out[s_idx[tid]] = s_ok[tid] ? s_M[tid] + log(S) - log((double)g.n_t) : NAN;
+        out[s_idx[tid]] = s_ok[tid] ? (s_M[tid] - s_q[tid]) + log(S) - log((double)g.n_t) : NAN;
     }
 }
 
