@@ -174,6 +174,77 @@ ile_status ile_run_prior(ile_ctx *ctx, uint64_t seed, int64_t N,
                          int64_t chunk, double d_min, double d_max,
                          ile_result *out);
 
+/* ----------------------------------------------------------- samplers
+ * The Monte Carlo over extrinsic parameters (Sec. II.A: direct Monte Carlo
+ * with an adaptive sampling prior; Sec. III.B: the sampling prior is
+ * regenerated from the most recent chunk of points, in two sky parameters).
+ *
+ * Plain adaptive sampler: the proposal is a product of two n_bins-bin
+ * histogram densities, in ra on [0, 2 pi) and in sin(dec) on [-1, 1], times
+ * the prior in the other five parameters.  Draws use the Philox stream of
+ * ile_draw_prior_dev (same counters and uniforms); ra and sin(dec) go
+ * through the inverse CDF of the histograms (bin b = last with C[b] <= u,
+ * C the running sum of P in bin order; position (u - C[b]) / P[b]).
+ * ln q = ln p + ln(n_bins P_ra[b_ra]) + ln(n_bins P_sd[b_sd]).
+ * A refit from a chunk tempers its weights, w = exp(beta (ln w - max)) with
+ * beta = min(1, temper / (max ln w - mean ln w)), sums them per bin, and
+ * mixes with the prior: P = (1 - floor) H / sum H + floor / n_bins.  Every
+ * sum runs in a fixed order (bit-reproducible).  The context holds the
+ * current histograms (initially uniform = the prior). */
+#define ILE_MAX_BINS 64
+
+typedef enum {
+    ILE_SAMPLER_PRIOR = 0,     /* proposal = prior (ln p - ln q = 0)        */
+    ILE_SAMPLER_ADAPTIVE = 1,  /* histogram proposal, refit per chunk       */
+    ILE_SAMPLER_LEARNED = 2    /* reserved: learned proposal                */
+} ile_sampler;
+
+typedef struct {
+    ile_sampler sampler;
+    uint64_t seed;           /* Philox key; sample i of the run uses counter i */
+    int64_t chunk;           /* samples per chunk (<= 0: 100000)             */
+    int64_t max_samples;     /* hard stop (> 0)                              */
+    double n_eff_target;     /* stop once n_eff >= target (<= 0: never)      */
+    double d_min_mpc, d_max_mpc;  /* distance prior support                  */
+    int32_t n_bins;          /* bins per adapted parameter (<= 0: 50)        */
+    double floor;            /* prior weight in each refit (< 0: 0.1)        */
+    double temper;           /* tempering scale (<= 0: 10)                   */
+    int32_t adapt_chunks;    /* refit after at most this many chunks; < 0:
+                                until ln L_marg > max(10, max lnLmargT / 2) */
+    int32_t reset;           /* 1: start from uniform histograms; 0: keep the
+                                context's current ones (warm start)          */
+} ile_run_opts;
+
+/* Monte Carlo estimate of ln L_marg: chunk after chunk, draw on the device,
+ * evaluate, accumulate the mergeable partials (M, S1, S2, n); refit the
+ * adaptive proposal after each of the first chunks; stop at n_eff_target
+ * or max_samples.  Each chunk's weights use the proposal it was drawn from,
+ * so the combined estimate is unbiased.  n_chunks_out may be NULL. */
+ile_status ile_run(ile_ctx *ctx, const ile_run_opts *opts, ile_result *out,
+                   int64_t *n_chunks_out);
+
+/* Copy the context's histograms out / in (host arrays of n_bins doubles;
+ * ile_hist_set normalizes nothing: P must be positive and sum to 1). */
+ile_status ile_hist_get(ile_ctx *ctx, int32_t n_bins, double *P_ra, double *P_sd);
+ile_status ile_hist_set(ile_ctx *ctx, int32_t n_bins, const double *P_ra,
+                        const double *P_sd);
+
+/* Device draw from the context's histograms: samples_dev[7][ld], ln_p_dev,
+ * ln_q_dev [N] (either may be NULL), bins_dev int32 [2][ld] (ra bin, sin
+ * dec bin; may be NULL). */
+ile_status ile_hist_draw_dev(ile_ctx *ctx, uint64_t seed, int64_t first, int64_t N,
+                             double d_min, double d_max, double *samples_dev,
+                             int64_t ld, double *ln_p_dev, double *ln_q_dev,
+                             int32_t *bins_dev);
+
+/* Device refit of the context's histograms from N samples given by their
+ * bins (int32 [2][ld]) and log-weights lnLmargT + ln p - ln q (ln_p_dev and
+ * ln_q_dev may be NULL = 0). */
+ile_status ile_hist_refit_dev(ile_ctx *ctx, const int32_t *bins_dev, int64_t ld,
+                              const double *lnL_dev, const double *ln_p_dev,
+                              const double *ln_q_dev, int64_t N, double floor,
+                              double temper);
+
 /* Wait for the context's stream; report a sticky device-side error. */
 ile_status ile_sync(ile_ctx *ctx);
 

@@ -392,3 +392,120 @@ void orc_prior_draw(uint64_t seed, int64_t first, int64_t n, double d_min,
         }
     }
 }
+
+/* ------------------------------------------------- plain adaptive sampler
+ * Sec. II.A cites an adaptive Monte Carlo and Sec. III.B says the sampling
+ * prior is regenerated from the most recent chunk of points, in two sky
+ * parameters; the paper gives no further detail.  Reading: the proposal is
+ * a product of two nb-bin histogram densities, in ra on [0, 2 pi) and in
+ * sin(dec) on [-1, 1], times the prior in the other five parameters.
+ * Draws use the same counter-based uniforms as orc_prior_draw; ra and
+ * sin(dec) go through the inverse CDF of the piecewise-constant density:
+ * bin b is the last with C[b] <= u (C the running sum of P in bin order),
+ * and the position inside it is (u - C[b]) / P[b]. */
+static int orc_hist_invert(const double *P, const double *C, int nb, double u,
+                           double *frac)
+{
+    int lo = 0, hi = nb - 1;     /* last b with C[b] <= u */
+    while (lo < hi) {
+        int mid = (lo + hi + 1) / 2;
+        if (C[mid] <= u)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    double f = (u - C[lo]) / P[lo];
+    *frac = f < 1.0 ? f : 1.0;
+    return lo;
+}
+
+void orc_hist_cdf(const double *P, int nb, double *C)
+{
+    C[0] = 0.0;
+    for (int b = 0; b < nb; b++) C[b + 1] = C[b] + P[b];
+}
+
+void orc_hist_draw(uint64_t seed, int64_t first, int64_t n, int nb,
+                   const double *P_ra, const double *P_sd, double d_min,
+                   double d_max, double t_ref_max, double *samples, int64_t ld,
+                   double *ln_p, double *ln_q, int32_t *bins)
+{
+    double *C_ra = (double *)malloc(sizeof(double) * (nb + 1));
+    double *C_sd = (double *)malloc(sizeof(double) * (nb + 1));
+    orc_hist_cdf(P_ra, nb, C_ra);
+    orc_hist_cdf(P_sd, nb, C_sd);
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    double v3 = d_max * d_max * d_max - d_min * d_min * d_min;
+    for (int64_t t = 0; t < n; t++) {
+        uint64_t i = (uint64_t)(first + t);
+        uint32_t w[16];
+        for (uint32_t b = 0; b < 4; b++) {
+            uint32_t ctr[4] = {(uint32_t)i, (uint32_t)(i >> 32), b, 0x494C4531u};
+            orc_philox4x32_10(ctr, key, &w[4 * b]);
+        }
+        double u[7];
+        for (int p = 0; p < 7; p++) u[p] = orc_u53(w[2 * p], w[2 * p + 1]);
+        double fr, fs;
+        int br = orc_hist_invert(P_ra, C_ra, nb, u[0], &fr);
+        int bs = orc_hist_invert(P_sd, C_sd, nb, u[1], &fs);
+        double ra = ((double)br + fr) * (2.0 * ORC_PI / nb);
+        double sd = -1.0 + ((double)bs + fs) * (2.0 / nb);
+        double dec = asin(sd);
+        double psi = ORC_PI * u[2];
+        double phi = 2.0 * ORC_PI * u[3];
+        double ci = 2.0 * u[4] - 1.0;
+        double D = cbrt(d_min * d_min * d_min + u[5] * v3);
+        double tr = t_ref_max * (2.0 * u[6] - 1.0);
+        samples[0 * ld + t] = ra;
+        samples[1 * ld + t] = dec;
+        samples[2 * ld + t] = psi;
+        samples[3 * ld + t] = phi;
+        samples[4 * ld + t] = ci;
+        samples[5 * ld + t] = D;
+        samples[6 * ld + t] = tr;
+        double lp = -log(2.0 * ORC_PI) + log(cos(dec) / 2.0) - log(ORC_PI) -
+                    log(2.0 * ORC_PI) - log(2.0) + log(3.0 * D * D / v3) -
+                    log(2.0 * t_ref_max);
+        /* q / p = (nb P_ra[br]) (nb P_sd[bs]) */
+        double lq = lp + log(nb * P_ra[br]) + log(nb * P_sd[bs]);
+        if (ln_p) ln_p[t] = lp;
+        if (ln_q) ln_q[t] = lq;
+        if (bins) {
+            bins[t] = br;
+            bins[ld + t] = bs;
+        }
+    }
+    free(C_ra);
+    free(C_sd);
+}
+
+/* Refit from the latest chunk: tempered weights w = exp(beta (ln w - max)),
+ * beta = min(1, scale / (max - mean)) (the paper is silent on tempering;
+ * this keeps a single sample from collapsing the proposal), bin sums in
+ * sample order, then a mixture with the prior: P = (1 - floor) H / sum H +
+ * floor / nb. */
+void orc_hist_refit(const int32_t *bins, int64_t ld, const double *lnw,
+                    int64_t n, int nb, double floor_w, double scale,
+                    double *P_ra, double *P_sd)
+{
+    double M = -INFINITY, sum = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+        if (lnw[i] > M) M = lnw[i];
+        sum += lnw[i];
+    }
+    double mean = sum / (double)n;
+    double beta = (M - mean) > scale ? scale / (M - mean) : 1.0;
+    long double *H = (long double *)calloc(2 * nb, sizeof(long double));
+    long double tot = 0.0L;
+    for (int64_t i = 0; i < n; i++) {
+        double w = exp(beta * (lnw[i] - M));
+        H[bins[i]] += w;
+        H[nb + bins[ld + i]] += w;
+        tot += w;
+    }
+    for (int b = 0; b < nb; b++) {
+        P_ra[b] = (double)((1.0L - floor_w) * H[b] / tot) + floor_w / nb;
+        P_sd[b] = (double)((1.0L - floor_w) * H[nb + b] / tot) + floor_w / nb;
+    }
+    free(H);
+}

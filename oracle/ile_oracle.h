@@ -117,6 +117,16 @@ void orc_prior_draw(uint64_t seed, int64_t first, int64_t n, double d_min,
                     double d_max, double t_ref_max, double *samples,
                     int64_t ld, double *ln_p);
 
+/* Plain adaptive sampler: histogram proposal in ra and sin(dec). */
+void orc_hist_cdf(const double *P, int nb, double *C);
+void orc_hist_draw(uint64_t seed, int64_t first, int64_t n, int nb,
+                   const double *P_ra, const double *P_sd, double d_min,
+                   double d_max, double t_ref_max, double *samples, int64_t ld,
+                   double *ln_p, double *ln_q, int32_t *bins);
+void orc_hist_refit(const int32_t *bins, int64_t ld, const double *lnw,
+                    int64_t n, int nb, double floor_w, double scale,
+                    double *P_ra, double *P_sd);
+
 #ifdef __cplusplus
 }
 #endif

@@ -175,6 +175,35 @@ def prior_draw(seed, first, n, d_min=10.0, d_max=1000.0, t_ref_max=0.01):
     return s, lp
 
 
+def hist_draw(seed, first, n, P_ra, P_sd, d_min=10.0, d_max=1000.0, t_ref_max=0.01):
+    """Draws from the histogram proposal (ra, sin dec) x prior; returns
+    samples [7][n], ln p, ln q and the bins [2][n]."""
+    P_ra = np.ascontiguousarray(P_ra, np.float64)
+    P_sd = np.ascontiguousarray(P_sd, np.float64)
+    nb = P_ra.size
+    s = np.zeros((7, n))
+    lp = np.zeros(n)
+    lq = np.zeros(n)
+    bins = np.zeros((2, n), np.int32)
+    lib().orc_hist_draw(C.c_uint64(seed), C.c_int64(first), C.c_int64(n), int(nb),
+                        _p(P_ra), _p(P_sd), C.c_double(d_min), C.c_double(d_max),
+                        C.c_double(t_ref_max), _p(s), C.c_int64(n), _p(lp), _p(lq),
+                        bins.ctypes.data_as(C.POINTER(C.c_int32)))
+    return s, lp, lq, bins
+
+
+def hist_refit(bins, lnw, nb, floor=0.1, scale=10.0):
+    bins = np.ascontiguousarray(bins, np.int32)
+    lnw = np.ascontiguousarray(lnw, np.float64)
+    n = lnw.size
+    P_ra = np.zeros(nb)
+    P_sd = np.zeros(nb)
+    lib().orc_hist_refit(bins.ctypes.data_as(C.POINTER(C.c_int32)), C.c_int64(n),
+                         _p(lnw), C.c_int64(n), int(nb), C.c_double(floor),
+                         C.c_double(scale), _p(P_ra), _p(P_sd))
+    return P_ra, P_sd
+
+
 # ------------------------------------------------- injection (pins only)
 def mode_factors(inst, theta):
     """(F_k = F+ + i Fx per detector, -2Y_lm(iota, phi) per mode)."""

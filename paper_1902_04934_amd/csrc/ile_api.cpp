@@ -42,6 +42,8 @@ struct ile_ctx {
     DevBuf Q, U, V;
     DevBuf smp, out, lnp, lnq, shifts, keys, perm, hist, scan_tmp, errflag,
         red_tmp, parts, res, series;
+    DevBuf hP, hC, bins, hist_tmp;  // adaptive proposal state and scratch
+    int hist_nb = 0;
     std::vector<hipEvent_t> ev;   // pairs around contraction launches
     int n_ev_used = 0;
     double last_ms = 0.0;
@@ -631,6 +633,183 @@ ile_status ile_run_prior(ile_ctx *c, uint64_t seed, int64_t N, int64_t chunk,
     return ILE_OK;
 }
 
+static ile_status hist_init(ile_ctx *c, int nb, bool reset)
+{
+    if (nb < 2 || nb > ILE_MAX_BINS || nb > ile_hist_max_bins())
+        return fail(c, ILE_E_ARG, "n_bins = %d outside [2, %d]", nb, ILE_MAX_BINS);
+    ile_status s;
+    if ((s = ensure(c, c->hP, 2 * (size_t)ILE_MAX_BINS * sizeof(double)))) return s;
+    if ((s = ensure(c, c->hC, 2 * (size_t)(ILE_MAX_BINS + 1) * sizeof(double)))) return s;
+    if (reset || c->hist_nb != nb) {
+        HIP_TRY(c, ile_launch_hist_uniform(nb, (double *)c->hP.p, (double *)c->hC.p, c->stream));
+        c->hist_nb = nb;
+    }
+    return ILE_OK;
+}
+
+ile_status ile_hist_get(ile_ctx *c, int32_t nb, double *P_ra, double *P_sd)
+{
+    if (!c) return ILE_E_ARG;
+    begin_call(c);
+    if (!P_ra || !P_sd) return fail(c, ILE_E_ARG, "null pointer");
+    HIP_TRY(c, hipSetDevice(c->cfg.device));
+    ile_status s = hist_init(c, nb, false);
+    if (s) return s;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(P_ra, c->hP.p, nb * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(P_sd, (double *)c->hP.p + nb, nb * sizeof(double),
+                         hipMemcpyDeviceToHost));
+    return ILE_OK;
+}
+
+ile_status ile_hist_set(ile_ctx *c, int32_t nb, const double *P_ra, const double *P_sd)
+{
+    if (!c) return ILE_E_ARG;
+    begin_call(c);
+    if (!P_ra || !P_sd) return fail(c, ILE_E_ARG, "null pointer");
+    double sr = 0, ss = 0;
+    for (int b = 0; b < nb; b++) {
+        if (!(P_ra[b] > 0) || !(P_sd[b] > 0) || !std::isfinite(P_ra[b]) ||
+            !std::isfinite(P_sd[b]))
+            return fail(c, ILE_E_ARG, "histogram bin %d not positive and finite", b);
+        sr += P_ra[b];
+        ss += P_sd[b];
+    }
+    if (std::fabs(sr - 1) > 1e-9 || std::fabs(ss - 1) > 1e-9)
+        return fail(c, ILE_E_ARG, "histograms must sum to 1");
+    HIP_TRY(c, hipSetDevice(c->cfg.device));
+    ile_status s = hist_init(c, nb, true);
+    if (s) return s;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(c->hP.p, P_ra, nb * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy((double *)c->hP.p + nb, P_sd, nb * sizeof(double),
+                         hipMemcpyHostToDevice));
+    // the cumulative sums follow the bins' order
+    HIP_TRY(c, ile_launch_hist_cdf(nb, (const double *)c->hP.p, (double *)c->hC.p,
+                                   c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return ILE_OK;
+}
+
+ile_status ile_hist_draw_dev(ile_ctx *c, uint64_t seed, int64_t first, int64_t N,
+                             double d_min, double d_max, double *smp, int64_t ld,
+                             double *lp, double *lq, int32_t *bins)
+{
+    if (!c) return ILE_E_ARG;
+    begin_call(c);
+    if (N < 0 || first < 0 || (N > 0 && !smp) || ld < N || !(d_min > 0) ||
+        !(d_max > d_min) || !std::isfinite(d_max))
+        return fail(c, ILE_E_ARG, "bad draw arguments");
+    HIP_TRY(c, hipSetDevice(c->cfg.device));
+    ile_status s = hist_init(c, c->hist_nb ? c->hist_nb : 50, false);
+    if (s) return s;
+    HIP_TRY(c, ile_launch_hist_draw(seed, first, N, c->hist_nb, (const double *)c->hP.p,
+                                    (const double *)c->hC.p, d_min, d_max,
+                                    c->cfg.t_ref_max_s, smp, ld, lp, lq, bins, c->stream));
+    return ILE_OK;
+}
+
+static ile_status refit_impl(ile_ctx *c, const int32_t *bins, int64_t ld, const double *lnL,
+                             const double *lp, const double *lq, int64_t N, double floor_w,
+                             double temper)
+{
+    ile_status s;
+    if ((s = ensure(c, c->hist_tmp, ile_hist_refit_tmp_doubles(N, c->hist_nb) * sizeof(double))))
+        return s;
+    HIP_TRY(c, ile_launch_hist_refit(bins, ld, lnL, lp, lq, N, c->hist_nb, floor_w, temper,
+                                     (double *)c->hist_tmp.p, (double *)c->hP.p,
+                                     (double *)c->hC.p, c->stream));
+    return ILE_OK;
+}
+
+ile_status ile_hist_refit_dev(ile_ctx *c, const int32_t *bins, int64_t ld, const double *lnL,
+                              const double *lp, const double *lq, int64_t N, double floor_w,
+                              double temper)
+{
+    if (!c) return ILE_E_ARG;
+    begin_call(c);
+    if (N <= 0 || !bins || !lnL || ld < N || !(floor_w >= 0 && floor_w <= 1) || !(temper > 0))
+        return fail(c, ILE_E_ARG, "bad refit arguments");
+    HIP_TRY(c, hipSetDevice(c->cfg.device));
+    ile_status s = hist_init(c, c->hist_nb ? c->hist_nb : 50, false);
+    if (s) return s;
+    return refit_impl(c, bins, ld, lnL, lp, lq, N, floor_w, temper);
+}
+
+ile_status ile_run(ile_ctx *c, const ile_run_opts *o, ile_result *out, int64_t *n_chunks_out)
+{
+    ile_status s = check_ready(c);
+    if (s) return s;
+    if (!o || !out) return fail(c, ILE_E_ARG, "null pointer");
+    if (o->sampler == ILE_SAMPLER_LEARNED)
+        return fail(c, ILE_E_UNSUPPORTED, "learned proposal not available in ile_run");
+    if (o->sampler != ILE_SAMPLER_PRIOR && o->sampler != ILE_SAMPLER_ADAPTIVE)
+        return fail(c, ILE_E_ARG, "unknown sampler");
+    if (o->max_samples <= 0 || !(o->d_min_mpc > 0) || !(o->d_max_mpc > o->d_min_mpc) ||
+        !std::isfinite(o->d_max_mpc))
+        return fail(c, ILE_E_ARG, "bad run options");
+    const int64_t chunk = std::min<int64_t>(o->chunk > 0 ? o->chunk : 100000, o->max_samples);
+    const int nb = o->n_bins > 0 ? o->n_bins : 50;
+    const double floor_w = o->floor >= 0 ? o->floor : 0.1;
+    const double temper = o->temper > 0 ? o->temper : 10.0;
+    if (floor_w > 1) return fail(c, ILE_E_ARG, "floor > 1");
+    const bool adaptive = o->sampler == ILE_SAMPLER_ADAPTIVE;
+    const int64_t max_chunks = (o->max_samples + chunk - 1) / chunk;
+    if (max_chunks > (1 << 22)) return fail(c, ILE_E_ARG, "too many chunks");
+    if (adaptive && (s = hist_init(c, nb, o->reset != 0))) return s;
+    if ((s = ensure(c, c->smp, (size_t)chunk * 7 * sizeof(double)))) return s;
+    if ((s = ensure(c, c->out, (size_t)chunk * sizeof(double)))) return s;
+    if ((s = ensure(c, c->lnp, (size_t)chunk * sizeof(double)))) return s;
+    if ((s = ensure(c, c->lnq, (size_t)chunk * sizeof(double)))) return s;
+    if ((s = ensure(c, c->bins, (size_t)chunk * 2 * sizeof(int32_t)))) return s;
+    if ((s = ensure(c, c->parts, (size_t)max_chunks * 5 * sizeof(double)))) return s;
+    if ((s = ensure_work(c, chunk))) return s;
+    bool adapting = adaptive;
+    int64_t done = 0, ci = 0;
+    double r[6] = {0, 0, 0, 0, 0, 0};
+    while (done < o->max_samples) {
+        const int64_t n = std::min(chunk, o->max_samples - done);
+        double *smp = (double *)c->smp.p, *lp = nullptr, *lq = nullptr;
+        if (adaptive) {
+            lp = (double *)c->lnp.p;
+            lq = (double *)c->lnq.p;
+            HIP_TRY(c, ile_launch_hist_draw(o->seed, done, n, nb, (const double *)c->hP.p,
+                                            (const double *)c->hC.p, o->d_min_mpc,
+                                            o->d_max_mpc, c->cfg.t_ref_max_s, smp, n, lp, lq,
+                                            (int32_t *)c->bins.p, c->stream));
+        } else {
+            HIP_TRY(c, ile_launch_prior(o->seed, done, n, o->d_min_mpc, o->d_max_mpc,
+                                        c->cfg.t_ref_max_s, smp, n, nullptr, c->stream));
+        }
+        if ((s = run_eval(c, smp, n, (double *)c->out.p, nullptr))) return s;
+        HIP_TRY(c, ile_launch_reduce((const double *)c->out.p, lp, lq, n,
+                                     (double *)c->red_tmp.p, (double *)c->parts.p + 5 * ci,
+                                     c->stream));
+        if (adapting &&
+            (s = refit_impl(c, (const int32_t *)c->bins.p, n, (const double *)c->out.p, lp,
+                            lq, n, floor_w, temper)))
+            return s;
+        HIP_TRY(c, ile_launch_finish((const double *)c->parts.p, (int)(ci + 1),
+                                     (double *)c->res.p, c->stream));
+        done += n;
+        ci++;
+        const bool check = o->n_eff_target > 0 || (adapting && o->adapt_chunks < 0);
+        if (check || done >= o->max_samples) {
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            HIP_TRY(c, hipMemcpy(r, c->res.p, sizeof(r), hipMemcpyDeviceToHost));
+            if (o->n_eff_target > 0 && r[1] >= o->n_eff_target) break;
+            if (adapting && o->adapt_chunks < 0 && r[0] > std::max(10.0, 0.5 * r[4]))
+                adapting = false;
+        }
+        if (adapting && o->adapt_chunks >= 0 && ci >= o->adapt_chunks) adapting = false;
+    }
+    if ((s = finish_call(c))) return s;
+    HIP_TRY(c, hipMemcpy(r, c->res.p, sizeof(r), hipMemcpyDeviceToHost));
+    copy_result(r, out);
+    if (n_chunks_out) *n_chunks_out = ci;
+    return ILE_OK;
+}
+
 ile_status ile_sync(ile_ctx *c)
 {
     if (!c) return ILE_E_ARG;
@@ -675,7 +854,8 @@ void ile_destroy(ile_ctx *c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (DevBuf *b : {&c->Q, &c->U, &c->V, &c->smp, &c->out, &c->lnp, &c->lnq,
                       &c->shifts, &c->keys, &c->perm, &c->hist, &c->scan_tmp,
-                      &c->errflag, &c->red_tmp, &c->parts, &c->res, &c->series})
+                      &c->errflag, &c->red_tmp, &c->parts, &c->res, &c->series,
+                      &c->hP, &c->hC, &c->bins, &c->hist_tmp})
         release(*b);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);

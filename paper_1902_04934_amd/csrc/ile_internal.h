@@ -78,5 +78,18 @@ hipError_t ile_launch_reduce(const double *lnL, const double *ln_p,
 // Merge n_part partials (fixed order) and finish into result[6].
 hipError_t ile_launch_finish(const double *partials, int n_part, double *result,
                              hipStream_t st);
+// Adaptive sampler (ile_sampler.hip): histogram state P[2][nb], C[2][nb+1].
+int ile_hist_max_bins();
+hipError_t ile_launch_hist_uniform(int nb, double *P, double *C, hipStream_t st);
+hipError_t ile_launch_hist_cdf(int nb, const double *P, double *C, hipStream_t st);
+hipError_t ile_launch_hist_draw(uint64_t seed, int64_t first, int64_t N, int nb,
+                                const double *P, const double *C, double d_min,
+                                double d_max, double t_ref_max, double *smp, int64_t ld,
+                                double *ln_p, double *ln_q, int32_t *bins, hipStream_t st);
+size_t ile_hist_refit_tmp_doubles(int64_t N, int nb);
+hipError_t ile_launch_hist_refit(const int32_t *bins, int64_t ld, const double *lnL,
+                                 const double *ln_p, const double *ln_q, int64_t N, int nb,
+                                 double floor_w, double scale, double *tmp, double *P,
+                                 double *C, hipStream_t st);
 hipError_t ile_launch_to_bf16_split(const double *Q, int64_t n, void *dst,
                                     hipStream_t st);

@@ -52,6 +52,17 @@ class Config(C.Structure):
                 ("device", C.c_int32), ("stream", C.c_void_p)]
 
 
+SAMPLER = {"prior": 0, "adaptive": 1, "learned": 2}
+
+
+class RunOpts(C.Structure):
+    _fields_ = [("sampler", C.c_int), ("seed", C.c_uint64), ("chunk", C.c_int64),
+                ("max_samples", C.c_int64), ("n_eff_target", C.c_double),
+                ("d_min_mpc", C.c_double), ("d_max_mpc", C.c_double),
+                ("n_bins", C.c_int32), ("floor", C.c_double), ("temper", C.c_double),
+                ("adapt_chunks", C.c_int32), ("reset", C.c_int32)]
+
+
 class Result(C.Structure):
     _fields_ = [("ln_L_marg", C.c_double), ("n_eff", C.c_double),
                 ("n_eff_kish", C.c_double), ("sigma_ln_L", C.c_double),
@@ -87,6 +98,14 @@ def lib():
                                          C.c_double, C.c_double, _vp, C.c_int64, _vp]
         L.ile_run_prior.argtypes = [_vp, C.c_uint64, C.c_int64, C.c_int64,
                                     C.c_double, C.c_double, C.POINTER(Result)]
+        L.ile_run.argtypes = [_vp, C.POINTER(RunOpts), C.POINTER(Result),
+                              C.POINTER(C.c_int64)]
+        L.ile_hist_get.argtypes = [_vp, C.c_int32, _dp, _dp]
+        L.ile_hist_set.argtypes = [_vp, C.c_int32, _dp, _dp]
+        L.ile_hist_draw_dev.argtypes = [_vp, C.c_uint64, C.c_int64, C.c_int64, C.c_double,
+                                        C.c_double, _vp, C.c_int64, _vp, _vp, _vp]
+        L.ile_hist_refit_dev.argtypes = [_vp, _vp, C.c_int64, _vp, _vp, _vp, C.c_int64,
+                                         C.c_double, C.c_double]
         L.ile_sync.argtypes = [_vp]
         L.ile_set_option.argtypes = [_vp, C.c_int, C.c_int64]
         L.ile_last_kernel_ms.argtypes = [_vp]
@@ -193,6 +212,48 @@ def ile_run_prior(h, seed, n, chunk, d_min=10.0, d_max=1000.0):
     return r.as_dict()
 
 
+def ile_run(h, sampler="adaptive", seed=1, chunk=100_000, max_samples=1_000_000,
+            n_eff_target=0.0, d_min=10.0, d_max=1000.0, n_bins=50, floor=0.1,
+            temper=10.0, adapt_chunks=-1, reset=True):
+    o = RunOpts(SAMPLER[sampler], int(seed), int(chunk), int(max_samples),
+                float(n_eff_target), float(d_min), float(d_max), int(n_bins),
+                float(floor), float(temper), int(adapt_chunks), 1 if reset else 0)
+    r = Result()
+    nc = C.c_int64()
+    _check(lib().ile_run(h, C.byref(o), C.byref(r), C.byref(nc)), h)
+    d = r.as_dict()
+    d["n_chunks"] = nc.value
+    return d
+
+
+def ile_hist_get(h, n_bins):
+    a = np.zeros(n_bins)
+    b = np.zeros(n_bins)
+    _check(lib().ile_hist_get(h, int(n_bins), a.ctypes.data_as(_dp),
+                              b.ctypes.data_as(_dp)), h)
+    return a, b
+
+
+def ile_hist_set(h, P_ra, P_sd):
+    a, ap = _f64(P_ra)
+    b, bp = _f64(P_sd)
+    _check(lib().ile_hist_set(h, int(a.size), ap, bp), h)
+
+
+def ile_hist_draw_dev(h, seed, first, n, d_min, d_max, samples_dev, ld,
+                      ln_p_dev=None, ln_q_dev=None, bins_dev=None):
+    _check(lib().ile_hist_draw_dev(h, int(seed), int(first), int(n), float(d_min),
+                                   float(d_max), _dev(samples_dev), int(ld),
+                                   _dev(ln_p_dev), _dev(ln_q_dev), _dev(bins_dev)), h)
+
+
+def ile_hist_refit_dev(h, bins_dev, ld, lnL_dev, ln_p_dev, ln_q_dev, n, floor=0.1,
+                       temper=10.0):
+    _check(lib().ile_hist_refit_dev(h, _dev(bins_dev), int(ld), _dev(lnL_dev),
+                                    _dev(ln_p_dev), _dev(ln_q_dev), int(n), float(floor),
+                                    float(temper)), h)
+
+
 def ile_sync(h):
     _check(lib().ile_sync(h), h)
 
@@ -256,6 +317,9 @@ class Context:
 
     def run_prior(self, seed, n, chunk=0, d_min=10.0, d_max=1000.0):
         return ile_run_prior(self.h, seed, n, chunk, d_min, d_max)
+
+    def run(self, **kw):
+        return ile_run(self.h, **kw)
 
     def sync(self):
         ile_sync(self.h)
