@@ -245,6 +245,59 @@ ile_status ile_hist_refit_dev(ile_ctx *ctx, const int32_t *bins_dev, int64_t ld,
                               const double *ln_q_dev, int64_t N, double floor,
                               double temper);
 
+/* ------------------------------------------------------ batched form
+ * Many intrinsic points (Sec. III.B: each ILE instance loops over many
+ * points to amortize its startup), each with its own detectors, modes,
+ * window length and Q/U/V, evaluated together: one prior draw, one window
+ * and ordering pass and one counting sort for all points, one persistent
+ * contraction kernel draining a (point, tile) queue, and one per-point
+ * reduction -- captured once in a HIP graph and replayed.  Point p draws
+ * from the Philox stream of key seed + p (the stream of ile_draw_prior_dev).
+ * Tuning (threads per workgroup, persistent workgroups per CU, queue order)
+ * is set by hand or by ile_batch_autotune, which times the candidates and
+ * caches the winner in a text file keyed by device, precision and the
+ * points' shapes. */
+typedef struct ile_batch ile_batch;
+
+typedef struct {
+    ile_precision precision;  /* bulk contraction precision of every point   */
+    int32_t device;
+    void *stream;             /* hipStream_t, or NULL for a new one          */
+} ile_batch_config;
+
+typedef struct {
+    int32_t threads;          /* 256 or 512                                  */
+    int32_t wgs_per_cu;       /* persistent workgroups per compute unit, 1..4 */
+    int32_t order;            /* 0: queue by decreasing cost, 1: point order  */
+    int32_t engine;           /* FP64 only: 1 matrix cores, 0 vector FMA      */
+} ile_batch_tuning;
+
+ile_status ile_batch_create(const ile_batch_config *cfg, ile_batch **out);
+/* Add one point: cfg describes it exactly as for ile_create (its precision,
+ * device and stream fields are ignored), then Q/U/V/dets as ile_set_data.
+ * The data are validated and copied; *id_out receives the point index. */
+ile_status ile_batch_add_point(ile_batch *b, const ile_config *cfg, const double *Q,
+                               int64_t n_q, double t0_s, const double *U,
+                               const double *V, const ile_detector *dets,
+                               int32_t *id_out);
+/* Draw n_per_point prior samples per point, evaluate, reduce: results[p]
+ * for every point p (host array of ile_batch_n_points entries). */
+ile_status ile_batch_run(ile_batch *b, uint64_t seed, int64_t n_per_point, double d_min,
+                         double d_max, ile_result *results);
+/* Per-point ln L_margT of the last run into host out[offset of p + i]
+ * (points concatenated, n_per_point each). */
+ile_status ile_batch_lnL(ile_batch *b, double *out, int64_t n_total);
+int32_t ile_batch_n_points(const ile_batch *b);
+ile_status ile_batch_set_tuning(ile_batch *b, const ile_batch_tuning *t);
+ile_status ile_batch_get_tuning(const ile_batch *b, ile_batch_tuning *t);
+/* Time every candidate tuning on a run of n_per_point samples per point and
+ * keep the fastest; cache_path (may be NULL) is read first and updated. */
+ile_status ile_batch_autotune(ile_batch *b, int64_t n_per_point, const char *cache_path);
+/* Device time in ms of the last run's graph (HIP events on its stream). */
+double ile_batch_last_ms(const ile_batch *b);
+void ile_batch_destroy(ile_batch *b);
+const char *ile_batch_last_error(const ile_batch *b);
+
 /* Wait for the context's stream; report a sticky device-side error. */
 ile_status ile_sync(ile_ctx *ctx);
 

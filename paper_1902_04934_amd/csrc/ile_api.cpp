@@ -27,6 +27,14 @@ struct DevBuf {
 
 }  // namespace
 
+struct ile_ctx;
+// accessors used by the batched form (ile_batch_api.cpp)
+const ile_geom &ile_ctx_geom(const ile_ctx *c);
+const void *ile_ctx_Q(const ile_ctx *c);
+const double *ile_ctx_U(const ile_ctx *c);
+const double *ile_ctx_V(const ile_ctx *c);
+ile_precision ile_ctx_precision(const ile_ctx *c);
+
 struct ile_ctx {
     ile_config cfg{};
     std::vector<ile_mode> modes;
@@ -280,6 +288,12 @@ ile_status check_ready(ile_ctx *c)
 
 }  // namespace
 
+const ile_geom &ile_ctx_geom(const ile_ctx *c) { return c->g; }
+const void *ile_ctx_Q(const ile_ctx *c) { return c->Q.p; }
+const double *ile_ctx_U(const ile_ctx *c) { return (const double *)c->U.p; }
+const double *ile_ctx_V(const ile_ctx *c) { return (const double *)c->V.p; }
+ile_precision ile_ctx_precision(const ile_ctx *c) { return c->cfg.precision; }
+
 // ------------------------------------------------------------------ C ABI
 extern "C" {
 
@@ -466,7 +480,7 @@ ile_status ile_set_data(ile_ctx *c, const double *Q, int64_t n_q, double t0_s,
     }
     HIP_TRY(c, hipMemcpy(c->U.p, U, nUV * 16, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->V.p, V, nUV * 16, hipMemcpyHostToDevice));
-    if ((s = ensure_work(c, 1))) return s;
+    if ((s = ensure(c, c->errflag, 16))) return s;
     HIP_TRY(c, hipMemset(c->errflag.p, 0, 16));
     c->have_data = true;
     return ILE_OK;

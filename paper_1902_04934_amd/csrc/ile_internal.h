@@ -36,6 +36,17 @@ struct ile_geom {
     signed char term_ps[ILE_MAX_TERMS];
 };
 
+// Device pointers of one intrinsic point of a batch.
+struct ile_point_dev {
+    const void *Q;            // planar Q (context precision)
+    const double2 *U, *V;
+    const double *smp;        // samples [7][N]
+    int64_t N;
+    const int32_t *perm;      // sorted order (local indices)
+    const int32_t *shifts;    // window starts [n_det][N]
+    double *out;              // lnLmargT [N]
+};
+
 // K steps of the matrix-core contraction (4 real rows = 2 modes each),
 // rounded up to a multiple of 3; the device Q holds 4 * ksp_of(n_lm) rows
 // per detector (rows 2a and 2a+1 = Re, Im of mode a, the rest zero).
@@ -91,5 +102,23 @@ hipError_t ile_launch_hist_refit(const int32_t *bins, int64_t ld, const double *
                                  const double *ln_p, const double *ln_q, int64_t N, int nb,
                                  double floor_w, double scale, double *tmp, double *P,
                                  double *C, hipStream_t st);
+// Batched form (ile_batch.hip + the persistent contraction).
+size_t ile_contract_dyn_bytes(const ile_geom &g, ile_precision prec, const ile_tune &tu);
+hipError_t ile_launch_contract_batched(ile_precision prec, const ile_tune &tu,
+                                       const ile_geom *geoms, const ile_point_dev *pts,
+                                       const int2 *items, int n_items, unsigned *counter,
+                                       int grid, size_t dyn, hipStream_t st);
+hipError_t ile_launch_prior_multi(const uint64_t *seed_dev, const int64_t *offs, int n_points,
+                                  int64_t n_total, double d_min, double d_max,
+                                  double t_ref_max, double *smp, hipStream_t st);
+hipError_t ile_launch_prep_multi(const ile_geom *geoms, const int64_t *offs, int n_points,
+                                 int64_t n_total, const double *smp, int32_t *shifts,
+                                 uint32_t *keys, uint32_t *hist, uint32_t B, int32_t *err,
+                                 hipStream_t st);
+hipError_t ile_launch_scatter_multi(const uint32_t *keys, const int64_t *offs, int n_points,
+                                    int64_t n_total, uint32_t *pos, int32_t *perm,
+                                    hipStream_t st);
+hipError_t ile_launch_reduce_points(const double *out, const int64_t *offs, int n_points,
+                                    double *res, hipStream_t st);
 hipError_t ile_launch_to_bf16_split(const double *Q, int64_t n, void *dst,
                                     hipStream_t st);

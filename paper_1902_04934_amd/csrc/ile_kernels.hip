@@ -366,9 +366,10 @@ template <int ENG> __host__ __device__ inline size_t coef_bytes(int ts, int nd, 
     return ENG == ENG_VALU ? (size_t)nd * nl * ts * 2 * e : (size_t)nd * ksp_of(nl) * 64 * e;
 }
 
+// One tile: samples perm[base .. base + TS) of a point (those below N).
 template <typename TQ, int TS, int NT, int ENG, bool DUMP>
-__global__ __launch_bounds__(NT) void k_contract(
-    ile_geom g, const double *__restrict__ smp, int64_t N,
+__device__ __forceinline__ void contract_tile(
+    const ile_geom &g, int64_t base, const double *__restrict__ smp, int64_t N,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ shifts,
     const TQ *__restrict__ Q, const double2 *__restrict__ U,
     const double2 *__restrict__ V, double *__restrict__ out,
@@ -390,7 +391,6 @@ __global__ __launch_bounds__(NT) void k_contract(
     const int tid = threadIdx.x;
     const int nd = g.n_det, nl = g.n_lm, nq = g.n_q;
     const int KSP = ksp_of(nl), RP = 4 * KSP;   // k-steps and Q rows per detector (padded)
-    const int64_t base = (int64_t)blockIdx.x * TS;
 
     // prologue scratch: inside Gs when it fits, else after the coefficients
     const size_t scr_bytes = prologue_scratch_bytes(TS, nd, nl);
@@ -627,6 +627,41 @@ __global__ __launch_bounds__(NT) void k_contract(
         double S = s_red[0][tid];
         for (int w = 1; w < NW; w++) S += s_red[w][tid];
         out[s_idx[tid]] = s_ok[tid] ? (s_M[tid] - s_q[tid]) + log(S) - log((double)g.n_t) : NAN;
+    }
+}
+
+template <typename TQ, int TS, int NT, int ENG, bool DUMP>
+__global__ __launch_bounds__(NT) void k_contract(
+    ile_geom g, const double *__restrict__ smp, int64_t N,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ shifts,
+    const TQ *__restrict__ Q, const double2 *__restrict__ U,
+    const double2 *__restrict__ V, double *__restrict__ out,
+    double *__restrict__ series)
+{
+    contract_tile<TQ, TS, NT, ENG, DUMP>(g, (int64_t)blockIdx.x * TS, smp, N, perm, shifts,
+                                         Q, U, V, out, series);
+}
+
+// Persistent form over many intrinsic points: every workgroup takes
+// (point, tile) items from a queue in list order (the host sorts the list by
+// decreasing cost) until it is empty; every wave reaches the exit.
+template <typename TQ, int TS, int NT, int ENG>
+__global__ __launch_bounds__(NT) void k_contract_batched(
+    const ile_geom *__restrict__ geoms, const ile_point_dev *__restrict__ pts,
+    const int2 *__restrict__ items, int n_items, unsigned *counter)
+{
+    __shared__ int s_item;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int it = s_item;
+        if (it >= n_items) break;
+        const int2 w = items[it];
+        const ile_point_dev &P = pts[w.x];
+        contract_tile<TQ, TS, NT, ENG, false>(geoms[w.x], (int64_t)w.y * TS, P.smp, P.N,
+                                              P.perm, P.shifts, (const TQ *)P.Q, P.U, P.V,
+                                              P.out, nullptr);
     }
 }
 
@@ -951,6 +986,41 @@ hipError_t ile_launch_contract(const ile_geom &g, ile_precision prec,
     if (tu.threads == 512) ILE_CONTRACT(float, 512, ENG_VALU);
     ILE_CONTRACT(float, 256, ENG_VALU);
 #undef ILE_CONTRACT
+}
+
+size_t ile_contract_dyn_bytes(const ile_geom &g, ile_precision prec, const ile_tune &tu)
+{
+    const size_t e = prec == ILE_FP64 ? 8 : 4;
+    size_t dyn = tu.engine == ENG_MFMA ? coef_bytes<ENG_MFMA>(tu.tile_samples, g.n_det, g.n_lm, e)
+                                       : coef_bytes<ENG_VALU>(tu.tile_samples, g.n_det, g.n_lm, e);
+    const size_t scr = prologue_scratch_bytes(tu.tile_samples, g.n_det, g.n_lm);
+    if (scr > (size_t)tu.tile_samples * tu.threads * e) dyn += scr;
+    return dyn;
+}
+
+hipError_t ile_launch_contract_batched(ile_precision prec, const ile_tune &tu,
+                                       const ile_geom *geoms, const ile_point_dev *pts,
+                                       const int2 *items, int n_items, unsigned *counter,
+                                       int grid, size_t dyn, hipStream_t st)
+{
+    if (!ile_tune_supported(prec, tu)) return hipErrorInvalidValue;
+#define ILE_BATCHED(TQ, NT, ENG)                                                              \
+    do {                                                                                      \
+        hipLaunchKernelGGL((k_contract_batched<TQ, 16, NT, ENG>), dim3(grid), dim3(NT), dyn,   \
+                           st, geoms, pts, items, n_items, counter);                          \
+        return hipGetLastError();                                                             \
+    } while (0)
+    if (prec == ILE_FP64) {
+        if (tu.engine == ENG_MFMA) {
+            if (tu.threads == 512) ILE_BATCHED(double, 512, ENG_MFMA);
+            ILE_BATCHED(double, 256, ENG_MFMA);
+        }
+        if (tu.threads == 512) ILE_BATCHED(double, 512, ENG_VALU);
+        ILE_BATCHED(double, 256, ENG_VALU);
+    }
+    if (tu.threads == 512) ILE_BATCHED(float, 512, ENG_VALU);
+    ILE_BATCHED(float, 256, ENG_VALU);
+#undef ILE_BATCHED
 }
 
 hipError_t ile_launch_prior(uint64_t seed, int64_t first, int64_t N,

@@ -63,6 +63,15 @@ class RunOpts(C.Structure):
                 ("adapt_chunks", C.c_int32), ("reset", C.c_int32)]
 
 
+class BatchConfig(C.Structure):
+    _fields_ = [("precision", C.c_int), ("device", C.c_int32), ("stream", C.c_void_p)]
+
+
+class BatchTuning(C.Structure):
+    _fields_ = [("threads", C.c_int32), ("wgs_per_cu", C.c_int32), ("order", C.c_int32),
+                ("engine", C.c_int32)]
+
+
 class Result(C.Structure):
     _fields_ = [("ln_L_marg", C.c_double), ("n_eff", C.c_double),
                 ("n_eff_kish", C.c_double), ("sigma_ln_L", C.c_double),
@@ -106,6 +115,22 @@ def lib():
                                         C.c_double, _vp, C.c_int64, _vp, _vp, _vp]
         L.ile_hist_refit_dev.argtypes = [_vp, _vp, C.c_int64, _vp, _vp, _vp, C.c_int64,
                                          C.c_double, C.c_double]
+        L.ile_batch_create.argtypes = [C.POINTER(BatchConfig), C.POINTER(_vp)]
+        L.ile_batch_add_point.argtypes = [_vp, C.POINTER(Config), _dp, C.c_int64, C.c_double,
+                                          _dp, _dp, C.POINTER(Detector), C.POINTER(C.c_int32)]
+        L.ile_batch_run.argtypes = [_vp, C.c_uint64, C.c_int64, C.c_double, C.c_double,
+                                    C.POINTER(Result)]
+        L.ile_batch_lnL.argtypes = [_vp, _dp, C.c_int64]
+        L.ile_batch_n_points.argtypes = [_vp]
+        L.ile_batch_set_tuning.argtypes = [_vp, C.POINTER(BatchTuning)]
+        L.ile_batch_get_tuning.argtypes = [_vp, C.POINTER(BatchTuning)]
+        L.ile_batch_autotune.argtypes = [_vp, C.c_int64, C.c_char_p]
+        L.ile_batch_last_ms.argtypes = [_vp]
+        L.ile_batch_last_ms.restype = C.c_double
+        L.ile_batch_destroy.argtypes = [_vp]
+        L.ile_batch_destroy.restype = None
+        L.ile_batch_last_error.argtypes = [_vp]
+        L.ile_batch_last_error.restype = C.c_char_p
         L.ile_sync.argtypes = [_vp]
         L.ile_set_option.argtypes = [_vp, C.c_int, C.c_int64]
         L.ile_last_kernel_ms.argtypes = [_vp]
@@ -333,6 +358,89 @@ class Context:
     def close(self):
         if getattr(self, "h", None):
             ile_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ batched form
+def _bcheck(status, b):
+    if status != ILE_OK:
+        m = lib().ile_batch_last_error(b) if b else b""
+        raise IleError(status, (m or b"").decode() or lib().ile_status_string(status).decode())
+
+
+class Batch:
+    """Many intrinsic points evaluated in one graph-captured run
+    (ile_batch_* of include/ile.h)."""
+
+    def __init__(self, precision="fp32", device=0, stream=None):
+        cfg = BatchConfig(PRECISION[precision], int(device),
+                          C.c_void_p(stream) if stream else None)
+        self.h = _vp()
+        _bcheck(lib().ile_batch_create(C.byref(cfg), C.byref(self.h)), None)
+
+    def add_point(self, inst):
+        modes_arr = (Mode * inst.n_lm)(*[Mode(int(l), int(m)) for (l, m) in inst.modes])
+        cfg = Config(inst.n_det, inst.n_lm, modes_arr, float(inst.srate_hz), int(inst.n_t),
+                     inst.d_ref_mpc, inst.gmst_rad, inst.earth_radius_m, inst.t_ref_max_s,
+                     0, 0, None)
+        Qa = np.ascontiguousarray(inst.Q, np.complex128)
+        Qf, Qp = _f64(Qa.view(np.float64))
+        Uf, Up = _f64(np.ascontiguousarray(inst.U, np.complex128).view(np.float64))
+        Vf, Vp = _f64(np.ascontiguousarray(inst.V, np.complex128).view(np.float64))
+        darr = (Detector * inst.n_det)(*[Detector(*d) for d in inst.dets])
+        pid = C.c_int32()
+        _bcheck(lib().ile_batch_add_point(self.h, C.byref(cfg), Qp, Qa.shape[-1],
+                                          float(inst.t0_s), Up, Vp, darr, C.byref(pid)),
+                self.h)
+        return pid.value
+
+    @property
+    def n_points(self):
+        return lib().ile_batch_n_points(self.h)
+
+    def run(self, seed, n_per_point, d_min=10.0, d_max=1000.0):
+        res = (Result * self.n_points)()
+        _bcheck(lib().ile_batch_run(self.h, int(seed), int(n_per_point), float(d_min),
+                                    float(d_max), res), self.h)
+        return [r.as_dict() for r in res]
+
+    def lnL(self, n_per_point):
+        out = np.empty(self.n_points * int(n_per_point))
+        _bcheck(lib().ile_batch_lnL(self.h, out.ctypes.data_as(_dp), out.size), self.h)
+        return out.reshape(self.n_points, -1)
+
+    def set_tuning(self, threads=256, wgs_per_cu=2, order=0, engine=1):
+        t = BatchTuning(threads, wgs_per_cu, order, engine)
+        _bcheck(lib().ile_batch_set_tuning(self.h, C.byref(t)), self.h)
+
+    def get_tuning(self):
+        t = BatchTuning()
+        _bcheck(lib().ile_batch_get_tuning(self.h, C.byref(t)), self.h)
+        return dict(threads=t.threads, wgs_per_cu=t.wgs_per_cu, order=t.order, engine=t.engine)
+
+    def autotune(self, n_per_point, cache_path=None):
+        _bcheck(lib().ile_batch_autotune(self.h, int(n_per_point),
+                                         cache_path.encode() if cache_path else None), self.h)
+        return self.get_tuning()
+
+    def last_ms(self):
+        return lib().ile_batch_last_ms(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ile_batch_destroy(self.h)
             self.h = None
 
     def __enter__(self):

@@ -1,0 +1,81 @@
+"""GPU parity of the batched form (many intrinsic points with uneven mode
+counts and window lengths in one graph-captured run) against the oracle,
+point by point, plus graph replay determinism and the autotuner."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1902_04934_amd import ile, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available()
+    return T
+
+
+@pytest.fixture(scope="module")
+def points():
+    return [synth.batched_point(p, n_q=8192, srate_hz=8192.0) for p in range(10)]
+
+
+def _check_batch(b, pts, seed, n, tol, rel):
+    from oracle import oracle as O
+    res = b.run(seed, n)
+    lnl = b.lnL(n)
+    for p, inst in enumerate(pts):
+        s, lp = O.prior_draw(seed + p, 0, n)
+        want = O.Ctx(inst).eval(s)
+        err = np.abs(lnl[p] - want) / (np.maximum(1.0, np.abs(want)) if rel else 1.0)
+        assert np.all(np.isfinite(lnl[p]))
+        assert err.max() <= tol, (p, inst.n_lm, inst.n_t, err.max())
+        ref = O.integrate(want, lp, lp)
+        assert abs(res[p]["ln_L_marg"] - ref["ln_L_marg"]) <= (1e-9 if not rel else 1e-3)
+        assert res[p]["n_samples"] == n
+    return res
+
+
+@pytest.mark.parametrize("precision,tol,rel", [("fp64", 1e-9, False), ("fp32", 1e-4, True)])
+def test_batch_matches_oracle(torch, points, precision, tol, rel):
+    with ile.Batch(precision) as b:
+        for inst in points:
+            b.add_point(inst)
+        assert b.n_points == len(points)
+        _check_batch(b, points, 500, 2003, tol, rel)
+        # other tunings give the same answers
+        b.set_tuning(threads=512, wgs_per_cu=1, order=1, engine=1)
+        _check_batch(b, points, 501, 2003, tol, rel)
+
+
+def test_batch_graph_replay_deterministic(torch, points):
+    with ile.Batch("fp32") as b:
+        for inst in points[:4]:
+            b.add_point(inst)
+        r1 = b.run(7, 4000)
+        l1 = b.lnL(4000)
+        r2 = b.run(8, 4000)
+        r3 = b.run(7, 4000)
+        l3 = b.lnL(4000)
+    assert r1 == r3 and np.array_equal(l1, l3)
+    assert r1 != r2
+
+
+def test_batch_autotune_and_cache(torch, points, tmp_path):
+    cache = str(tmp_path / "tune.txt")
+    with ile.Batch("fp32") as b:
+        for inst in points[:3]:
+            b.add_point(inst)
+        t = b.autotune(1000, cache)
+        assert t["threads"] in (256, 512) and 1 <= t["wgs_per_cu"] <= 3
+        lines = open(cache).read().splitlines()
+        assert len(lines) == 1 and lines[0].split()[1] == str(t["threads"])
+        _check_batch(b, points[:3], 42, 1000, 1e-4, True)
+    with ile.Batch("fp32") as b2:
+        for inst in points[:3]:
+            b2.add_point(inst)
+        assert b2.autotune(1000, cache) == t            # read from the cache
+        assert len(open(cache).read().splitlines()) == 1
