@@ -366,6 +366,60 @@ template <int ENG> __host__ __device__ inline size_t coef_bytes(int ts, int nd, 
     return ENG == ENG_VALU ? (size_t)nd * nl * ts * 2 * e : (size_t)nd * ksp_of(nl) * 64 * e;
 }
 
+// Online log-sum-exp of one bin's contraction per sample (q is constant
+// over bins and is subtracted at the end); one exp per sample and bin.
+template <typename TQ, int TS>
+__device__ __forceinline__ void lse_update(const TQ *L, double *m, double *sacc)
+{
+#pragma unroll
+    for (int al = 0; al < TS; al++) {
+        const double x = (double)L[al];
+        const double d = x - m[al];
+        const double e = exp(-fabs(d));
+        const bool gt = d > 0.0;
+        sacc[al] = gt ? fma(sacc[al], e, 1.0) : sacc[al] + e;
+        m[al] = gt ? x : m[al];
+    }
+}
+
+// Iterator over the pipeline items (chunk j0 of Jc bins, detector k,
+// position block blk).
+struct PipeIt {
+    int j0, Jc, k, blk;
+    bool valid;
+};
+
+__device__ __forceinline__ void pipe_first(PipeIt &it, int J, int n_t)
+{
+    it.j0 = 0;
+    it.Jc = min(J, n_t);
+    it.k = 0;
+    it.blk = 0;
+    it.valid = n_t > 0;
+}
+
+__device__ __forceinline__ void pipe_next(PipeIt &it, int J, int n_t, int nd,
+                                          const int *spread, int NP)
+{
+    it.blk += NP;
+    if (it.blk < it.Jc + spread[it.k]) return;
+    it.blk = 0;
+    if (++it.k < nd) return;
+    it.k = 0;
+    it.j0 += J;
+    if (it.j0 < n_t) {
+        it.Jc = min(J, n_t - it.j0);
+        return;
+    }
+    it.valid = false;
+}
+
+__device__ __forceinline__ bool pipe_last_of_chunk(const PipeIt &it, int nd, int spread_last,
+                                                   int NP)
+{
+    return it.k == nd - 1 && it.blk + NP >= it.Jc + spread_last;
+}
+
 // One tile: samples perm[base .. base + TS) of a point (those below N).
 template <typename TQ, int TS, int NT, int ENG, bool DUMP>
 __device__ __forceinline__ void contract_tile(
@@ -375,7 +429,7 @@ __device__ __forceinline__ void contract_tile(
     const double2 *__restrict__ V, double *__restrict__ out,
     double *__restrict__ series)
 {
-    static_assert(ENG == ENG_VALU || (TS == 16 && NT % 64 == 0), "MFMA tile is 16 samples");
+    static_assert(ENG == ENG_VALU || (TS == 16 && NT % 128 == 0), "MFMA tile is 16 samples");
     constexpr int NW = NT / 64;
     __shared__ __align__(16) TQ Gs[TS * NT];
     __shared__ double s_q[TS];
@@ -448,10 +502,11 @@ __device__ __forceinline__ void contract_tile(
 
     // 3. coefficients c = (d_ref/D) F_k Y_lm and rows of the quadratic term;
     //    modes a in [nl, 2 KS) are the zero padding of the MFMA K dimension
+    //    samples fastest, so the 16 lanes of one (k, a) read the same U, V row
     const int nlp = ENG == ENG_MFMA ? 2 * KSP : nl;
     for (int t = tid; t < TS * nd * nlp; t += NT) {
-        int al = t / (nd * nlp), r = t - al * (nd * nlp);
-        int k = r / nlp, a = r - k * nlp;
+        const int al = t % TS, r = t / TS;
+        const int k = r / nlp, a = r - k * nlp;
         double cx = 0.0, cy = 0.0, row = 0.0;
         if (a < nl) {
             double kap = s_ok[al] ? g.d_ref / s_th[5 * TS + al] : 0.0;
@@ -489,14 +544,10 @@ __device__ __forceinline__ void contract_tile(
     }
     __syncthreads();
 
-    // 4. quadratic term per sample; per-detector window range of the tile
-    if (tid < TS) {
-        double sum = 0.0;
-        for (int r = 0; r < nd * nl; r++) sum += s_qp[tid * (nd * nl) + r];
-        double kap = s_ok[tid] ? g.d_ref / s_th[5 * TS + tid] : 0.0;
-        s_q[tid] = 0.25 * kap * kap * sum;
-    } else if (tid >= 64 && tid < 64 + nd) {
-        int k = tid - 64;
+    // 4. per-detector window range of the tile; quadratic term per sample,
+    //    16 lanes per sample, fixed-order butterfly
+    if (tid < nd) {
+        const int k = tid;
         int lo = 0x7fffffff, hi = -1;
         for (int al = 0; al < TS; al++)
             if (s_ok[al]) {
@@ -507,6 +558,17 @@ __device__ __forceinline__ void contract_tile(
         s_smin[k] = lo;
         s_spread[k] = hi - lo;
     }
+    static_assert(NT >= 16 * TS, "16 lanes per sample for the quadratic sum");
+    if (tid < 16 * TS) {
+        const int al = tid >> 4, l16 = tid & 15;
+        double sum = 0.0;
+        for (int r = l16; r < nd * nl; r += 16) sum += s_qp[al * (nd * nl) + r];
+        for (int off = 8; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+        if (l16 == 0) {
+            const double kap = s_ok[al] ? g.d_ref / s_th[5 * TS + al] : 0.0;
+            s_q[al] = 0.25 * kap * kap * sum;
+        }
+    }
     __syncthreads();
     if (tid < TS)
         for (int k = 0; k < nd; k++) s_d[k][tid] = s_ok[tid] ? s_d[k][tid] - s_smin[k] : 0;
@@ -514,7 +576,10 @@ __device__ __forceinline__ void contract_tile(
 
     int smax_all = 0;
     for (int k = 0; k < nd; k++) smax_all = max(smax_all, s_spread[k]);
-    int J = NT - smax_all;
+    // NP positions per G block: every thread for the vector engine, the
+    // producer half of the workgroup for the matrix-core engine
+    constexpr int NP = ENG == ENG_MFMA ? NT / 2 : NT;
+    int J = NP - smax_all;
     if (J < 64) J = 64;
 
     double m[TS], sacc[TS];
@@ -525,21 +590,21 @@ __device__ __forceinline__ void contract_tile(
     }
     const int lane = tid & 63, wv = tid >> 6;
 
-    for (int j0 = 0; j0 < g.n_t; j0 += J) {
-        const int Jc = min(J, g.n_t - j0);
-        // thread tid owns the bins j == tid (mod NT); its bin in this chunk
-        const int jrel = ((tid - j0) % NT + NT) % NT;
-        const bool has = jrel < Jc;
-        TQ L[TS];
+    if constexpr (ENG == ENG_VALU) {
+        for (int j0 = 0; j0 < g.n_t; j0 += J) {
+            const int Jc = min(J, g.n_t - j0);
+            // thread tid owns the bins j == tid (mod NT); its bin in this chunk
+            const int jrel = ((tid - j0) % NT + NT) % NT;
+            const bool has = jrel < Jc;
+            TQ L[TS];
 #pragma unroll
-        for (int al = 0; al < TS; al++) L[al] = (TQ)0;
+            for (int al = 0; al < TS; al++) L[al] = (TQ)0;
 
-        for (int k = 0; k < nd; k++) {
-            const int Pk = s_smin[k] + j0;
-            const int Wk = Jc + s_spread[k];
-            const TQ *Qk = Q + (int64_t)k * RP * nq;
-            for (int blk = 0; blk < Wk; blk += NT) {
-                if (ENG == ENG_VALU) {
+            for (int k = 0; k < nd; k++) {
+                const int Pk = s_smin[k] + j0;
+                const int Wk = Jc + s_spread[k];
+                const TQ *Qk = Q + (int64_t)k * RP * nq;
+                for (int blk = 0; blk < Wk; blk += NT) {
                     const int p = blk + tid;
                     TQ acc[TS];
 #pragma unroll
@@ -563,40 +628,92 @@ __device__ __forceinline__ void contract_tile(
                     }
 #pragma unroll
                     for (int al = 0; al < TS; al++) Gs[al * NT + tid] = acc[al];
-                } else {
-                    mfma_gphase<TQ, NT>(Gs, coef + (size_t)k * KSP * 64, Qk, nq, KSP,
-                                        Pk + blk, min(Wk - blk, NT), lane);
-                }
-                __syncthreads();
-                if (has) {
+                    __syncthreads();
+                    if (has) {
 #pragma unroll
-                    for (int al = 0; al < TS; al++) {
-                        const int ix = s_d[k][al] + jrel - blk;
-                        const bool in = (unsigned)ix < (unsigned)NT;
-                        const TQ v = Gs[al * NT + (in ? ix : 0)];
-                        L[al] += in ? v : (TQ)0;
+                        for (int al = 0; al < TS; al++) {
+                            const int ix = s_d[k][al] + jrel - blk;
+                            const bool in = (unsigned)ix < (unsigned)NT;
+                            const TQ v = Gs[al * NT + (in ? ix : 0)];
+                            L[al] += in ? v : (TQ)0;
+                        }
                     }
+                    __syncthreads();
                 }
-                __syncthreads();
+            }
+            if (has) {
+                const int j = j0 + jrel;
+                if (DUMP) {
+                    for (int al = 0; al < TS; al++)
+                        if (s_ok[al]) series[(int64_t)s_idx[al] * g.n_t + j] = (double)L[al] - s_q[al];
+                }
+                lse_update<TQ, TS>(L, m, sacc);
             }
         }
-
-        if (has) {
-            const int j = j0 + jrel;
-            if (DUMP) {
-                for (int al = 0; al < TS; al++)
-                    if (s_ok[al]) series[(int64_t)s_idx[al] * g.n_t + j] = (double)L[al] - s_q[al];
+    } else {
+        // Producer/consumer pipeline over the items (chunk, detector, block):
+        // at step s the producer waves compute item s into Gs buffer s % 2
+        // on the matrix cores while the consumer waves realign item s-1 from
+        // the other buffer (and run the log-sum-exp at the end of a chunk);
+        // one barrier per step.  Both iterators are advanced identically by
+        // every thread, so the loop bounds are uniform.
+        const bool producer = __builtin_amdgcn_readfirstlane(tid) < NP;
+        // Separate loops per role (wave-uniform branch) so that the consumer
+        // state and the producer's operand buffers are never live together;
+        // both loops take the same steps and meet at one barrier per step.
+        PipeIt pi, ci;
+        pipe_first(pi, J, g.n_t);
+        pipe_first(ci, J, g.n_t);
+        if (producer) {
+            for (int step = 0; pi.valid || ci.valid; step++) {
+                if (pi.valid) {
+                    const int k = pi.k;
+                    mfma_gphase<TQ, NP>(Gs + (step & 1) * (TS * NP), coef + (size_t)k * KSP * 64,
+                                        Q + (int64_t)k * RP * nq, nq, KSP,
+                                        s_smin[k] + pi.j0 + pi.blk,
+                                        min(pi.Jc + s_spread[k] - pi.blk, NP), lane);
+                    pipe_next(pi, J, g.n_t, nd, s_spread, NP);
+                }
+                if (step > 0 && ci.valid) pipe_next(ci, J, g.n_t, nd, s_spread, NP);
+                __syncthreads();
             }
-            // online log-sum-exp of the contraction alone: q_alpha is constant
-            // over bins and is subtracted at the end; one exp per bin
+        } else {
+            const int tc = tid - NP;   // consumer index
+            TQ L[TS];
 #pragma unroll
-            for (int al = 0; al < TS; al++) {
-                const double x = (double)L[al];
-                const double d = x - m[al];
-                const double e = exp(-fabs(d));
-                const bool gt = d > 0.0;
-                sacc[al] = gt ? fma(sacc[al], e, 1.0) : sacc[al] + e;
-                m[al] = gt ? x : m[al];
+            for (int al = 0; al < TS; al++) L[al] = (TQ)0;
+            for (int step = 0; pi.valid || ci.valid; step++) {
+                if (step > 0 && ci.valid) {
+                    const TQ *G = Gs + ((step - 1) & 1) * (TS * NP);
+                    const int jrel = ((tc - ci.j0) % NP + NP) % NP;
+                    const bool has = jrel < ci.Jc;
+                    if (has) {
+#pragma unroll
+                        for (int al = 0; al < TS; al++) {
+                            const int ix = s_d[ci.k][al] + jrel - ci.blk;
+                            const bool in = (unsigned)ix < (unsigned)NP;
+                            const TQ v = G[al * NP + (in ? ix : 0)];
+                            L[al] += in ? v : (TQ)0;
+                        }
+                    }
+                    if (pipe_last_of_chunk(ci, nd, s_spread[nd - 1], NP)) {
+                        if (has) {
+                            const int j = ci.j0 + jrel;
+                            if (DUMP) {
+                                for (int al = 0; al < TS; al++)
+                                    if (s_ok[al])
+                                        series[(int64_t)s_idx[al] * g.n_t + j] =
+                                            (double)L[al] - s_q[al];
+                            }
+                            lse_update<TQ, TS>(L, m, sacc);
+                        }
+#pragma unroll
+                        for (int al = 0; al < TS; al++) L[al] = (TQ)0;
+                    }
+                    pipe_next(ci, J, g.n_t, nd, s_spread, NP);
+                }
+                if (pi.valid) pipe_next(pi, J, g.n_t, nd, s_spread, NP);
+                __syncthreads();
             }
         }
     }
@@ -949,7 +1066,7 @@ size_t ile_contract_lds_bytes(const ile_geom &g, ile_precision prec,
                               const ile_tune &tu)
 {
     const size_t e = prec == ILE_FP64 ? 8 : 4;
-    const size_t gs = (size_t)tu.tile_samples * tu.threads * e;
+    const size_t gs = (size_t)tu.tile_samples * (tu.engine == ENG_MFMA ? 2 : 1) * tu.threads * e;
     const size_t coef = tu.engine == ENG_MFMA
                             ? coef_bytes<ENG_MFMA>(tu.tile_samples, g.n_det, g.n_lm, e)
                             : coef_bytes<ENG_VALU>(tu.tile_samples, g.n_det, g.n_lm, e);
@@ -977,8 +1094,9 @@ hipError_t ile_launch_contract(const ile_geom &g, ile_precision prec,
     return launch_contract_t<TQ, 16, NT, ENG>(g, smp, N, perm, shifts, Q, U, V, out, series, st)
     if (prec == ILE_FP64) {
         if (tu.engine == ENG_MFMA) {
-            if (tu.threads == 512) ILE_CONTRACT(double, 512, ENG_MFMA);
-            ILE_CONTRACT(double, 256, ENG_MFMA);
+            // producer + consumer halves: threads = 2 x positions per block
+            if (tu.threads == 512) ILE_CONTRACT(double, 1024, ENG_MFMA);
+            ILE_CONTRACT(double, 512, ENG_MFMA);
         }
         if (tu.threads == 512) ILE_CONTRACT(double, 512, ENG_VALU);
         ILE_CONTRACT(double, 256, ENG_VALU);
@@ -988,13 +1106,18 @@ hipError_t ile_launch_contract(const ile_geom &g, ile_precision prec,
 #undef ILE_CONTRACT
 }
 
+static int kernel_threads(const ile_tune &tu)
+{
+    return tu.engine == ENG_MFMA ? 2 * tu.threads : tu.threads;
+}
+
 size_t ile_contract_dyn_bytes(const ile_geom &g, ile_precision prec, const ile_tune &tu)
 {
     const size_t e = prec == ILE_FP64 ? 8 : 4;
     size_t dyn = tu.engine == ENG_MFMA ? coef_bytes<ENG_MFMA>(tu.tile_samples, g.n_det, g.n_lm, e)
                                        : coef_bytes<ENG_VALU>(tu.tile_samples, g.n_det, g.n_lm, e);
     const size_t scr = prologue_scratch_bytes(tu.tile_samples, g.n_det, g.n_lm);
-    if (scr > (size_t)tu.tile_samples * tu.threads * e) dyn += scr;
+    if (scr > (size_t)tu.tile_samples * kernel_threads(tu) * e) dyn += scr;
     return dyn;
 }
 
@@ -1012,8 +1135,8 @@ hipError_t ile_launch_contract_batched(ile_precision prec, const ile_tune &tu,
     } while (0)
     if (prec == ILE_FP64) {
         if (tu.engine == ENG_MFMA) {
-            if (tu.threads == 512) ILE_BATCHED(double, 512, ENG_MFMA);
-            ILE_BATCHED(double, 256, ENG_MFMA);
+            if (tu.threads == 512) ILE_BATCHED(double, 1024, ENG_MFMA);
+            ILE_BATCHED(double, 512, ENG_MFMA);
         }
         if (tu.threads == 512) ILE_BATCHED(double, 512, ENG_VALU);
         ILE_BATCHED(double, 256, ENG_VALU);
