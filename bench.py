@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "lnL evals/s (sample×time-bin) + N_eff/s learned vs plain at 1e-3, 1 GPU"
 FP64_PEAK_TFLOPS = 78.6   # 256 CU x 2.4 GHz x 64 lanes x 2 flop (FMA)
 FP32_PEAK_TFLOPS = 157.3
+BF16_PEAK_TFLOPS = 2500.0  # dense matrix peak
 
 
 def flops_per_sample(n_det, n_lm, n_t):
@@ -61,7 +62,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--samples", type=int, default=None)
     ap.add_argument("--engine", default=None, choices=["mfma", "valu"],
                     help="contraction engine (default: matrix cores for FP64)")
@@ -103,7 +104,8 @@ def main():
     kernel_ms = sum(kms) / len(kms)
     fl = flops_per_sample(inst.n_det, inst.n_lm, inst.n_t) * n
     achieved = fl / (kernel_ms * 1e-3) / 1e12
-    peak = FP64_PEAK_TFLOPS if args.precision == "fp64" else FP32_PEAK_TFLOPS
+    peak = {"fp64": FP64_PEAK_TFLOPS, "fp32": FP32_PEAK_TFLOPS,
+            "bf16": BF16_PEAK_TFLOPS}[args.precision]
     out = {
         "metric": METRIC,
         "value": n * inst.n_t / (ms_step * 1e-3),
@@ -111,14 +113,14 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16x3+f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": "plain ILE at scale, one intrinsic point: 3 detectors, "
                                "21 modes (l=2..4), Q 16384 complex points at 16384 Hz, "
                                f"{n} prior samples, {inst.n_t} time bins",
                    "n_samples": n, "n_t": inst.n_t, "n_det": inst.n_det,
                    "n_lm": inst.n_lm, "precision": args.precision,
-                   "engine": args.engine or ("mfma" if args.precision == "fp64" else "valu"),
+                   "engine": args.engine or "mfma",
                    "threads": args.threads or 256},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,

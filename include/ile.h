@@ -269,7 +269,7 @@ typedef struct {
     int32_t threads;          /* 256 or 512                                  */
     int32_t wgs_per_cu;       /* persistent workgroups per compute unit, 1..4 */
     int32_t order;            /* 0: queue by decreasing cost, 1: point order  */
-    int32_t engine;           /* FP64 only: 1 matrix cores, 0 vector FMA      */
+    int32_t engine;           /* 1 matrix cores, 0 vector FMA (not for BF16)  */
 } ile_batch_tuning;
 
 ile_status ile_batch_create(const ile_batch_config *cfg, ile_batch **out);
@@ -304,8 +304,8 @@ ile_status ile_sync(ile_ctx *ctx);
 typedef enum {
     ILE_OPT_SORT = 0,    /* 1: order samples by window position before the
                             contraction (default), 0: keep input order */
-    ILE_OPT_ENGINE = 1,  /* contraction engine: 1 = FP64 matrix cores (FP64
-                            default), 0 = vector FMA (the only FP32 engine) */
+    ILE_OPT_ENGINE = 1,  /* contraction engine: 1 = matrix cores (default;
+                            the only BF16 engine), 0 = vector FMA */
     ILE_OPT_THREADS = 2  /* threads per workgroup = positions per block:
                             256 (default) or 512 */
 } ile_option;

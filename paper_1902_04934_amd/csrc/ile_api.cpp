@@ -160,6 +160,23 @@ void detector_frame(const ile_detector &d, double R, double r[3], double D[9])
         for (int j = 0; j < 3; j++) D[3 * i + j] = 0.5 * (x[i] * x[j] - y[i] * y[j]);
 }
 
+// float -> bfloat16, round to nearest even (inputs are finite)
+uint16_t bf16_rne(float f)
+{
+    uint32_t b;
+    std::memcpy(&b, &f, 4);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+float bf16_to_float(uint16_t h)
+{
+    const uint32_t b = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &b, 4);
+    return f;
+}
+
 bool sample_valid(const ile_ctx *c, const double *s, int64_t N, int64_t i)
 {
     double th[7];
@@ -334,7 +351,6 @@ ile_status ile_create(const ile_config *cfg, ile_ctx **out)
         int l = cfg->modes[a].l, m = cfg->modes[a].m;
         if (l < 2 || l > ILE_LMAX || m < -l || m > l) return ILE_E_ARG;
     }
-    if (cfg->precision == ILE_BF16) return ILE_E_UNSUPPORTED;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return ILE_E_DEVICE;
     if (cfg->device < 0 || cfg->device >= ndev) return ILE_E_ARG;
@@ -352,8 +368,8 @@ ile_status ile_create(const ile_config *cfg, ile_ctx **out)
         delete c;
         return ILE_E_DEVICE;
     }
-    // FP64: matrix-core G phase; FP32: vector ALUs
-    c->tune.engine = cfg->precision == ILE_FP64 ? 1 : 0;
+    // every precision defaults to the matrix cores (BF16 has no other engine)
+    c->tune.engine = 1;
     if (cfg->stream) {
         c->stream = (hipStream_t)cfg->stream;
     } else {
@@ -454,7 +470,9 @@ ile_status ile_set_data(ile_ctx *c, const double *Q, int64_t n_q, double t0_s,
     const size_t rp = (size_t)4 * ksp_of(nl);
     const size_t nQd = (size_t)nd * rp * n_q;
     const size_t qe = c->cfg.precision == ILE_FP64 ? 8 : 4;
-    if ((s = ensure(c, c->Q, nQd * qe))) return s;
+    const size_t kb = (size_t)32 * ksb_of(nl);   // BF16 rows per position
+    const size_t q_bytes = c->cfg.precision == ILE_BF16 ? (size_t)nd * n_q * kb * 2 : nQd * qe;
+    if ((s = ensure(c, c->Q, q_bytes))) return s;
     if ((s = ensure(c, c->U, nUV * 16))) return s;
     if ((s = ensure(c, c->V, nUV * 16))) return s;
     if (c->cfg.precision == ILE_FP64) {
@@ -467,6 +485,25 @@ ile_status ile_set_data(ile_ctx *c, const double *Q, int64_t n_q, double t0_s,
                     h[((size_t)k * rp + 2 * a + 1) * n_q + i] = q[1];
                 }
         HIP_TRY(c, hipMemcpy(c->Q.p, h.data(), nQd * 8, hipMemcpyHostToDevice));
+    } else if (c->cfg.precision == ILE_BF16) {
+        // K-contiguous per position: [Q_hi rows; Q_lo rows; Q_hi rows; zeros]
+        std::vector<uint16_t> h((size_t)nd * n_q * kb, 0);
+        const size_t R = 2 * (size_t)nl;
+        for (int k = 0; k < nd; k++)
+            for (int a = 0; a < nl; a++)
+                for (int64_t i = 0; i < n_q; i++) {
+                    const double *q = Q + 2 * (((size_t)k * nl + a) * n_q + i);
+                    uint16_t *row = &h[((size_t)k * n_q + i) * kb];
+                    for (int c2 = 0; c2 < 2; c2++) {
+                        const uint16_t hi = bf16_rne((float)q[c2]);
+                        const uint16_t lo = bf16_rne((float)(q[c2] - (double)bf16_to_float(hi)));
+                        const size_t r = 2 * a + c2;
+                        row[r] = hi;
+                        row[R + r] = lo;
+                        row[2 * R + r] = hi;
+                    }
+                }
+        HIP_TRY(c, hipMemcpy(c->Q.p, h.data(), h.size() * 2, hipMemcpyHostToDevice));
     } else {
         std::vector<float> h(nQd, 0.0f);
         for (int k = 0; k < nd; k++)

@@ -110,7 +110,7 @@ void drop_graph(ile_batch *b)
 
 ile_tune point_tune(const ile_batch *b)
 {
-    ile_tune t{16, b->tune.threads, b->cfg.precision == ILE_FP64 ? b->tune.engine : 0};
+    ile_tune t{16, b->tune.threads, b->tune.engine};
     return t;
 }
 
@@ -308,7 +308,9 @@ ile_status ile_batch_create(const ile_batch_config *cfg, ile_batch **out)
 {
     if (!out) return ILE_E_ARG;
     *out = nullptr;
-    if (!cfg || (cfg->precision != ILE_FP64 && cfg->precision != ILE_FP32)) return ILE_E_ARG;
+    if (!cfg || (cfg->precision != ILE_FP64 && cfg->precision != ILE_FP32 &&
+                 cfg->precision != ILE_BF16))
+        return ILE_E_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return ILE_E_DEVICE;
     if (cfg->device < 0 || cfg->device >= ndev) return ILE_E_ARG;
@@ -324,7 +326,7 @@ ile_status ile_batch_create(const ile_batch_config *cfg, ile_batch **out)
     b->cu_count = prop.multiProcessorCount;
     b->lds_max = (int)prop.sharedMemPerBlock;
     b->dev_name = prop.gcnArchName;
-    b->tune.engine = cfg->precision == ILE_FP64 ? 1 : 0;
+    b->tune.engine = 1;
     if (cfg->stream) {
         b->stream = (hipStream_t)cfg->stream;
     } else if (hipStreamCreate(&b->stream) != hipSuccess) {
@@ -413,11 +415,10 @@ ile_status ile_batch_set_tuning(ile_batch *b, const ile_batch_tuning *t)
         t->wgs_per_cu > 4 || (t->order != 0 && t->order != 1) ||
         (t->engine != 0 && t->engine != 1))
         return bfail(b, ILE_E_ARG, "bad tuning");
-    ile_tune tu{16, t->threads, b->cfg.precision == ILE_FP64 ? t->engine : 0};
+    ile_tune tu{16, t->threads, t->engine};
     if (!ile_tune_supported(b->cfg.precision, tu))
         return bfail(b, ILE_E_UNSUPPORTED, "tuning not supported for this precision");
     b->tune = *t;
-    if (b->cfg.precision != ILE_FP64) b->tune.engine = 0;
     return ILE_OK;
 }
 
@@ -450,12 +451,11 @@ ile_status ile_batch_autotune(ile_batch *b, int64_t n, const char *cache_path)
         }
     }
     std::vector<ile_batch_tuning> cand;
-    const int engines = b->cfg.precision == ILE_FP64 ? 2 : 1;
+    const int engines = b->cfg.precision == ILE_BF16 ? 1 : 2;
     for (int th : {256, 512})
         for (int w : {1, 2, 3})
             for (int o : {0, 1})
-                for (int en = 0; en < engines; en++)
-                    cand.push_back({th, w, o, b->cfg.precision == ILE_FP64 ? 1 - en : 0});
+                for (int en = 0; en < engines; en++) cand.push_back({th, w, o, 1 - en});
     ile_batch_tuning best = b->tune;
     double best_ms = 1e300;
     for (const ile_batch_tuning &t : cand) {

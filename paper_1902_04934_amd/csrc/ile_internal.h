@@ -52,6 +52,11 @@ struct ile_point_dev {
 // per detector (rows 2a and 2a+1 = Re, Im of mode a, the rest zero).
 __host__ __device__ inline int ksp_of(int n_lm) { return 3 * (((2 * n_lm + 3) / 4 + 2) / 3); }
 
+// K steps (32 rows each) of the BF16 hi/lo contraction: the rows are
+// [Q_hi (2 n_lm); Q_lo (2 n_lm); Q_hi (2 n_lm)], zero-padded; the device Q
+// holds them K-contiguous per position: [n_det][n_q][32 * ksb_of(n_lm)] bf16.
+__host__ __device__ inline int ksb_of(int n_lm) { return (6 * n_lm + 31) / 32; }
+
 // Tuning of the contraction kernel.
 struct ile_tune {
     int tile_samples;   // samples per workgroup tile (16)

@@ -267,9 +267,32 @@ __global__ __launch_bounds__(256) void k_identity(int32_t *perm, int64_t N)
 //             16 positions, A (coefficients) from LDS, B (Q) from memory.
 // Realign: thread j of the chunk adds G[alpha][s_alpha,k - s_min,k + j] for
 // every sample; online FP64 log-sum-exp over the bins each thread owns.
-enum { ENG_VALU = 0, ENG_MFMA = 1 };
+enum { ENG_VALU = 0, ENG_MFMA = 1, ENG_BF16 = 2 };
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// One 16x16x4 matrix-core step in the precision of the operands.  Output
+// layouts on gfx950 (checked with lane-layout probes): f64 gives
+// D[l/16 + 4v][l%16], f32 (and bf16 below) D[4(l/16) + v][l%16].
+template <typename TQ> struct mfma_acc;
+template <> struct mfma_acc<double> {
+    using type = v4d;
+    static __device__ inline v4d step(double a, double b, v4d c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int r, int v) { return r + 4 * v; }
+};
+template <> struct mfma_acc<float> {
+    using type = v4f;
+    static __device__ inline v4f step(float a, float b, v4f c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int r, int v) { return 4 * r + v; }
+};
 
 // G block on the matrix cores: Gs[alpha][p] = sum_r A[alpha][r] Qm[r][P0 + p]
 // for p < W (<= NT), 16 samples.  v_mfma_f64_16x16x4 on gfx950 (checked
@@ -285,11 +308,12 @@ __device__ inline void mfma_tiles(TQ *Gs, const TQ *coefA, const TQ *Qk, int nq,
 {
     constexpr int NW = NT / 64;
     const int row = lane >> 4, col = lane & 15;
-    v4d acc[NU];
+    using M = mfma_acc<TQ>;
+    typename M::type acc[NU];
     const TQ *qb[NU];
 #pragma unroll
     for (int u = 0; u < NU; u++) {
-        acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+        acc[u] = typename M::type{0, 0, 0, 0};
         qb[u] = Qk + (int64_t)row * nq + min(P0 + 16 * (wv + NW * u) + col, nq - 1);
     }
     const int64_t step = 4 * (int64_t)nq;
@@ -297,11 +321,11 @@ __device__ inline void mfma_tiles(TQ *Gs, const TQ *coefA, const TQ *Qk, int nq,
     // operand buffers, each reloaded right after its MFMAs consumed it, so
     // every load is in flight for two k-steps and the loop body has no
     // branches (prefetch indices past the end are clamped and unused)
-    double a0 = coefA[lane], a1 = coefA[64 + lane], a2, b0[NU], b1[NU], b2[NU];
+    TQ a0 = coefA[lane], a1 = coefA[64 + lane], a2, b0[NU], b1[NU], b2[NU];
 #pragma unroll
     for (int u = 0; u < NU; u++) {
-        b0[u] = (double)qb[u][0];
-        b1[u] = (double)qb[u][step];
+        b0[u] = qb[u][0];
+        b1[u] = qb[u][step];
     }
     // sched_barrier(0) keeps the compiler from folding the prefetch back
     // next to its use
@@ -309,34 +333,34 @@ __device__ inline void mfma_tiles(TQ *Gs, const TQ *coefA, const TQ *Qk, int nq,
         const int k3 = min(ks + 3, KSP - 1), k4 = min(ks + 4, KSP - 1);
         a2 = coefA[(ks + 2) * 64 + lane];
 #pragma unroll
-        for (int u = 0; u < NU; u++) b2[u] = (double)qb[u][(ks + 2) * step];
+        for (int u = 0; u < NU; u++) b2[u] = qb[u][(ks + 2) * step];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < NU; u++)
-            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0[u], acc[u], 0, 0, 0);
+            acc[u] = M::step(a0, b0[u], acc[u]);
         __builtin_amdgcn_sched_barrier(0);
         a0 = coefA[k3 * 64 + lane];
 #pragma unroll
-        for (int u = 0; u < NU; u++) b0[u] = (double)qb[u][k3 * step];
+        for (int u = 0; u < NU; u++) b0[u] = qb[u][k3 * step];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < NU; u++)
-            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1[u], acc[u], 0, 0, 0);
+            acc[u] = M::step(a1, b1[u], acc[u]);
         __builtin_amdgcn_sched_barrier(0);
         a1 = coefA[k4 * 64 + lane];
 #pragma unroll
-        for (int u = 0; u < NU; u++) b1[u] = (double)qb[u][k4 * step];
+        for (int u = 0; u < NU; u++) b1[u] = qb[u][k4 * step];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < NU; u++)
-            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b2[u], acc[u], 0, 0, 0);
+            acc[u] = M::step(a2, b2[u], acc[u]);
         __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int u = 0; u < NU; u++) {
         const int t = wv + NW * u;
 #pragma unroll
-        for (int v = 0; v < 4; v++) Gs[(row + 4 * v) * NT + 16 * t + col] = (TQ)acc[u][v];
+        for (int v = 0; v < 4; v++) Gs[M::row(row, v) * NT + 16 * t + col] = (TQ)acc[u][v];
     }
 }
 
@@ -360,10 +384,65 @@ __device__ inline void mfma_gphase(TQ *Gs, const TQ *coefA, const TQ *Qk, int nq
     }
 }
 
+// BF16 hi/lo contraction on v_mfma_f32_16x16x32_bf16: the K dimension is
+// the concatenation [Q_hi; Q_lo; Q_hi] against [C_hi, C_hi, C_lo] (3 x 2 n_lm
+// rows, zero-padded to 32 KSB), i.e. C.Q to about 16 significant bits with
+// float accumulation.  Q is stored K-contiguous per position
+// (Qb[p][32 KSB] bf16), so a lane's 8 consecutive k values are one 16-byte
+// load; A comes from LDS in the same [ks][lane][8] order.
+template <int NT, int NU>
+__device__ inline void bf16_tiles(float *Gs, const v8bf *coefA, const v8bf *Qk, int nq, int KSB,
+                                  int P0, int lane, int wv)
+{
+    constexpr int NW = NT / 64;
+    const int row = lane >> 4, col = lane & 15;
+    v4f acc[NU];
+    const v8bf *qb[NU];
+#pragma unroll
+    for (int u = 0; u < NU; u++) {
+        acc[u] = v4f{0, 0, 0, 0};
+        qb[u] = Qk + (int64_t)min(P0 + 16 * (wv + NW * u) + col, nq - 1) * (4 * KSB) + row;
+    }
+    for (int ks = 0; ks < KSB; ks++) {
+        const v8bf a = coefA[ks * 64 + lane];
+        v8bf b[NU];
+#pragma unroll
+        for (int u = 0; u < NU; u++) b[u] = qb[u][4 * ks];
+#pragma unroll
+        for (int u = 0; u < NU; u++) acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[u], acc[u], 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < NU; u++) {
+        const int t = wv + NW * u;
+#pragma unroll
+        for (int v = 0; v < 4; v++) Gs[(4 * row + v) * NT + 16 * t + col] = acc[u][v];
+    }
+}
+
+template <int NT>
+__device__ inline void bf16_gphase(float *Gs, const v8bf *coefA, const v8bf *Qk, int nq, int KSB,
+                                   int P0, int W, int lane)
+{
+    constexpr int NW = NT / 64, TPW = NT / 16 / NW;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ntile = (W + 15) >> 4;
+    int nu = ntile > wv ? (ntile - wv + NW - 1) / NW : 0;
+    nu = __builtin_amdgcn_readfirstlane(nu < TPW ? nu : TPW);
+    switch (nu) {
+    case 4: bf16_tiles<NT, 4>(Gs, coefA, Qk, nq, KSB, P0, lane, wv); break;
+    case 3: bf16_tiles<NT, 3>(Gs, coefA, Qk, nq, KSB, P0, lane, wv); break;
+    case 2: bf16_tiles<NT, 2>(Gs, coefA, Qk, nq, KSB, P0, lane, wv); break;
+    case 1: bf16_tiles<NT, 1>(Gs, coefA, Qk, nq, KSB, P0, lane, wv); break;
+    default: break;
+    }
+}
+
 template <int ENG> __host__ __device__ inline size_t coef_bytes(int ts, int nd, int nl, size_t e)
 {
-    // VALU: complex [nd][nl][ts]; MFMA: real [nd][KSP][64]
-    return ENG == ENG_VALU ? (size_t)nd * nl * ts * 2 * e : (size_t)nd * ksp_of(nl) * 64 * e;
+    // VALU: complex [nd][nl][ts]; MFMA: real [nd][KSP][64]; BF16: [nd][KSB][64][8] bf16
+    return ENG == ENG_VALU   ? (size_t)nd * nl * ts * 2 * e
+           : ENG == ENG_MFMA ? (size_t)nd * ksp_of(nl) * 64 * e
+                             : (size_t)nd * ksb_of(nl) * 64 * 8 * 2;
 }
 
 // Online log-sum-exp of one bin's contraction per sample (q is constant
@@ -430,6 +509,7 @@ __device__ __forceinline__ void contract_tile(
     double *__restrict__ series)
 {
     static_assert(ENG == ENG_VALU || (TS == 16 && NT % 128 == 0), "MFMA tile is 16 samples");
+    static_assert(ENG != ENG_BF16 || sizeof(TQ) == 4, "BF16 engine accumulates in float");
     constexpr int NW = NT / 64;
     __shared__ __align__(16) TQ Gs[TS * NT];
     __shared__ double s_q[TS];
@@ -445,6 +525,8 @@ __device__ __forceinline__ void contract_tile(
     const int tid = threadIdx.x;
     const int nd = g.n_det, nl = g.n_lm, nq = g.n_q;
     const int KSP = ksp_of(nl), RP = 4 * KSP;   // k-steps and Q rows per detector (padded)
+    const int KSB = ksb_of(nl);                 // BF16 k-steps
+    constexpr bool MF = ENG != ENG_VALU;        // matrix-core engines
 
     // prologue scratch: inside Gs when it fits, else after the coefficients
     const size_t scr_bytes = prologue_scratch_bytes(TS, nd, nl);
@@ -503,6 +585,11 @@ __device__ __forceinline__ void contract_tile(
     // 3. coefficients c = (d_ref/D) F_k Y_lm and rows of the quadratic term;
     //    modes a in [nl, 2 KS) are the zero padding of the MFMA K dimension
     //    samples fastest, so the 16 lanes of one (k, a) read the same U, V row
+    if (ENG == ENG_BF16) {
+        unsigned short *cz = reinterpret_cast<unsigned short *>(coef);
+        for (int t = tid; t < nd * KSB * 64 * 8; t += NT) cz[t] = 0;
+        __syncthreads();
+    }
     const int nlp = ENG == ENG_MFMA ? 2 * KSP : nl;
     for (int t = tid; t < TS * nd * nlp; t += NT) {
         const int al = t % TS, r = t / TS;
@@ -535,6 +622,25 @@ __device__ __forceinline__ void contract_tile(
         if (ENG == ENG_VALU) {
             coef[((k * nl + a) * TS + al) * 2] = (TQ)cx;
             coef[((k * nl + a) * TS + al) * 2 + 1] = (TQ)cy;
+        } else if (ENG == ENG_BF16) {
+            // A row k' of [C_hi, C_hi, C_lo]: lane = 16 (k' % 32 / 8) + alpha,
+            // element k' % 8, k-step k' / 32
+            __bf16 *cb = reinterpret_cast<__bf16 *>(coef) + (size_t)k * KSB * 64 * 8;
+            const int R = 2 * nl;
+            const double cv[2] = {cx, cy};
+#pragma unroll
+            for (int c = 0; c < 2; c++) {
+                const __bf16 hi = (__bf16)(float)cv[c];
+                const __bf16 lo = (__bf16)(float)(cv[c] - (double)(float)hi);
+                const int r = 2 * a + c;
+                const int kk[3] = {r, R + r, 2 * R + r};
+                const __bf16 vv[3] = {hi, hi, lo};
+#pragma unroll
+                for (int q = 0; q < 3; q++) {
+                    const int kp = kk[q];
+                    cb[((kp >> 5) * 64 + ((kp & 31) >> 3) * 16 + al) * 8 + (kp & 7)] = vv[q];
+                }
+            }
         } else {
             // A operand of k-step ks: lane = 16 * (row within the step) + alpha
             const int r0 = 2 * a;
@@ -578,7 +684,7 @@ __device__ __forceinline__ void contract_tile(
     for (int k = 0; k < nd; k++) smax_all = max(smax_all, s_spread[k]);
     // NP positions per G block: every thread for the vector engine, the
     // producer half of the workgroup for the matrix-core engine
-    constexpr int NP = ENG == ENG_MFMA ? NT / 2 : NT;
+    constexpr int NP = MF ? NT / 2 : NT;
     int J = NP - smax_all;
     if (J < 64) J = 64;
 
@@ -668,10 +774,16 @@ __device__ __forceinline__ void contract_tile(
             for (int step = 0; pi.valid || ci.valid; step++) {
                 if (pi.valid) {
                     const int k = pi.k;
-                    mfma_gphase<TQ, NP>(Gs + (step & 1) * (TS * NP), coef + (size_t)k * KSP * 64,
-                                        Q + (int64_t)k * RP * nq, nq, KSP,
-                                        s_smin[k] + pi.j0 + pi.blk,
-                                        min(pi.Jc + s_spread[k] - pi.blk, NP), lane);
+                    const int P0 = s_smin[k] + pi.j0 + pi.blk;
+                    const int W = min(pi.Jc + s_spread[k] - pi.blk, NP);
+                    if constexpr (ENG == ENG_BF16)
+                        bf16_gphase<NP>(reinterpret_cast<float *>(Gs) + (step & 1) * (TS * NP),
+                                        reinterpret_cast<const v8bf *>(coef) + (size_t)k * KSB * 64,
+                                        reinterpret_cast<const v8bf *>(Q) + (int64_t)k * nq * 4 * KSB,
+                                        nq, KSB, P0, W, lane);
+                    else
+                        mfma_gphase<TQ, NP>(Gs + (step & 1) * (TS * NP), coef + (size_t)k * KSP * 64,
+                                            Q + (int64_t)k * RP * nq, nq, KSP, P0, W, lane);
                     pipe_next(pi, J, g.n_t, nd, s_spread, NP);
                 }
                 if (step > 0 && ci.valid) pipe_next(ci, J, g.n_t, nd, s_spread, NP);
@@ -1062,14 +1174,24 @@ hipError_t ile_launch_identity(int32_t *perm, int64_t N, hipStream_t st)
     return hipGetLastError();
 }
 
+static int kernel_threads(const ile_tune &tu)
+{
+    return tu.engine == ENG_MFMA ? 2 * tu.threads : tu.threads;
+}
+
+static size_t coef_bytes_of(const ile_geom &g, ile_precision prec, const ile_tune &tu, size_t e)
+{
+    if (prec == ILE_BF16) return coef_bytes<ENG_BF16>(tu.tile_samples, g.n_det, g.n_lm, e);
+    return tu.engine == ENG_MFMA ? coef_bytes<ENG_MFMA>(tu.tile_samples, g.n_det, g.n_lm, e)
+                                 : coef_bytes<ENG_VALU>(tu.tile_samples, g.n_det, g.n_lm, e);
+}
+
 size_t ile_contract_lds_bytes(const ile_geom &g, ile_precision prec,
                               const ile_tune &tu)
 {
     const size_t e = prec == ILE_FP64 ? 8 : 4;
     const size_t gs = (size_t)tu.tile_samples * (tu.engine == ENG_MFMA ? 2 : 1) * tu.threads * e;
-    const size_t coef = tu.engine == ENG_MFMA
-                            ? coef_bytes<ENG_MFMA>(tu.tile_samples, g.n_det, g.n_lm, e)
-                            : coef_bytes<ENG_VALU>(tu.tile_samples, g.n_det, g.n_lm, e);
+    const size_t coef = coef_bytes_of(g, prec, tu, e);
     const size_t scr = prologue_scratch_bytes(tu.tile_samples, g.n_det, g.n_lm);
     return gs + coef + (scr > gs ? scr : 0) + 4096;
 }
@@ -1078,8 +1200,8 @@ bool ile_tune_supported(ile_precision prec, const ile_tune &tu)
 {
     if (tu.tile_samples != 16) return false;
     if (tu.threads != 256 && tu.threads != 512) return false;
-    if (tu.engine == ENG_MFMA) return prec == ILE_FP64;
-    return tu.engine == ENG_VALU && (prec == ILE_FP64 || prec == ILE_FP32);
+    if (prec == ILE_BF16) return tu.engine == ENG_MFMA;   // BF16 runs on the matrix cores only
+    return tu.engine == ENG_MFMA || tu.engine == ENG_VALU;
 }
 
 hipError_t ile_launch_contract(const ile_geom &g, ile_precision prec,
@@ -1101,21 +1223,23 @@ hipError_t ile_launch_contract(const ile_geom &g, ile_precision prec,
         if (tu.threads == 512) ILE_CONTRACT(double, 512, ENG_VALU);
         ILE_CONTRACT(double, 256, ENG_VALU);
     }
+    if (prec == ILE_BF16) {
+        if (tu.threads == 512) ILE_CONTRACT(float, 1024, ENG_BF16);
+        ILE_CONTRACT(float, 512, ENG_BF16);
+    }
+    if (tu.engine == ENG_MFMA) {
+        if (tu.threads == 512) ILE_CONTRACT(float, 1024, ENG_MFMA);
+        ILE_CONTRACT(float, 512, ENG_MFMA);
+    }
     if (tu.threads == 512) ILE_CONTRACT(float, 512, ENG_VALU);
     ILE_CONTRACT(float, 256, ENG_VALU);
 #undef ILE_CONTRACT
 }
 
-static int kernel_threads(const ile_tune &tu)
-{
-    return tu.engine == ENG_MFMA ? 2 * tu.threads : tu.threads;
-}
-
 size_t ile_contract_dyn_bytes(const ile_geom &g, ile_precision prec, const ile_tune &tu)
 {
     const size_t e = prec == ILE_FP64 ? 8 : 4;
-    size_t dyn = tu.engine == ENG_MFMA ? coef_bytes<ENG_MFMA>(tu.tile_samples, g.n_det, g.n_lm, e)
-                                       : coef_bytes<ENG_VALU>(tu.tile_samples, g.n_det, g.n_lm, e);
+    size_t dyn = coef_bytes_of(g, prec, tu, e);
     const size_t scr = prologue_scratch_bytes(tu.tile_samples, g.n_det, g.n_lm);
     if (scr > (size_t)tu.tile_samples * kernel_threads(tu) * e) dyn += scr;
     return dyn;
@@ -1140,6 +1264,14 @@ hipError_t ile_launch_contract_batched(ile_precision prec, const ile_tune &tu,
         }
         if (tu.threads == 512) ILE_BATCHED(double, 512, ENG_VALU);
         ILE_BATCHED(double, 256, ENG_VALU);
+    }
+    if (prec == ILE_BF16) {
+        if (tu.threads == 512) ILE_BATCHED(float, 1024, ENG_BF16);
+        ILE_BATCHED(float, 512, ENG_BF16);
+    }
+    if (tu.engine == ENG_MFMA) {
+        if (tu.threads == 512) ILE_BATCHED(float, 1024, ENG_MFMA);
+        ILE_BATCHED(float, 512, ENG_MFMA);
     }
     if (tu.threads == 512) ILE_BATCHED(float, 512, ENG_VALU);
     ILE_BATCHED(float, 256, ENG_VALU);

@@ -39,7 +39,8 @@ def _check_batch(b, pts, seed, n, tol, rel):
     return res
 
 
-@pytest.mark.parametrize("precision,tol,rel", [("fp64", 1e-9, False), ("fp32", 1e-4, True)])
+@pytest.mark.parametrize("precision,tol,rel", [("fp64", 1e-9, False), ("fp32", 1e-4, True),
+                                               ("bf16", 1e-4, True)])
 def test_batch_matches_oracle(torch, points, precision, tol, rel):
     with ile.Batch(precision) as b:
         for inst in points:

@@ -142,16 +142,20 @@ def test_series_per_bin(torch):
             assert i in _flagged(octx, s, [i])
 
 
-def test_fp32_config2_shape(torch, c2_small):
+@pytest.mark.parametrize("precision,engine", [("fp32", "mfma"), ("fp32", "valu"), ("bf16", "mfma")])
+def test_reduced_precision_config2_shape(torch, c2_small, precision, engine):
+    """FP32 and BF16 hi/lo bulk contraction with FP64 log-sum-exp: per-sample
+    ln L_margT within 1e-4 relative, ln L_marg within 1e-3."""
     from oracle import oracle as O
     inst, s, lp, want = c2_small
-    with ile.Context(inst, precision="fp32") as ctx:
+    with ile.Context(inst, precision=precision, engine=engine) as ctx:
         got = ctx.eval(s)
         res = ctx.integrate(s, lp, lp)
     err = check_margT(got, want, s, O.Ctx(inst), inst, tol=1e-4, rel=True)
     ref = O.integrate(want, lp, lp)
     assert abs(res["ln_L_marg"] - ref["ln_L_marg"]) <= 1e-3
-    print(f"fp32: max rel err {err:.3e}, d ln L_marg {res['ln_L_marg'] - ref['ln_L_marg']:.3e}")
+    print(f"{precision}/{engine}: max rel err {err:.3e}, "
+          f"d ln L_marg {res['ln_L_marg'] - ref['ln_L_marg']:.3e}")
 
 
 def test_integrate_matches_oracle(torch, c1):
