@@ -11,11 +11,11 @@ LIB = os.path.join(HERE, "libile_oracle.so")
 
 
 def build(verbose: bool = False) -> str:
-    src = os.path.join(HERE, "ile_oracle.c")
+    srcs = [os.path.join(HERE, f) for f in ("ile_oracle.c", "mdn_oracle.c")]
     tmp = LIB + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fopenmp",
            "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-Wall", "-Wextra", "-o", tmp, src, "-lm"]
+           "-Wall", "-Wextra", "-o", tmp, *srcs, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

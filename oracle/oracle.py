@@ -280,3 +280,88 @@ def injection_instance(base, h_lm, theta_inj, noise_sigma=0.0, rng=None):
             Q[k, a] = np.fft.ifft(np.conj(np.fft.fft(h_lm[a])) * D)
     inst.Q, inst.U, inst.V = Q, U, V
     return inst, data, lags
+
+
+# ------------------------------------------------- learned proposal (MDN)
+MDN_NPARAM = 60880
+
+
+class MdnTransform(C.Structure):
+    _fields_ = [("origin", C.c_double * 3), ("mean", C.c_double * 7),
+                ("scale", C.c_double * 7), ("d_min", C.c_double),
+                ("d_max", C.c_double), ("t_ref_max", C.c_double),
+                ("sigma_floor", C.c_double)]
+
+
+def mdn_transform(origin=(0.0, 0.0, 0.0), mean=None, scale=None, d_min=10.0,
+                  d_max=1000.0, t_ref_max=0.01, sigma_floor=1e-3):
+    tr = MdnTransform()
+    for j in range(3):
+        tr.origin[j] = origin[j]
+    for d in range(7):
+        tr.mean[d] = 0.0 if mean is None else mean[d]
+        tr.scale[d] = 1.0 if scale is None else scale[d]
+    tr.d_min, tr.d_max, tr.t_ref_max = d_min, d_max, t_ref_max
+    tr.sigma_floor = sigma_floor
+    return tr
+
+
+def mdn_mask():
+    L = lib()
+    return np.array([L.orc_mdn_mask(C.c_int64(j)) for j in range(MDN_NPARAM)], np.int32)
+
+
+def mdn_to_z(tr, x):
+    L = lib()
+    L.orc_mdn_to_z.restype = C.c_double
+    x = np.ascontiguousarray(x, np.float64)
+    z = np.zeros(7)
+    lj = L.orc_mdn_to_z(C.byref(tr), _p(x), _p(z))
+    return z, lj
+
+
+def mdn_lnq_z(params, tr, z):
+    """(ln q(z~), per-dimension terms)."""
+    L = lib()
+    L.orc_mdn_lnq_z.restype = C.c_double
+    P = np.ascontiguousarray(params, np.float64)
+    z = np.ascontiguousarray(z, np.float64)
+    dims = np.zeros(7)
+    v = L.orc_mdn_lnq_z(_p(P), C.byref(tr), _p(z), _p(dims))
+    return v, dims
+
+
+def mdn_logpdf(params, tr, x):
+    P = np.ascontiguousarray(params, np.float64)
+    x = np.ascontiguousarray(x, np.float64)
+    n = x.shape[1]
+    out = np.zeros(n)
+    lib().orc_mdn_logpdf(_p(P), C.byref(tr), _p(x), C.c_int64(n), C.c_int64(n), _p(out))
+    return out
+
+
+def mdn_loss_grad(params, tr, x, w=None):
+    P = np.ascontiguousarray(params, np.float64)
+    x = np.ascontiguousarray(x, np.float64)
+    n = x.shape[1]
+    g = np.zeros(MDN_NPARAM)
+    loss = C.c_double()
+    wp = None
+    if w is not None:
+        w = np.ascontiguousarray(w, np.float64)
+        wp = _p(w)
+    lib().orc_mdn_loss_grad(_p(P), C.byref(tr), _p(x), C.c_int64(n), C.c_int64(n), wp,
+                            C.byref(loss), _p(g))
+    return loss.value, g
+
+
+def mdn_fit_transform(x, lnw, temper=10.0, d_min=10.0, d_max=1000.0, t_ref_max=0.01,
+                      sigma_floor=1e-3):
+    x = np.ascontiguousarray(x, np.float64)
+    lnw = np.ascontiguousarray(lnw, np.float64)
+    n = x.shape[1]
+    tr = mdn_transform(d_min=d_min, d_max=d_max, t_ref_max=t_ref_max,
+                       sigma_floor=sigma_floor)
+    lib().orc_mdn_fit_transform(_p(x), C.c_int64(n), _p(lnw), C.c_int64(n),
+                                C.c_double(temper), C.byref(tr))
+    return tr

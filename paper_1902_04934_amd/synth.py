@@ -177,3 +177,27 @@ def batched_point(p, *, n_q=16384, srate_hz=16384.0):
     n_t = 2 * int(rng.integers(100, 801)) + 1
     return make_instance(["D1", "D2", "D3"], n_lm, n_q, srate_hz, n_t,
                          seed + 7_000_000)
+
+
+# ------------------------------------------------- learned-proposal inputs
+MDN_BLOCKS = [  # (name, size, fan_in, fan_out) of the flat parameter vector
+    ("W1", 128 * 7, 7, 128), ("b1", 128, 0, 0),
+    ("W2", 128 * 128, 128, 128), ("b2", 128, 0, 0),
+    ("W3", 336 * 128, 128, 336), ("b3", 336, 0, 0),
+]
+
+
+def mdn_params(seed, *, gain=1.0, bias=0.3):
+    """A seeded parameter vector for the mixture-density proposal (float32,
+    60880 values in the block order of MDN_BLOCKS): Glorot-uniform weights
+    times gain, uniform biases in [-bias, bias].  Plain random numbers; the
+    masks are applied by whoever evaluates the network."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _, size, fi, fo in MDN_BLOCKS:
+        if fi:
+            a = gain * math.sqrt(6.0 / (fi + fo))
+            out.append(rng.uniform(-a, a, size))
+        else:
+            out.append(rng.uniform(-bias, bias, size))
+    return np.concatenate(out).astype(np.float32)
