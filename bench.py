@@ -57,6 +57,46 @@ def cpu_baseline(inst, n_total, seed, target_s=12.0):
                       f"FP64 C oracle with OpenMP ({dt:.1f} s)"}
 
 
+def learned_leg(target=1e4):
+    """The learned proposal against the plain adaptive sampler on the zero-noise
+    injection workload (3 detectors, 9 modes, 16384 points at 16384 Hz, 1601
+    bins, network SNR 20): wall time of each to n_eff = target, n_eff/s, and
+    their ln L_marg."""
+    import numpy as np
+    from paper_1902_04934_amd import ile, synth
+    c = synth.config4_parts()
+    base = synth.Instance(dets=c["dets"], modes=c["modes"], srate_hz=c["srate_hz"],
+                          n_t=c["n_t"], Q=np.zeros((3, 9, c["n_q"]), complex),
+                          U=np.zeros((3, 9, 9), complex), V=np.zeros((3, 9, 9), complex))
+    out = {"workload": "zero-noise injection at network SNR 20: 3 detectors, 9 modes "
+                       "(l=2,3), Q 16384 complex points at 16384 Hz, 1601 time bins, FP64",
+           "n_eff_target": target}
+    with ile.Context(base) as ctx:
+        rho2, dinj = ile.ile_inject(ctx.h, c["h_lm"], base.t0_s, base.dets, c["theta_inj"],
+                                    c["snr"])
+        ctx.run(sampler="prior", seed=1, chunk=100_000, max_samples=100_000)   # warm-up
+        for name, kw in (("plain", dict(sampler="adaptive", adapt_chunks=-1,
+                                        max_samples=50_000_000)),
+                         ("learned", dict(sampler="learned", adapt_chunks=3,
+                                          max_samples=20_000_000, eps=0.1,
+                                          train_steps=1000, train_batch=4096))):
+            prop = ile.Proposal(ctx, seed=3) if name == "learned" else None
+            t0 = time.perf_counter()
+            r = ctx.run(seed=41, chunk=100_000, n_eff_target=target, prop=prop, **kw)
+            dt = time.perf_counter() - t0
+            entry = {"seconds": dt, "n_eff": r["n_eff"], "n_eff_per_s": r["n_eff"] / dt,
+                     "ln_L_marg": r["ln_L_marg"], "sigma_ln_L": r["sigma_ln_L"],
+                     "samples": r["n_samples"]}
+            if prop is not None:
+                entry.update(train_samples=r["n_train_samples"], train_ms=r["train_ms"],
+                             fell_back=r["fell_back"])
+                prop.close()
+            out[name] = entry
+    out["gain_n_eff_per_s"] = out["learned"]["n_eff_per_s"] / max(out["plain"]["n_eff_per_s"], 1e-30)
+    out["d_ln_L_marg"] = out["learned"]["ln_L_marg"] - out["plain"]["ln_L_marg"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +108,8 @@ def main():
                     help="contraction engine (default: matrix cores for FP64)")
     ap.add_argument("--threads", type=int, default=None, choices=[256, 512])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-vs-plain sampler comparison")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -130,6 +172,7 @@ def main():
                    "sigma_ln_L": res["sigma_ln_L"]},
     }
     ctx.close()
+    out["learned"] = None if args.no_learned else learned_leg()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, n_total, seed)
     else:

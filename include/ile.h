@@ -65,6 +65,7 @@ extern "C" {
 #endif
 
 typedef struct ile_ctx ile_ctx;
+typedef struct ile_prop ile_prop;   /* learned proposal, below */
 
 typedef enum {
     ILE_OK = 0,
@@ -127,6 +128,24 @@ ile_status ile_create(const ile_config *cfg, ile_ctx **out);
 ile_status ile_set_data(ile_ctx *ctx, const double *Q, int64_t n_q,
                         double t0_s, const double *U, const double *V,
                         const ile_detector *dets);
+
+/* A zero-noise injection built on the device and installed as by
+ * ile_set_data: a physically consistent instance for tests of recovery.
+ * White unit-variance noise, so Eq. (2) is <a|b> = sum_i conj(a_i) b_i with
+ * circular shifts.  From mode series h_lm (host double [n_lm][n_q][2]) and
+ * injected parameters theta[7]:
+ *   d_k[i]   = Re(F_k (D_ref/D) sum_lm Y_lm h_lm[(i - lag_k) mod n_q]),
+ *              F_k = F+ + i Fx, lag_k = floor((t_ref + tau_k - t0)/dt + 1/2),
+ *   Q_k,lm[s] = sum_i conj(h_lm[(i - s) mod n_q]) d_k[i]        (Eq. (8)),
+ *   U_k = sum_i conj(h_a[i]) h_b[i],  V_k = sum_i h_a[i] h_b[i]  (every k).
+ * If snr > 0 the data are scaled to network SNR sqrt(sum_k <d_k|d_k>) =
+ * snr, which moves the injected distance to *d_inj_out.  rho2_out (SNR^2),
+ * d_inj_out and the host copies Q_out, U_out, V_out (layouts of
+ * ile_set_data) may be NULL. */
+ile_status ile_inject(ile_ctx *ctx, const double *h_lm, int64_t n_q, double t0_s,
+                      const ile_detector *dets, const double *theta, double snr,
+                      double *rho2_out, double *d_inj_out, double *Q_out, double *U_out,
+                      double *V_out);
 
 /* ln L_margT for N host samples into host lnL_margT[N].  ILE_E_RANGE if any
  * sample has D <= 0, |cos iota| > 1, |t_ref| > t_ref_max or a non-finite
@@ -196,7 +215,7 @@ ile_status ile_run_prior(ile_ctx *ctx, uint64_t seed, int64_t N,
 typedef enum {
     ILE_SAMPLER_PRIOR = 0,     /* proposal = prior (ln p - ln q = 0)        */
     ILE_SAMPLER_ADAPTIVE = 1,  /* histogram proposal, refit per chunk       */
-    ILE_SAMPLER_LEARNED = 2    /* reserved: learned proposal                */
+    ILE_SAMPLER_LEARNED = 2    /* adaptive rounds, then the learned proposal */
 } ile_sampler;
 
 typedef struct {
@@ -213,6 +232,18 @@ typedef struct {
                                 until ln L_marg > max(10, max lnLmargT / 2) */
     int32_t reset;           /* 1: start from uniform histograms; 0: keep the
                                 context's current ones (warm start)          */
+    /* sampler LEARNED only: adapt_chunks (<= 0: 3) adaptive rounds of
+     * `chunk` samples train `prop` (train_steps Adam steps of train_batch,
+     * learning rate lr; <= 0: defaults of ile_prop_train_dev); then chunks
+     * are drawn from (1 - eps) q_net + eps q_hist (the histograms as left by
+     * the rounds).  If the first learned chunk alone has n_eff below
+     * fallback_neff, the run continues with the adaptive sampler.  The
+     * estimate covers the chunks after training only. */
+    ile_prop *prop;
+    double eps;              /* defensive weight (< 0: 0.1)                   */
+    double fallback_neff;    /* (< 0: 1000; 0: never fall back)               */
+    int32_t train_steps, train_batch;
+    double lr;
 } ile_run_opts;
 
 /* Monte Carlo estimate of ln L_marg: chunk after chunk, draw on the device,
@@ -222,6 +253,16 @@ typedef struct {
  * so the combined estimate is unbiased.  n_chunks_out may be NULL. */
 ile_status ile_run(ile_ctx *ctx, const ile_run_opts *opts, ile_result *out,
                    int64_t *n_chunks_out);
+
+/* Result of the last ile_run with sampler LEARNED: samples drawn before
+ * training (adaptive rounds), after training, and whether it fell back. */
+typedef struct {
+    int64_t n_train_samples, n_learned_samples;
+    int32_t fell_back;
+    double train_ms;           /* device time of the training steps          */
+    double final_loss;
+} ile_learned_info;
+ile_status ile_last_learned_info(const ile_ctx *ctx, ile_learned_info *out);
 
 /* Copy the context's histograms out / in (host arrays of n_bins doubles;
  * ile_hist_set normalizes nothing: P must be positive and sum to 1). */
@@ -244,6 +285,100 @@ ile_status ile_hist_refit_dev(ile_ctx *ctx, const int32_t *bins_dev, int64_t ld,
                               const double *lnL_dev, const double *ln_p_dev,
                               const double *ln_q_dev, int64_t N, double floor,
                               double temper);
+
+/* --------------------------------------------------- learned proposal
+ * Not in the paper, which adapts 1-D histograms (Sec. II.A, Sec. III.C): a
+ * masked autoregressive mixture density network over the 7 extrinsic
+ * parameters, trained on the weighted samples of the first adaptive rounds
+ * and used in a defensive mixture with the histogram proposal.
+ *
+ * Transform x -> z~ (x in the sample order ra, dec, psi, phi, cos iota, D,
+ * t_ref): u = frac((x - origin)/P + 1/2) for ra (P = 2 pi), psi (P = pi),
+ * phi (P = 2 pi); u = (sin dec + 1)/2, (cos iota + 1)/2, (D - d_min)/(d_max
+ * - d_min), (t_ref + t_max)/(2 t_max); z = ln(u/(1-u)); z~ = (z - mean) /
+ * scale.  ln q(x) = ln q(z~) + sum_d ln |dz~_d/dx_d| (-inf if a u is 0 or 1).
+ *
+ * Network: h1 = tanh(W1 z~ + b1), h2 = tanh(W2 h1 + b2), o = W3 h2 + b3;
+ * float32 parameters, ILE_PROP_NPARAM of them, flat and row-major:
+ *   W1[128][7] | b1[128] | W2[128][128] | b2[128] | W3[336][128] | b3[336].
+ * MADE masks, hidden degree deg(k) = k mod 6: W1[k][i] used iff i <= deg(k),
+ * W2[k2][k1] iff deg(k1) <= deg(k2), W3[o][k] iff deg(k) < o / 48; masked
+ * entries are held at zero.  Dimension d is a 16-component Gaussian mixture
+ * in z~_d with logits o[48d + c], means o[48d + 16 + c] and scales
+ * sigma_floor + softplus(o[48d + 32 + c]).
+ *
+ * Device arithmetic: layer 1 FP32; layers 2 and 3 BF16 on the matrix cores
+ * with FP32 accumulation; mixture densities FP32; transform, Jacobian,
+ * ln p and the defensive mixture FP64.  Draws: Philox4x32-10 counters
+ * (i, b, 0x4D444E31), b = 0..7, key seed: uniforms 0..6 choose components,
+ * 7..14 give normals (Box-Muller), 15 picks the member of the defensive
+ * mixture; a histogram member draws exactly as ile_hist_draw_dev (counter
+ * i).  The ln q returned by ile_prop_sample_dev is bit-identical to what
+ * ile_prop_logpdf_dev returns for the drawn sample.
+ *
+ * Training minimizes -sum w ln q(z~) / sum w with Adam (0.9, 0.999, 1e-8)
+ * on minibatches drawn from the training set with probability proportional
+ * to the tempered weights w = exp(beta (ln w - max)), beta = min(1, temper
+ * / (max - mean)); each workgroup's gradient is one partial row, summed in
+ * a fixed order, so training is bit-reproducible. */
+#define ILE_PROP_NPARAM 60880
+
+typedef struct {
+    double d_min_mpc, d_max_mpc, t_ref_max_s;   /* prior support            */
+    double sigma_floor;      /* <= 0: 1e-3                                    */
+    uint64_t seed;           /* initial weights                               */
+    int32_t device;
+    void *stream;            /* hipStream_t, or NULL for a new one            */
+} ile_prop_config;
+
+typedef struct {
+    int32_t steps;           /* Adam steps (<= 0: 1000)                       */
+    int32_t batch;           /* minibatch (<= 0: 4096)                        */
+    double lr;               /* (<= 0: 1e-3)                                  */
+    double temper;           /* tempering scale (<= 0: 10)                    */
+    uint64_t seed;           /* minibatch draws                               */
+    int32_t fit_transform;   /* 1: fit the transform to the data first:
+                                weighted circular means of ra, psi, phi as
+                                origins, weighted mean / standard deviation
+                                of z (>= 1e-3) as mean / scale            */
+} ile_prop_train_opts;
+
+ile_status ile_prop_create(const ile_prop_config *cfg, ile_prop **out);
+/* Host float32 arrays of ILE_PROP_NPARAM values (set: masked entries are
+ * zeroed, Adam state reset). */
+ile_status ile_prop_set_params(ile_prop *p, const float *params);
+ile_status ile_prop_get_params(ile_prop *p, float *params);
+ile_status ile_prop_set_transform(ile_prop *p, const double origin[3], const double mean[7],
+                                  const double scale[7]);
+ile_status ile_prop_get_transform(ile_prop *p, double origin[3], double mean[7],
+                                  double scale[7]);
+/* Fit the transform to device samples x_dev[7][ld] with log-weights lnw_dev. */
+ile_status ile_prop_fit_transform_dev(ile_prop *p, const double *x_dev, int64_t ld,
+                                      const double *lnw_dev, int64_t n, double temper);
+/* Loss -sum w ln q(z~) / sum w of n device samples (w_dev NULL: all 1) and
+ * its gradient (device float grad_dev[ILE_PROP_NPARAM], may be NULL; masked
+ * entries 0); loss to the host (may be NULL).  n <= 2^20. */
+ile_status ile_prop_grad_dev(ile_prop *p, const double *x_dev, int64_t ld, const double *w_dev,
+                             int64_t n, float *grad_dev, double *loss);
+/* Train on n device samples with log-weights ln w = lnLmargT + ln p - ln q. */
+ile_status ile_prop_train_dev(ile_prop *p, const double *x_dev, int64_t ld,
+                              const double *lnw_dev, int64_t n,
+                              const ile_prop_train_opts *opts, double *final_loss);
+/* ln q of device samples; with mix_ctx and eps > 0 the density of the
+ * defensive mixture (1 - eps) q_net + eps q_hist (the context's histograms,
+ * which must share the proposal's stream). */
+ile_status ile_prop_logpdf_dev(ile_prop *p, const ile_ctx *mix_ctx, double eps,
+                               const double *x_dev, int64_t ld, int64_t n, double *ln_q_dev);
+/* Draw samples first .. first+n-1 of stream `seed` into x_dev[7][ld], with
+ * ln p (may be NULL) and ln q of the (mixture) proposal. */
+ile_status ile_prop_sample_dev(ile_prop *p, const ile_ctx *mix_ctx, double eps, uint64_t seed,
+                               int64_t first, int64_t n, double *x_dev, int64_t ld,
+                               double *ln_p_dev, double *ln_q_dev);
+ile_status ile_prop_sync(ile_prop *p);
+/* Device time in ms of the last training or draw (HIP events). */
+double ile_prop_last_ms(ile_prop *p);
+void ile_prop_destroy(ile_prop *p);
+const char *ile_prop_last_error(const ile_prop *p);
 
 /* ------------------------------------------------------ batched form
  * Many intrinsic points (Sec. III.B: each ILE instance loops over many
@@ -297,6 +432,10 @@ ile_status ile_batch_autotune(ile_batch *b, int64_t n_per_point, const char *cac
 double ile_batch_last_ms(const ile_batch *b);
 void ile_batch_destroy(ile_batch *b);
 const char *ile_batch_last_error(const ile_batch *b);
+
+/* The context's stream (hipStream_t): the one its device calls are
+ * ordered on, to share with a proposal. */
+ile_status ile_get_stream(const ile_ctx *ctx, void **stream_out);
 
 /* Wait for the context's stream; report a sticky device-side error. */
 ile_status ile_sync(ile_ctx *ctx);

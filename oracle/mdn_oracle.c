@@ -195,8 +195,13 @@ void orc_mdn_loss_grad(const double *params, const orc_mdn_transform *tr, const 
 {
     const double *W2 = params + ORC_MDN_OFF_W2, *W3 = params + ORC_MDN_OFF_W3;
     memset(grad, 0, sizeof(double) * ORC_MDN_NPARAM);
+    /* samples outside the transform's domain (a u of 0 or 1) carry no weight */
     double wsum = 0.0, lsum = 0.0;
-    for (int64_t i = 0; i < n; i++) wsum += w ? w[i] : 1.0;
+    for (int64_t i = 0; i < n; i++) {
+        double xi[7], z[7];
+        for (int d = 0; d < 7; d++) xi[d] = x[d * ld + i];
+        if (orc_mdn_to_z(tr, xi, z) != -INFINITY) wsum += w ? w[i] : 1.0;
+    }
     for (int64_t i = 0; i < n; i++) {
         const double wi = (w ? w[i] : 1.0) / wsum;
         double xi[7], z[7];
@@ -250,17 +255,21 @@ void orc_mdn_loss_grad(const double *params, const orc_mdn_transform *tr, const 
 void orc_mdn_fit_transform(const double *x, int64_t ld, const double *lnw, int64_t n,
                            double temper, orc_mdn_transform *tr)
 {
+    /* samples whose ln w is not finite carry no weight */
     double mx = -INFINITY;
     long double mean = 0.0L;
+    int64_t cnt = 0;
     for (int64_t i = 0; i < n; i++) {
+        if (!isfinite(lnw[i])) continue;
         mx = fmax(mx, lnw[i]);
         mean += lnw[i];
+        cnt++;
     }
-    mean /= (long double)n;
+    mean = cnt > 0 ? mean / (long double)cnt : 0.0L;
     double spread = mx - (double)mean;
     double beta = spread > 0 ? fmin(1.0, temper / spread) : 1.0;
     double *w = (double *)malloc(sizeof(double) * (size_t)n);
-    for (int64_t i = 0; i < n; i++) w[i] = exp(beta * (lnw[i] - mx));
+    for (int64_t i = 0; i < n; i++) w[i] = isfinite(lnw[i]) ? exp(beta * (lnw[i] - mx)) : 0.0;
     /* circular means of the periodic dimensions */
     const double period[3] = {2 * PI, PI, 2 * PI};
     for (int j = 0; j < 3; j++) {

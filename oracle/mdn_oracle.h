@@ -88,8 +88,8 @@ void orc_mdn_loss_grad(const double *params, const orc_mdn_transform *tr,
 /* Transform fit from weighted samples: tempered weights
  * w = exp(beta (lnw - max)), beta = min(1, temper/(max - mean)); origins =
  * weighted circular means; mean/scale = weighted mean and standard
- * deviation of z (scale floored at 1e-3). Sums in index order (long
- * double). */
+ * deviation of z (scale floored at 1e-3); max and mean over the finite
+ * ln w, non-finite ones weigh 0. Sums in index order (long double). */
 void orc_mdn_fit_transform(const double *x, int64_t ld, const double *lnw,
                            int64_t n, double temper, orc_mdn_transform *tr);
 

@@ -15,6 +15,7 @@ likelihood used to pin it, both written from the paper:
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 
 import numpy as np
@@ -246,13 +247,16 @@ def direct_lnL(data, model):
     return tot
 
 
-def injection_instance(base, h_lm, theta_inj, noise_sigma=0.0, rng=None):
+def injection_instance(base, h_lm, theta_inj, noise_sigma=0.0, rng=None, snr=None):
     """Physically consistent instance: the data d_k is the response to
     theta_inj (zero noise unless noise_sigma > 0), and Q, U, V are the
     white-noise inner products of Eq. (8) with circular shifts.
 
     Q index s of the instance corresponds to arrival lag s - n_q/2 samples
-    after the start of h_lm, matching t0 = -(n_q/2) dt.
+    after the start of h_lm, matching t0 = -(n_q/2) dt.  With snr, the
+    (noise-free) data are scaled to network SNR sqrt(sum_k <d_k|d_k>) = snr,
+    i.e. the injected distance becomes theta_inj[5] / scale
+    (inst.meta["d_inj"]).
     Returns (instance, data, injected lags)."""
     import copy
     inst = copy.copy(base)
@@ -267,6 +271,10 @@ def injection_instance(base, h_lm, theta_inj, noise_sigma=0.0, rng=None):
         lags.append(int(np.floor(x + 0.5)))
     lags = np.array(lags)
     data = detector_response(inst, h_lm, theta_inj, lags)
+    scale = 1.0
+    if snr is not None and snr > 0:
+        scale = snr / math.sqrt(sum(float(np.dot(d, d)) for d in data))
+        data = data * scale
     if noise_sigma > 0:
         data = data + noise_sigma * rng.standard_normal(data.shape)
     A = h_lm.T  # [i, lm]
@@ -279,6 +287,7 @@ def injection_instance(base, h_lm, theta_inj, noise_sigma=0.0, rng=None):
             # Q[s] = sum_i conj(h[(i - s) mod n]) d[i]: circular correlation
             Q[k, a] = np.fft.ifft(np.conj(np.fft.fft(h_lm[a])) * D)
     inst.Q, inst.U, inst.V = Q, U, V
+    inst.meta = dict(inst.meta, d_inj=theta_inj[5] / scale, rho2=float(sum(np.dot(d, d) for d in data)))
     return inst, data, lags
 
 

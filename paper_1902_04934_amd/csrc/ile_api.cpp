@@ -52,6 +52,8 @@ struct ile_ctx {
         red_tmp, parts, res, series;
     DevBuf hP, hC, bins, hist_tmp;  // adaptive proposal state and scratch
     int hist_nb = 0;
+    DevBuf trx, trw;                // training set of the learned sampler
+    ile_learned_info learned{};
     std::vector<hipEvent_t> ev;   // pairs around contraction launches
     int n_ev_used = 0;
     double last_ms = 0.0;
@@ -310,6 +312,13 @@ const void *ile_ctx_Q(const ile_ctx *c) { return c->Q.p; }
 const double *ile_ctx_U(const ile_ctx *c) { return (const double *)c->U.p; }
 const double *ile_ctx_V(const ile_ctx *c) { return (const double *)c->V.p; }
 ile_precision ile_ctx_precision(const ile_ctx *c) { return c->cfg.precision; }
+hipStream_t ile_ctx_stream(const ile_ctx *c) { return c->stream; }
+int ile_ctx_hist(const ile_ctx *c, const double **P, const double **C)
+{
+    *P = (const double *)c->hP.p;
+    *C = (const double *)c->hC.p;
+    return c->hP.p ? c->hist_nb : 0;
+}
 
 // ------------------------------------------------------------------ C ABI
 extern "C" {
@@ -520,6 +529,87 @@ ile_status ile_set_data(ile_ctx *c, const double *Q, int64_t n_q, double t0_s,
     if ((s = ensure(c, c->errflag, 16))) return s;
     HIP_TRY(c, hipMemset(c->errflag.p, 0, 16));
     c->have_data = true;
+    return ILE_OK;
+}
+
+ile_status ile_inject(ile_ctx *c, const double *h_lm, int64_t n_q, double t0_s,
+                      const ile_detector *dets, const double *theta, double snr,
+                      double *rho2_out, double *d_inj_out, double *Q_out, double *U_out,
+                      double *V_out)
+{
+    if (!c) return ILE_E_ARG;
+    begin_call(c);
+    if (!h_lm || !dets || !theta) return fail(c, ILE_E_ARG, "null pointer");
+    const int nd = c->cfg.n_det, nl = c->cfg.n_lm;
+    if (n_q < c->cfg.n_t || n_q > (1 << 24)) return fail(c, ILE_E_ARG, "n_q out of range");
+    for (int p = 0; p < 7; p++)
+        if (!std::isfinite(theta[p])) return fail(c, ILE_E_ARG, "theta not finite");
+    if (!(theta[5] > 0) || std::fabs(theta[4]) > 1.0 || !(snr >= 0) || !std::isfinite(snr))
+        return fail(c, ILE_E_ARG, "bad injected parameters or snr");
+    for (size_t i = 0; i < (size_t)2 * nl * n_q; i++)
+        if (!std::isfinite(h_lm[i])) return fail(c, ILE_E_NUMERIC, "h_lm not finite");
+    ile_geom g = c->g;
+    for (int k = 0; k < nd; k++) {
+        const ile_detector &d = dets[k];
+        if (!std::isfinite(d.lat_deg) || !std::isfinite(d.lon_deg) ||
+            !std::isfinite(d.xarm_az_deg) || std::fabs(d.lat_deg) > 90.0)
+            return fail(c, ILE_E_ARG, "detector %d invalid", k);
+        detector_frame(d, c->cfg.earth_radius_m, g.r[k], g.D[k]);
+    }
+    g.n_q = (int)n_q;
+    g.t0 = t0_s;
+    HIP_TRY(c, hipSetDevice(c->cfg.device));
+    const size_t n = (size_t)n_q;
+    DevBuf hd, th, dd, Qd, Ud, Vd;
+    auto cleanup = [&]() {
+        for (DevBuf *b : {&hd, &th, &dd, &Qd, &Ud, &Vd}) release(*b);
+    };
+    ile_status s = ILE_OK;
+    if ((s = ensure(c, hd, 16 * nl * n)) || (s = ensure(c, th, 7 * 8)) ||
+        (s = ensure(c, dd, 8 * nd * n)) || (s = ensure(c, Qd, 16 * (size_t)nd * nl * n)) ||
+        (s = ensure(c, Ud, 16 * (size_t)nl * nl)) || (s = ensure(c, Vd, 16 * (size_t)nl * nl))) {
+        cleanup();
+        return s;
+    }
+    std::vector<double> d((size_t)nd * n), Q((size_t)2 * nd * nl * n),
+        U1((size_t)2 * nl * nl), V1((size_t)2 * nl * nl);
+    hipError_t e = hipMemcpyAsync(hd.p, h_lm, 16 * nl * n, hipMemcpyHostToDevice, c->stream);
+    if (!e) e = hipMemcpyAsync(th.p, theta, 7 * 8, hipMemcpyHostToDevice, c->stream);
+    if (!e) e = ile_launch_inject(g, (const double *)hd.p, (int)n, (const double *)th.p,
+                                  (double *)dd.p, c->stream);
+    if (!e) e = hipStreamSynchronize(c->stream);
+    if (!e) e = hipMemcpy(d.data(), dd.p, 8 * d.size(), hipMemcpyDeviceToHost);
+    long double r2 = 0.0L;
+    for (double v : d) r2 += (long double)v * v;
+    const double rho2 = (double)r2;
+    const double scale = (snr > 0 && rho2 > 0) ? snr / std::sqrt(rho2) : 1.0;
+    if (!e) e = ile_launch_inject_qv(nd, nl, (int)n, (const double *)hd.p, (const double *)dd.p,
+                                     scale, (double *)Qd.p, (double *)Ud.p, (double *)Vd.p,
+                                     c->stream);
+    if (!e) e = hipStreamSynchronize(c->stream);
+    if (!e) e = hipMemcpy(Q.data(), Qd.p, 8 * Q.size(), hipMemcpyDeviceToHost);
+    if (!e) e = hipMemcpy(U1.data(), Ud.p, 8 * U1.size(), hipMemcpyDeviceToHost);
+    if (!e) e = hipMemcpy(V1.data(), Vd.p, 8 * V1.size(), hipMemcpyDeviceToHost);
+    cleanup();
+    if (e) return fail(c, ILE_E_DEVICE, "injection: %s", hipGetErrorString(e));
+    // white noise: the same U, V at every detector; U exactly Hermitian
+    std::vector<double> U((size_t)2 * nd * nl * nl), V(U.size());
+    for (int k = 0; k < nd; k++)
+        for (int a = 0; a < nl; a++)
+            for (int b = 0; b < nl; b++) {
+                const size_t o = 2 * (((size_t)k * nl + a) * nl + b), ab = 2 * ((size_t)a * nl + b),
+                             ba = 2 * ((size_t)b * nl + a);
+                U[o] = 0.5 * (U1[ab] + U1[ba]);
+                U[o + 1] = 0.5 * (U1[ab + 1] - U1[ba + 1]);
+                V[o] = V1[ab];
+                V[o + 1] = V1[ab + 1];
+            }
+    if ((s = ile_set_data(c, Q.data(), n_q, t0_s, U.data(), V.data(), dets))) return s;
+    if (rho2_out) *rho2_out = rho2 * scale * scale;
+    if (d_inj_out) *d_inj_out = theta[5] / scale;
+    if (Q_out) memcpy(Q_out, Q.data(), 8 * Q.size());
+    if (U_out) memcpy(U_out, U.data(), 8 * U.size());
+    if (V_out) memcpy(V_out, V.data(), 8 * V.size());
     return ILE_OK;
 }
 
@@ -787,13 +877,133 @@ ile_status ile_hist_refit_dev(ile_ctx *c, const int32_t *bins, int64_t ld, const
     return refit_impl(c, bins, ld, lnL, lp, lq, N, floor_w, temper);
 }
 
+// Sampler LEARNED: adaptive rounds (training set), training, then chunks
+// from the defensive mixture; falls back to the adaptive sampler if the
+// first learned chunk's n_eff is below the threshold.
+static ile_status run_learned(ile_ctx *c, const ile_run_opts *o, ile_result *out,
+                              int64_t *n_chunks_out)
+{
+    ile_status s;
+    if (!o->prop) return fail(c, ILE_E_ARG, "sampler LEARNED needs a proposal");
+    if (ile_prop_stream(o->prop) != c->stream)
+        return fail(c, ILE_E_ARG, "the proposal must use the context's stream");
+    if (o->max_samples <= 0 || !(o->d_min_mpc > 0) || !(o->d_max_mpc > o->d_min_mpc) ||
+        !std::isfinite(o->d_max_mpc))
+        return fail(c, ILE_E_ARG, "bad run options");
+    const int64_t chunk = o->chunk > 0 ? o->chunk : 100000;
+    const int rounds = o->adapt_chunks > 0 ? o->adapt_chunks : 3;
+    const int nb = o->n_bins > 0 ? o->n_bins : 50;
+    const double floor_w = o->floor >= 0 ? o->floor : 0.1;
+    const double temper = o->temper > 0 ? o->temper : 10.0;
+    const double eps = o->eps >= 0 ? o->eps : 0.1;
+    const double fb = o->fallback_neff >= 0 ? o->fallback_neff : 1000.0;
+    if (floor_w > 1 || eps >= 1) return fail(c, ILE_E_ARG, "floor > 1 or eps >= 1");
+    const int64_t ntr = (int64_t)rounds * chunk;
+    if (ntr > ((int64_t)1 << 30)) return fail(c, ILE_E_ARG, "training set too large");
+    const int64_t max_chunks = (o->max_samples + chunk - 1) / chunk;
+    if (max_chunks > (1 << 22)) return fail(c, ILE_E_ARG, "too many chunks");
+    if ((s = hist_init(c, nb, o->reset != 0))) return s;
+    if ((s = ensure(c, c->smp, (size_t)chunk * 7 * sizeof(double)))) return s;
+    if ((s = ensure(c, c->out, (size_t)chunk * sizeof(double)))) return s;
+    if ((s = ensure(c, c->lnp, (size_t)chunk * sizeof(double)))) return s;
+    if ((s = ensure(c, c->lnq, (size_t)chunk * sizeof(double)))) return s;
+    if ((s = ensure(c, c->bins, (size_t)chunk * 2 * sizeof(int32_t)))) return s;
+    if ((s = ensure(c, c->parts, (size_t)std::max<int64_t>(max_chunks, 1) * 5 * sizeof(double))))
+        return s;
+    if ((s = ensure(c, c->trx, (size_t)ntr * 7 * sizeof(double)))) return s;
+    if ((s = ensure(c, c->trw, (size_t)ntr * sizeof(double)))) return s;
+    if ((s = ensure_work(c, chunk))) return s;
+    c->learned = ile_learned_info{};
+    double *smp = (double *)c->smp.p, *lp = (double *)c->lnp.p, *lq = (double *)c->lnq.p;
+    double *trx = (double *)c->trx.p, *trw = (double *)c->trw.p;
+    // 1. adaptive rounds: the training set
+    for (int rd = 0; rd < rounds; rd++) {
+        const int64_t first = (int64_t)rd * chunk;
+        HIP_TRY(c, ile_launch_hist_draw(o->seed, first, chunk, nb, (const double *)c->hP.p,
+                                        (const double *)c->hC.p, o->d_min_mpc, o->d_max_mpc,
+                                        c->cfg.t_ref_max_s, smp, chunk, lp, lq,
+                                        (int32_t *)c->bins.p, c->stream));
+        if ((s = run_eval(c, smp, chunk, (double *)c->out.p, nullptr))) return s;
+        HIP_TRY(c, hipMemcpy2DAsync(trx + first, (size_t)ntr * sizeof(double), smp,
+                                    (size_t)chunk * sizeof(double), (size_t)chunk * sizeof(double),
+                                    7, hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(c, ile_launch_lnw((const double *)c->out.p, lp, lq, chunk, trw + first,
+                                  c->stream));
+        if ((s = refit_impl(c, (const int32_t *)c->bins.p, chunk, (const double *)c->out.p, lp,
+                            lq, chunk, floor_w, temper)))
+            return s;
+    }
+    // 2. training
+    ile_prop_train_opts to{};
+    to.steps = o->train_steps;
+    to.batch = o->train_batch;
+    to.lr = o->lr;
+    to.temper = temper;
+    to.seed = o->seed;
+    to.fit_transform = 1;
+    double loss = 0.0;
+    if (ile_prop_train_dev(o->prop, trx, ntr, trw, ntr, &to, &loss) != ILE_OK)
+        return fail(c, ILE_E_DEVICE, "training failed: %s", ile_prop_last_error(o->prop));
+    c->learned.n_train_samples = ntr;
+    c->learned.train_ms = ile_prop_last_ms(o->prop);
+    c->learned.final_loss = loss;
+    // 3. chunks from the defensive mixture
+    const ile_mdn_mix mix{nb, (const double *)c->hP.p, (const double *)c->hC.p, eps};
+    bool learned = true;
+    int64_t done = 0, ci = 0;
+    double r[6] = {0, 0, 0, 0, 0, 0};
+    while (done < o->max_samples) {
+        const int64_t n = std::min(chunk, o->max_samples - done);
+        const int64_t first = ntr + done;
+        if (learned) {
+            HIP_TRY(c, ile_launch_mdn_sample(ile_prop_dev(o->prop), mix, o->seed, first, n, smp,
+                                             n, lp, lq, ile_prop_grid(o->prop), c->stream));
+        } else {
+            HIP_TRY(c, ile_launch_hist_draw(o->seed, first, n, nb, (const double *)c->hP.p,
+                                            (const double *)c->hC.p, o->d_min_mpc,
+                                            o->d_max_mpc, c->cfg.t_ref_max_s, smp, n, lp, lq,
+                                            (int32_t *)c->bins.p, c->stream));
+        }
+        if ((s = run_eval(c, smp, n, (double *)c->out.p, nullptr))) return s;
+        HIP_TRY(c, ile_launch_reduce((const double *)c->out.p, lp, lq, n,
+                                     (double *)c->red_tmp.p, (double *)c->parts.p + 5 * ci,
+                                     c->stream));
+        if (!learned && (s = refit_impl(c, (const int32_t *)c->bins.p, n, (const double *)c->out.p,
+                                        lp, lq, n, floor_w, temper)))
+            return s;
+        HIP_TRY(c, ile_launch_finish((const double *)c->parts.p, (int)(ci + 1),
+                                     (double *)c->res.p, c->stream));
+        done += n;
+        ci++;
+        if (learned) c->learned.n_learned_samples += n;
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        HIP_TRY(c, hipMemcpy(r, c->res.p, sizeof(r), hipMemcpyDeviceToHost));
+        if (learned && ci == 1 && fb > 0 && r[1] < fb) {
+            learned = false;
+            c->learned.fell_back = 1;
+        }
+        if (o->n_eff_target > 0 && r[1] >= o->n_eff_target) break;
+    }
+    if ((s = finish_call(c))) return s;
+    HIP_TRY(c, hipMemcpy(r, c->res.p, sizeof(r), hipMemcpyDeviceToHost));
+    copy_result(r, out);
+    if (n_chunks_out) *n_chunks_out = ci;
+    return ILE_OK;
+}
+
+ile_status ile_last_learned_info(const ile_ctx *c, ile_learned_info *out)
+{
+    if (!c || !out) return ILE_E_ARG;
+    *out = c->learned;
+    return ILE_OK;
+}
+
 ile_status ile_run(ile_ctx *c, const ile_run_opts *o, ile_result *out, int64_t *n_chunks_out)
 {
     ile_status s = check_ready(c);
     if (s) return s;
     if (!o || !out) return fail(c, ILE_E_ARG, "null pointer");
-    if (o->sampler == ILE_SAMPLER_LEARNED)
-        return fail(c, ILE_E_UNSUPPORTED, "learned proposal not available in ile_run");
+    if (o->sampler == ILE_SAMPLER_LEARNED) return run_learned(c, o, out, n_chunks_out);
     if (o->sampler != ILE_SAMPLER_PRIOR && o->sampler != ILE_SAMPLER_ADAPTIVE)
         return fail(c, ILE_E_ARG, "unknown sampler");
     if (o->max_samples <= 0 || !(o->d_min_mpc > 0) || !(o->d_max_mpc > o->d_min_mpc) ||
@@ -861,6 +1071,13 @@ ile_status ile_run(ile_ctx *c, const ile_run_opts *o, ile_result *out, int64_t *
     return ILE_OK;
 }
 
+ile_status ile_get_stream(const ile_ctx *c, void **stream_out)
+{
+    if (!c || !stream_out) return ILE_E_ARG;
+    *stream_out = (void *)c->stream;
+    return ILE_OK;
+}
+
 ile_status ile_sync(ile_ctx *c)
 {
     if (!c) return ILE_E_ARG;
@@ -906,7 +1123,7 @@ void ile_destroy(ile_ctx *c)
     for (DevBuf *b : {&c->Q, &c->U, &c->V, &c->smp, &c->out, &c->lnp, &c->lnq,
                       &c->shifts, &c->keys, &c->perm, &c->hist, &c->scan_tmp,
                       &c->errflag, &c->red_tmp, &c->parts, &c->res, &c->series,
-                      &c->hP, &c->hC, &c->bins, &c->hist_tmp})
+                      &c->hP, &c->hC, &c->bins, &c->hist_tmp, &c->trx, &c->trw})
         release(*b);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);

@@ -11,6 +11,7 @@
 #include <math.h>
 
 #include "ile_internal.h"
+#include "ile_rng.h"
 
 namespace {
 
@@ -29,29 +30,7 @@ __device__ inline int point_of(const int64_t *offs, int n_points, int64_t i)
     return lo;
 }
 
-__device__ inline void philox(uint32_t c[4], uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; r++) {
-        if (r > 0) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
-        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
-        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-    }
-}
-
-__device__ inline double u53(uint32_t w0, uint32_t w1)
-{
-    return ((double)(w0 >> 5) * 67108864.0 + (double)(w1 >> 6) + 0.5) /
-           9007199254740992.0;
-}
+using ile_rng::u53;
 
 // prior draw: point p uses the Philox stream of key seed + p (the stream of
 // ile_draw_prior_dev), sample t of the point counter t
@@ -67,15 +46,7 @@ __global__ __launch_bounds__(256) void k_prior_multi(const uint64_t *seed_dev,
     const int64_t o = offs[p], n = offs[p + 1] - o, t = i - o;
     const uint64_t seed = *seed_dev + (uint64_t)p;
     uint32_t w[16];
-#pragma unroll
-    for (uint32_t b = 0; b < 4; b++) {
-        uint32_t c[4] = {(uint32_t)t, (uint32_t)((uint64_t)t >> 32), b, 0x494C4531u};
-        philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-        w[4 * b] = c[0];
-        w[4 * b + 1] = c[1];
-        w[4 * b + 2] = c[2];
-        w[4 * b + 3] = c[3];
-    }
+    ile_rng::prior_words(seed, (uint64_t)t, w);
     double *s = smp + 7 * o;
     {
 #pragma clang fp contract(off)

@@ -127,3 +127,114 @@ hipError_t ile_launch_reduce_points(const double *out, const int64_t *offs, int 
                                     double *res, hipStream_t st);
 hipError_t ile_launch_to_bf16_split(const double *Q, int64_t n, void *dst,
                                     hipStream_t st);
+
+// ------------------------------------------------ learned proposal (MDN)
+// Network sizes and the flat parameter layout (W1 | b1 | W2 | b2 | W3 | b3,
+// row-major, masked entries held at zero) documented in ile.h.
+#define ILE_MDN_D 7
+#define ILE_MDN_H 128
+#define ILE_MDN_C 16
+#define ILE_MDN_O 336
+#define ILE_MDN_OFF_W1 0
+#define ILE_MDN_OFF_B1 896
+#define ILE_MDN_OFF_W2 1024
+#define ILE_MDN_OFF_B2 17408
+#define ILE_MDN_OFF_W3 17536
+#define ILE_MDN_OFF_B3 60544
+#define ILE_MDN_NPARAM 60880
+#define ILE_MDN_W3T_LD 384    // rows of the transposed W3 copy, zero past 336
+#define ILE_MDN_NPART 60928   // per-workgroup partial: grads, loss sum, weight sum
+#define ILE_MDN_TILE 64       // samples per workgroup pass
+
+// MADE masks: hidden unit k has degree k mod 6; unit k sees inputs
+// i <= deg(k); layer-2 unit k2 sees k1 with deg(k1) <= deg(k2); output o
+// (dimension o / 48) sees units with deg(k) < o / 48.  Biases are free.
+__host__ __device__ inline bool ile_mdn_trainable(int j)
+{
+    if (j < 0 || j >= ILE_MDN_NPARAM) return false;
+    if (j < ILE_MDN_OFF_B1) return (j % ILE_MDN_D) <= (j / ILE_MDN_D) % 6;
+    if (j < ILE_MDN_OFF_W2) return true;
+    if (j < ILE_MDN_OFF_B2) {
+        const int q = j - ILE_MDN_OFF_W2;
+        return (q % ILE_MDN_H) % 6 <= (q / ILE_MDN_H) % 6;
+    }
+    if (j < ILE_MDN_OFF_W3) return true;
+    if (j < ILE_MDN_OFF_B3) {
+        const int q = j - ILE_MDN_OFF_W3;
+        return (q % ILE_MDN_H) % 6 < (q / ILE_MDN_H) / (3 * ILE_MDN_C);
+    }
+    return true;
+}
+
+// Transform between the sample vector and the network's inputs.
+struct ile_mdn_tr {
+    double origin[3];   // ra, psi, phi origins
+    double mean[7], scale[7];
+    double d_min, d_max, t_ref_max, sigma_floor;
+};
+
+// Device state of one proposal.
+struct ile_mdn_dev {
+    float *theta, *m, *v;               // [NPARAM] master weights and Adam moments
+    __bf16 *W2b, *W3b;                  // [o][k] copies (forward operands)
+    __bf16 *W2t, *W3t;                  // [k][o] copies (backward operands)
+    ile_mdn_tr *tr;                     // transform
+};
+
+// Defensive mixture with the histogram proposal (nb = 0 or eps = 0: none).
+struct ile_mdn_mix {
+    int nb;
+    const double *P, *C;   // histogram state [2][nb], [2][nb+1]
+    double eps;
+};
+
+hipError_t ile_launch_mdn_cast(const ile_mdn_dev &M, hipStream_t st);
+// ln q of n samples x[7][ld] (optionally mixed), or draws of n samples
+// (counters first..first+n-1 of key seed) with their ln p and ln q.
+hipError_t ile_launch_mdn_logpdf(const ile_mdn_dev &M, const ile_mdn_mix &mix,
+                                 const double *x, int64_t ld, int64_t n, double *ln_q,
+                                 int grid, hipStream_t st);
+hipError_t ile_launch_mdn_sample(const ile_mdn_dev &M, const ile_mdn_mix &mix,
+                                 uint64_t seed, int64_t first, int64_t n, double *x,
+                                 int64_t ld, double *ln_p, double *ln_q, int grid,
+                                 hipStream_t st);
+// Training pieces.  fit: transform + tempering from (x, lnw); prepare: z~
+// and tempered weights; cdf: inclusive prefix sums of the weights.
+hipError_t ile_launch_mdn_fit(const double *x, int64_t ld, const double *lnw, int64_t n,
+                              double temper, ile_mdn_tr *tr, double *stats, hipStream_t st);
+hipError_t ile_launch_mdn_prepare(const ile_mdn_tr *tr, const double *x, int64_t ld,
+                                  const double *lnw, int64_t n, const double *stats,
+                                  float *z, double *w, hipStream_t st);
+// the same with given weights w_in (NULL: 1) instead of tempered ones
+hipError_t ile_launch_mdn_prepare_w(const ile_mdn_tr *tr, const double *x, int64_t ld,
+                                    const double *w_in, int64_t n, float *z, double *w,
+                                    hipStream_t st);
+hipError_t ile_launch_mdn_cdf(const double *w, int64_t n, double *cdf, hipStream_t st);
+hipError_t ile_launch_mdn_draw_idx(uint64_t seed, int64_t step, int batch, const double *cdf,
+                                   int64_t n, int32_t *idx, hipStream_t st);
+// Forward + backward of a batch: per-workgroup partials [grid][NPART].
+hipError_t ile_launch_mdn_grad(const ile_mdn_dev &M, const float *z, int64_t ldz,
+                               const int32_t *idx, const double *w, int batch, float *part,
+                               hipStream_t st);
+// Reduce the partials in fixed order; mask; write the gradient (grad may be
+// NULL) and the loss; if adam, take one Adam step number `step` (1-based).
+hipError_t ile_launch_mdn_update(const ile_mdn_dev &M, const float *part, int n_part,
+                                 float *grad, double *loss, bool adam, int64_t step, double lr,
+                                 hipStream_t st);
+hipError_t ile_launch_lnw(const double *lnL, const double *ln_p, const double *ln_q, int64_t n,
+                          double *lnw, hipStream_t st);
+
+// cross-object accessors (defined in ile_api.cpp / ile_prop_api.cpp)
+hipStream_t ile_ctx_stream(const ile_ctx *c);
+int ile_ctx_hist(const ile_ctx *c, const double **P, const double **C);   // nb, or 0
+const ile_mdn_dev &ile_prop_dev(const ile_prop *p);
+hipStream_t ile_prop_stream(const ile_prop *p);
+int ile_prop_grid(const ile_prop *p);
+
+// Zero-noise injection (ile_kernels.hip): detector responses d[n_det][n] of
+// theta (device, 7 doubles), then Q [n_det][n_lm][n] (scaled), U and V
+// [n_lm][n_lm] (complex interleaved).
+hipError_t ile_launch_inject(const ile_geom &g, const double *h, int n, const double *theta,
+                             double *d, hipStream_t st);
+hipError_t ile_launch_inject_qv(int n_det, int n_lm, int n, const double *h, const double *d,
+                                double scale, double *Q, double *U, double *V, hipStream_t st);

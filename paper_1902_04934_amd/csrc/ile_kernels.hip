@@ -20,6 +20,7 @@
 #include <math.h>
 
 #include "ile_internal.h"
+#include "ile_rng.h"
 
 namespace {
 
@@ -111,6 +112,103 @@ __device__ inline bool sample_ok(const ile_geom &g, const double th[7])
     for (int p = 0; p < 7; p++) fin = fin && isfinite(th[p]);
     return fin && th[5] > 0.0 && th[4] >= -1.0 && th[4] <= 1.0 &&
            fabs(th[6]) <= g.t_ref_max;
+}
+
+// ------------------------------------------------------------- injection
+// Zero-noise injection with a white unit-variance noise spectrum, so the
+// inner product of Eq. (2) is <a|b> = sum_i conj(a_i) b_i (circular).
+// Detector response to theta (Eqs. (5), (6) and the response below Eq. (6)):
+//   d_k[i] = Re(F_k (D_ref/D) sum_a Y_a h_a[(i - lag_k) mod n]),
+//   lag_k  = floor((t_ref + tau_k - t0)/dt + 1/2)  (the window rounding).
+__global__ __launch_bounds__(256) void k_inject_resp(ile_geom g, const double2 *__restrict__ h,
+                                                     int n, const double *__restrict__ th,
+                                                     double *d)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (int64_t)g.n_det * n) return;
+    const int k = (int)(t / n), i = (int)(t % n);
+    double fp, fx;
+    antenna_dev(g, k, th[0], th[1], th[2], fp, fx);
+    const double tau = delay_dev(g, k, th[0], th[1]);
+    double x;
+    {
+#pragma clang fp contract(off)
+        x = (th[6] + tau - g.t0) / g.dt;
+    }
+    const int64_t lag = (int64_t)floor(x + 0.5);
+    int64_t src = ((int64_t)i - lag) % n;
+    if (src < 0) src += n;
+    const double kappa = g.d_ref / th[5];
+    double re = 0.0, im = 0.0;
+    for (int a = 0; a < g.n_lm; a++) {
+        const double2 y = sylm_dev(g, a, th[4], th[3]);
+        const double2 v = h[(size_t)a * n + src];
+        re += y.x * v.x - y.y * v.y;
+        im += y.x * v.y + y.y * v.x;
+    }
+    // Re(F z) with F = F+ + i Fx
+    d[t] = kappa * (fp * re - fx * im);
+}
+
+// Q_k,a[s] = scale * sum_i conj(h_a[(i - s) mod n]) d_k[i]  (Eq. (8)): one
+// workgroup per (k, a) and 256 consecutive s; d and the needed 511 h values
+// of each 256-wide chunk of i are staged in LDS; sums run in i order.
+__global__ __launch_bounds__(256) void k_inject_corr(int n_lm, int n, const double2 *__restrict__ h,
+                                                     const double *__restrict__ d, double scale,
+                                                     double2 *Q)
+{
+    __shared__ double sd[256];
+    __shared__ double2 sh[512];
+    const int ka = blockIdx.y, k = ka / n_lm, a = ka % n_lm;
+    const int s0 = blockIdx.x * 256, t = threadIdx.x, s = s0 + t;
+    double re = 0.0, im = 0.0;
+    for (int i0 = 0; i0 < n; i0 += 256) {
+        sd[t] = i0 + t < n ? d[(size_t)k * n + i0 + t] : 0.0;
+        for (int j = t; j < 511; j += 256) {
+            int64_t idx = ((int64_t)i0 - s0 - 255 + j) % n;
+            if (idx < 0) idx += n;
+            sh[j] = h[(size_t)a * n + idx];
+        }
+        __syncthreads();
+        for (int ii = 0; ii < 256; ii++) {
+            const double2 v = sh[ii - t + 255];
+            re += v.x * sd[ii];
+            im -= v.y * sd[ii];
+        }
+        __syncthreads();
+    }
+    if (s < n) Q[(size_t)ka * n + s] = make_double2(scale * re, scale * im);
+}
+
+// U_ab = sum_i conj(h_a[i]) h_b[i], V_ab = sum_i h_a[i] h_b[i] (Eq. (8));
+// one workgroup per (a, b), fixed-order tree sum.
+__global__ __launch_bounds__(256) void k_inject_gram(int n_lm, int n, const double2 *__restrict__ h,
+                                                     double2 *U, double2 *V)
+{
+    __shared__ double red[4][256];
+    const int a = blockIdx.x / n_lm, b = blockIdx.x % n_lm, t = threadIdx.x;
+    double ur = 0, ui = 0, vr = 0, vi = 0;
+    for (int i = t; i < n; i += 256) {
+        const double2 x = h[(size_t)a * n + i], y = h[(size_t)b * n + i];
+        ur += x.x * y.x + x.y * y.y;
+        ui += x.x * y.y - x.y * y.x;
+        vr += x.x * y.x - x.y * y.y;
+        vi += x.x * y.y + x.y * y.x;
+    }
+    red[0][t] = ur;
+    red[1][t] = ui;
+    red[2][t] = vr;
+    red[3][t] = vi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int q = 0; q < 4; q++) red[q][t] += red[q][t + w];
+        __syncthreads();
+    }
+    if (t == 0) {
+        U[blockIdx.x] = make_double2(red[0][0], red[1][0]);
+        V[blockIdx.x] = make_double2(red[2][0], red[3][0]);
+    }
 }
 
 // ------------------------------------------------------------------ prep
@@ -895,29 +993,7 @@ __global__ __launch_bounds__(NT) void k_contract_batched(
 }
 
 // --------------------------------------------------------------- prior
-__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; r++) {
-        if (r > 0) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
-        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
-        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-    }
-}
-
-__device__ inline double u53(uint32_t w0, uint32_t w1)
-{
-    return ((double)(w0 >> 5) * 67108864.0 + (double)(w1 >> 6) + 0.5) /
-           9007199254740992.0;
-}
+using ile_rng::u53;
 
 __global__ __launch_bounds__(256) void k_prior(uint64_t seed, int64_t first,
                                                int64_t N, double d_min,
@@ -929,15 +1005,7 @@ __global__ __launch_bounds__(256) void k_prior(uint64_t seed, int64_t first,
     if (t >= N) return;
     const uint64_t i = (uint64_t)(first + t);
     uint32_t w[16];
-#pragma unroll
-    for (uint32_t b = 0; b < 4; b++) {
-        uint32_t c[4] = {(uint32_t)i, (uint32_t)(i >> 32), b, 0x494C4531u};
-        philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-        w[4 * b] = c[0];
-        w[4 * b + 1] = c[1];
-        w[4 * b + 2] = c[2];
-        w[4 * b + 3] = c[3];
-    }
+    ile_rng::prior_words(seed, i, w);
     {
 #pragma clang fp contract(off)
     const double v3 = d_max * d_max * d_max - d_min * d_min * d_min;
@@ -1313,4 +1381,25 @@ hipError_t ile_launch_finish(const double *partials, int n_part, double *result,
 hipError_t ile_launch_to_bf16_split(const double *, int64_t, void *, hipStream_t)
 {
     return hipErrorNotSupported;
+}
+
+hipError_t ile_launch_inject(const ile_geom &g, const double *h, int n, const double *theta,
+                             double *d, hipStream_t st)
+{
+    const int64_t tot = (int64_t)g.n_det * n;
+    hipLaunchKernelGGL(k_inject_resp, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, g,
+                       (const double2 *)h, n, theta, d);
+    return hipGetLastError();
+}
+
+hipError_t ile_launch_inject_qv(int n_det, int n_lm, int n, const double *h, const double *d,
+                                double scale, double *Q, double *U, double *V, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_inject_corr, dim3((unsigned)((n + 255) / 256), (unsigned)(n_det * n_lm)),
+                       dim3(256), 0, st, n_lm, n, (const double2 *)h, d, scale, (double2 *)Q);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_inject_gram, dim3((unsigned)(n_lm * n_lm)), dim3(256), 0, st, n_lm, n,
+                       (const double2 *)h, (double2 *)U, (double2 *)V);
+    return hipGetLastError();
 }

@@ -17,52 +17,12 @@
 #include <algorithm>
 
 #include "ile_internal.h"
+#include "ile_rng.h"
 
 namespace {
 
-constexpr double kPi = 3.141592653589793238463;
-constexpr double kTwoPi = 6.283185307179586476925;
 
-__device__ inline void philox(uint32_t c[4], uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; r++) {
-        if (r > 0) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
-        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
-        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-    }
-}
-
-__device__ inline double u53(uint32_t w0, uint32_t w1)
-{
-    return ((double)(w0 >> 5) * 67108864.0 + (double)(w1 >> 6) + 0.5) /
-           9007199254740992.0;
-}
-
-// last bin b with C[b] <= u, and the position inside it
-__device__ inline int invert(const double *P, const double *C, int nb, double u,
-                             double &frac)
-{
-    int lo = 0, hi = nb - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (C[mid] <= u)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    const double f = (u - C[lo]) / P[lo];
-    frac = f < 1.0 ? f : 1.0;
-    return lo;
-}
+using ile_rng::u53;
 
 constexpr int kMaxBins = 64;   // per-thread LDS histograms: 64 threads x 2 x 64 doubles = 64 KB
 
@@ -79,41 +39,13 @@ __global__ __launch_bounds__(256) void k_hist_draw(
     if (t >= N) return;
     const uint64_t i = (uint64_t)(first + t);
     uint32_t w[16];
-#pragma unroll
-    for (uint32_t b = 0; b < 4; b++) {
-        uint32_t c[4] = {(uint32_t)i, (uint32_t)(i >> 32), b, 0x494C4531u};
-        philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-        w[4 * b] = c[0];
-        w[4 * b + 1] = c[1];
-        w[4 * b + 2] = c[2];
-        w[4 * b + 3] = c[3];
-    }
-    double fr, fs;
-    const int br = invert(sP, sC, nb, u53(w[0], w[1]), fr);
-    const int bs = invert(sP + nb, sC + nb + 1, nb, u53(w[2], w[3]), fs);
-    {
-#pragma clang fp contract(off)
-        const double v3 = d_max * d_max * d_max - d_min * d_min * d_min;
-        const double ra = ((double)br + fr) * (2.0 * kPi / nb);
-        const double sd = -1.0 + ((double)bs + fs) * (2.0 / nb);
-        const double dec = asin(sd);
-        const double psi = kPi * u53(w[4], w[5]);
-        const double phi = 2.0 * kPi * u53(w[6], w[7]);
-        const double ci = 2.0 * u53(w[8], w[9]) - 1.0;
-        const double D = cbrt(d_min * d_min * d_min + u53(w[10], w[11]) * v3);
-        const double tr = t_ref_max * (2.0 * u53(w[12], w[13]) - 1.0);
-        smp[0 * ld + t] = ra;
-        smp[1 * ld + t] = dec;
-        smp[2 * ld + t] = psi;
-        smp[3 * ld + t] = phi;
-        smp[4 * ld + t] = ci;
-        smp[5 * ld + t] = D;
-        smp[6 * ld + t] = tr;
-        const double lp = -log(kTwoPi) + log(cos(dec) / 2.0) - log(kPi) - log(kTwoPi) -
-                          log(2.0) + log(3.0 * D * D / v3) - log(2.0 * t_ref_max);
-        if (ln_p) ln_p[t] = lp;
-        if (ln_q) ln_q[t] = lp + log(nb * sP[br]) + log(nb * sP[nb + bs]);
-    }
+    ile_rng::prior_words(seed, i, w);
+    double x[7];
+    int br, bs;
+    const double lp = ile_rng::hist_sample(sP, sC, nb, w, d_min, d_max, t_ref_max, x, br, bs);
+    for (int d = 0; d < 7; d++) smp[d * ld + t] = x[d];
+    if (ln_p) ln_p[t] = lp;
+    if (ln_q) ln_q[t] = lp + log(nb * sP[br]) + log(nb * sP[nb + bs]);
     if (bins) {
         bins[t] = br;
         bins[ld + t] = bs;

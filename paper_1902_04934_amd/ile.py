@@ -60,7 +60,28 @@ class RunOpts(C.Structure):
                 ("max_samples", C.c_int64), ("n_eff_target", C.c_double),
                 ("d_min_mpc", C.c_double), ("d_max_mpc", C.c_double),
                 ("n_bins", C.c_int32), ("floor", C.c_double), ("temper", C.c_double),
-                ("adapt_chunks", C.c_int32), ("reset", C.c_int32)]
+                ("adapt_chunks", C.c_int32), ("reset", C.c_int32),
+                ("prop", C.c_void_p), ("eps", C.c_double), ("fallback_neff", C.c_double),
+                ("train_steps", C.c_int32), ("train_batch", C.c_int32), ("lr", C.c_double)]
+
+
+class LearnedInfo(C.Structure):
+    _fields_ = [("n_train_samples", C.c_int64), ("n_learned_samples", C.c_int64),
+                ("fell_back", C.c_int32), ("train_ms", C.c_double), ("final_loss", C.c_double)]
+
+
+class PropConfig(C.Structure):
+    _fields_ = [("d_min_mpc", C.c_double), ("d_max_mpc", C.c_double),
+                ("t_ref_max_s", C.c_double), ("sigma_floor", C.c_double),
+                ("seed", C.c_uint64), ("device", C.c_int32), ("stream", C.c_void_p)]
+
+
+class PropTrainOpts(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double),
+                ("temper", C.c_double), ("seed", C.c_uint64), ("fit_transform", C.c_int32)]
+
+
+PROP_NPARAM = 60880
 
 
 class BatchConfig(C.Structure):
@@ -131,6 +152,32 @@ def lib():
         L.ile_batch_destroy.restype = None
         L.ile_batch_last_error.argtypes = [_vp]
         L.ile_batch_last_error.restype = C.c_char_p
+        L.ile_inject.argtypes = [_vp, _dp, C.c_int64, C.c_double, C.POINTER(Detector), _dp,
+                                 C.c_double, _dp, _dp, _dp, _dp, _dp]
+        L.ile_last_learned_info.argtypes = [_vp, C.POINTER(LearnedInfo)]
+        L.ile_get_stream.argtypes = [_vp, C.POINTER(_vp)]
+        _fp = C.POINTER(C.c_float)
+        L.ile_prop_create.argtypes = [C.POINTER(PropConfig), C.POINTER(_vp)]
+        L.ile_prop_set_params.argtypes = [_vp, _fp]
+        L.ile_prop_get_params.argtypes = [_vp, _fp]
+        L.ile_prop_set_transform.argtypes = [_vp, _dp, _dp, _dp]
+        L.ile_prop_get_transform.argtypes = [_vp, _dp, _dp, _dp]
+        L.ile_prop_fit_transform_dev.argtypes = [_vp, _vp, C.c_int64, _vp, C.c_int64,
+                                                 C.c_double]
+        L.ile_prop_grad_dev.argtypes = [_vp, _vp, C.c_int64, _vp, C.c_int64, _vp, _dp]
+        L.ile_prop_train_dev.argtypes = [_vp, _vp, C.c_int64, _vp, C.c_int64,
+                                         C.POINTER(PropTrainOpts), _dp]
+        L.ile_prop_logpdf_dev.argtypes = [_vp, _vp, C.c_double, _vp, C.c_int64, C.c_int64,
+                                          _vp]
+        L.ile_prop_sample_dev.argtypes = [_vp, _vp, C.c_double, C.c_uint64, C.c_int64,
+                                          C.c_int64, _vp, C.c_int64, _vp, _vp]
+        L.ile_prop_sync.argtypes = [_vp]
+        L.ile_prop_last_ms.argtypes = [_vp]
+        L.ile_prop_last_ms.restype = C.c_double
+        L.ile_prop_destroy.argtypes = [_vp]
+        L.ile_prop_destroy.restype = None
+        L.ile_prop_last_error.argtypes = [_vp]
+        L.ile_prop_last_error.restype = C.c_char_p
         L.ile_sync.argtypes = [_vp]
         L.ile_set_option.argtypes = [_vp, C.c_int, C.c_int64]
         L.ile_last_kernel_ms.argtypes = [_vp]
@@ -239,16 +286,52 @@ def ile_run_prior(h, seed, n, chunk, d_min=10.0, d_max=1000.0):
 
 def ile_run(h, sampler="adaptive", seed=1, chunk=100_000, max_samples=1_000_000,
             n_eff_target=0.0, d_min=10.0, d_max=1000.0, n_bins=50, floor=0.1,
-            temper=10.0, adapt_chunks=-1, reset=True):
+            temper=10.0, adapt_chunks=-1, reset=True, prop=None, eps=-1.0,
+            fallback_neff=-1.0, train_steps=0, train_batch=0, lr=0.0):
     o = RunOpts(SAMPLER[sampler], int(seed), int(chunk), int(max_samples),
                 float(n_eff_target), float(d_min), float(d_max), int(n_bins),
-                float(floor), float(temper), int(adapt_chunks), 1 if reset else 0)
+                float(floor), float(temper), int(adapt_chunks), 1 if reset else 0,
+                prop, float(eps), float(fallback_neff), int(train_steps),
+                int(train_batch), float(lr))
     r = Result()
     nc = C.c_int64()
     _check(lib().ile_run(h, C.byref(o), C.byref(r), C.byref(nc)), h)
     d = r.as_dict()
     d["n_chunks"] = nc.value
+    if sampler == "learned":
+        li = LearnedInfo()
+        _check(lib().ile_last_learned_info(h, C.byref(li)), h)
+        d.update({f: getattr(li, f) for f, _ in li._fields_})
     return d
+
+
+def ile_inject(h, h_lm, t0_s, dets, theta, snr=0.0, want_data=False):
+    """Device zero-noise injection (see ile.h); returns (rho2, d_inj) and,
+    with want_data, the host Q, U, V it installed."""
+    hl = np.ascontiguousarray(h_lm, np.complex128)
+    n_lm, n_q = hl.shape
+    hv = hl.view(np.float64)
+    th, thp = _f64(theta)
+    d = (Detector * len(dets))(*[Detector(*x) for x in dets])
+    rho2, dinj = C.c_double(), C.c_double()
+    outs = [None, None, None]
+    if want_data:
+        n_det = len(dets)
+        outs = [np.zeros((n_det, n_lm, n_q), np.complex128),
+                np.zeros((n_det, n_lm, n_lm), np.complex128),
+                np.zeros((n_det, n_lm, n_lm), np.complex128)]
+    ptr = [None if o is None else o.view(np.float64).ctypes.data_as(_dp) for o in outs]
+    _check(lib().ile_inject(h, hv.ctypes.data_as(_dp), int(n_q), float(t0_s), d, thp,
+                            float(snr), C.byref(rho2), C.byref(dinj), *ptr), h)
+    if want_data:
+        return rho2.value, dinj.value, outs[0], outs[1], outs[2]
+    return rho2.value, dinj.value
+
+
+def ile_get_stream(h):
+    s = _vp()
+    _check(lib().ile_get_stream(h, C.byref(s)), h)
+    return s.value
 
 
 def ile_hist_get(h, n_bins):
@@ -344,7 +427,13 @@ class Context:
         return ile_run_prior(self.h, seed, n, chunk, d_min, d_max)
 
     def run(self, **kw):
+        if isinstance(kw.get("prop"), Proposal):
+            kw["prop"] = kw["prop"].h
         return ile_run(self.h, **kw)
+
+    def stream(self):
+        """The context's hipStream_t (as an integer)."""
+        return ile_get_stream(self.h)
 
     def sync(self):
         ile_sync(self.h)
@@ -441,6 +530,109 @@ class Batch:
     def close(self):
         if getattr(self, "h", None):
             lib().ile_batch_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# -------------------------------------------------------- learned proposal
+def _pcheck(status, p):
+    if status != ILE_OK:
+        m = lib().ile_prop_last_error(p) if p else b""
+        raise IleError(status, (m or b"").decode() or lib().ile_status_string(status).decode())
+
+
+class Proposal:
+    """The learned proposal (ile_prop_*).  Pass ctx to share its stream and
+    its histograms (for the defensive mixture)."""
+
+    def __init__(self, ctx=None, *, d_min=10.0, d_max=1000.0, t_ref_max=0.01,
+                 sigma_floor=1e-3, seed=1, device=0, stream=None):
+        if ctx is not None and stream is None:
+            stream = ctx.stream()
+        self.ctx = ctx
+        cfg = PropConfig(float(d_min), float(d_max), float(t_ref_max), float(sigma_floor),
+                         int(seed), int(device), stream)
+        h = _vp()
+        st = lib().ile_prop_create(C.byref(cfg), C.byref(h))
+        if st != ILE_OK:
+            raise IleError(st, lib().ile_status_string(st).decode())
+        self.h = h.value
+
+    def set_params(self, params):
+        a = np.ascontiguousarray(params, np.float32)
+        assert a.size == PROP_NPARAM
+        _pcheck(lib().ile_prop_set_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float))),
+                self.h)
+
+    def get_params(self):
+        a = np.zeros(PROP_NPARAM, np.float32)
+        _pcheck(lib().ile_prop_get_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float))),
+                self.h)
+        return a
+
+    def set_transform(self, origin, mean, scale):
+        o, op = _f64(origin)
+        m, mp = _f64(mean)
+        s, sp = _f64(scale)
+        _pcheck(lib().ile_prop_set_transform(self.h, op, mp, sp), self.h)
+
+    def get_transform(self):
+        o, m, s = np.zeros(3), np.zeros(7), np.zeros(7)
+        _pcheck(lib().ile_prop_get_transform(self.h, o.ctypes.data_as(_dp),
+                                             m.ctypes.data_as(_dp), s.ctypes.data_as(_dp)),
+                self.h)
+        return o, m, s
+
+    def fit_transform_dev(self, x_dev, ld, lnw_dev, n, temper=10.0):
+        _pcheck(lib().ile_prop_fit_transform_dev(self.h, _dev(x_dev), int(ld), _dev(lnw_dev),
+                                                 int(n), float(temper)), self.h)
+
+    def grad_dev(self, x_dev, ld, n, w_dev=None, grad_dev=None):
+        loss = C.c_double()
+        _pcheck(lib().ile_prop_grad_dev(self.h, _dev(x_dev), int(ld), _dev(w_dev), int(n),
+                                        _dev(grad_dev), C.byref(loss)), self.h)
+        return loss.value
+
+    def train_dev(self, x_dev, ld, lnw_dev, n, *, steps=1000, batch=4096, lr=1e-3,
+                  temper=10.0, seed=1, fit_transform=True):
+        o = PropTrainOpts(int(steps), int(batch), float(lr), float(temper), int(seed),
+                          1 if fit_transform else 0)
+        loss = C.c_double()
+        _pcheck(lib().ile_prop_train_dev(self.h, _dev(x_dev), int(ld), _dev(lnw_dev), int(n),
+                                         C.byref(o), C.byref(loss)), self.h)
+        return loss.value
+
+    def logpdf_dev(self, x_dev, ld, n, lnq_dev, eps=0.0):
+        mix = self.ctx.h if (self.ctx is not None and eps > 0) else None
+        _pcheck(lib().ile_prop_logpdf_dev(self.h, mix, float(eps), _dev(x_dev), int(ld),
+                                          int(n), _dev(lnq_dev)), self.h)
+
+    def sample_dev(self, seed, first, n, x_dev, ld, lnp_dev, lnq_dev, eps=0.0):
+        mix = self.ctx.h if (self.ctx is not None and eps > 0) else None
+        _pcheck(lib().ile_prop_sample_dev(self.h, mix, float(eps), int(seed), int(first),
+                                          int(n), _dev(x_dev), int(ld), _dev(lnp_dev),
+                                          _dev(lnq_dev)), self.h)
+
+    def sync(self):
+        _pcheck(lib().ile_prop_sync(self.h), self.h)
+
+    def last_ms(self):
+        return lib().ile_prop_last_ms(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ile_prop_destroy(self.h)
             self.h = None
 
     def __enter__(self):

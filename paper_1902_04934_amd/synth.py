@@ -201,3 +201,47 @@ def mdn_params(seed, *, gain=1.0, bias=0.3):
         else:
             out.append(rng.uniform(-bias, bias, size))
     return np.concatenate(out).astype(np.float32)
+
+
+# ------------------------------------------------ injection inputs
+def mode_waveforms(modes, n_q, srate_hz, seed, *, sigma_t=0.03, f0=40.0, fdot=1500.0,
+                   amp=1.0):
+    """Stand-in mode series h_lm[i] (complex [n_lm][n_q]) for a zero-noise
+    injection, in place of the paper's waveform models (Sec. III.A): a
+    Gaussian-enveloped chirp centred on sample 0 (circular time u = i dt,
+    wrapped to [-n_q/2, n_q/2) dt) whose phase advances m/2 times a common
+    chirp phase (the m-dependence of the modes), with mode amplitudes
+    amp * 0.3**rank and a seeded phase offset per mode.  Data only."""
+    rng = np.random.default_rng(seed)
+    dt = 1.0 / srate_hz
+    i = np.arange(n_q)
+    u = np.where(i < n_q // 2, i, i - n_q) * dt
+    env = np.exp(-u * u / (2 * sigma_t ** 2))
+    chirp = 2 * np.pi * (f0 * u + 0.5 * fdot * u * u)
+    h = np.zeros((len(modes), n_q), np.complex128)
+    for a, (l, m) in enumerate(modes):
+        ph = rng.uniform(0, 2 * np.pi)
+        h[a] = amp * 0.3 ** a * env * np.exp(1j * (ph + 0.5 * m * chirp))
+    return h
+
+
+CONFIG4_SEEDS = (4001, 4002)   # (data and injection, samples)
+
+
+def config4_parts(seed=None):
+    """Learned-proposal workload: 3 detectors, 9 modes (l = 2, 3), 16384
+    points at 16384 Hz, 1601 bins; a zero-noise injection at network SNR 20
+    of the stand-in waveforms at seeded parameters (distance set by the SNR).
+    Returns the pieces; the injection itself (responses, Q, U, V) is built by
+    whoever evaluates it."""
+    seed = CONFIG4_SEEDS[0] if seed is None else seed
+    rng = np.random.default_rng(seed)
+    names = ["D1", "D2", "D3"]
+    modes = MODE_ORDER[:9]
+    n_q, srate, n_t = 16384, 16384.0, 1601
+    theta = np.array([rng.uniform(0, 2 * np.pi), math.asin(rng.uniform(-1, 1)),
+                      rng.uniform(0, np.pi), rng.uniform(0, 2 * np.pi),
+                      rng.uniform(-1, 1), 400.0, rng.uniform(-0.5, 0.5) * T_REF_MAX_S])
+    h = mode_waveforms(modes, n_q, srate, seed + 1, amp=20.0)
+    return dict(det_names=names, dets=[DETECTORS[d] for d in names], modes=modes,
+                n_q=n_q, srate_hz=srate, n_t=n_t, h_lm=h, theta_inj=theta, snr=20.0)
