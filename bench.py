@@ -106,7 +106,7 @@ def main():
     ap.add_argument("--samples", type=int, default=None)
     ap.add_argument("--engine", default=None, choices=["mfma", "valu"],
                     help="contraction engine (default: matrix cores for FP64)")
-    ap.add_argument("--threads", type=int, default=None, choices=[256, 512])
+    ap.add_argument("--threads", type=int, default=None, choices=[128, 192, 256, 512])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-plain sampler comparison")
@@ -163,7 +163,7 @@ def main():
                    "n_samples": n, "n_t": inst.n_t, "n_det": inst.n_det,
                    "n_lm": inst.n_lm, "precision": args.precision,
                    "engine": args.engine or "mfma",
-                   "threads": args.threads or 256},
+                   "threads": args.threads or (192 if args.precision == "fp64" else 128)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                      "kernel": "k_contract", "kernel_ms": kernel_ms,

@@ -233,17 +233,25 @@ typedef struct {
     int32_t reset;           /* 1: start from uniform histograms; 0: keep the
                                 context's current ones (warm start)          */
     /* sampler LEARNED only: adapt_chunks (<= 0: 3) adaptive rounds of
-     * `chunk` samples train `prop` (train_steps Adam steps of train_batch,
-     * learning rate lr; <= 0: defaults of ile_prop_train_dev); then chunks
-     * are drawn from (1 - eps) q_net + eps q_hist (the histograms as left by
-     * the rounds).  If the first learned chunk alone has n_eff below
+     * `chunk` samples fill a training ring of as many chunks and train
+     * `prop` (train_steps Adam steps of train_batch, learning rate lr;
+     * <= 0: defaults of ile_prop_train_dev).  Refinement: up to
+     * refine_rounds chunks are drawn from (1 - eps) q_net + eps q_hist (the
+     * histograms as left by the rounds); each replaces the oldest chunk of
+     * the ring and the network is refit (transform and refine_steps warm
+     * Adam steps), until a chunk's own n_eff reaches refine_eff times its
+     * size.  Then chunks are drawn from the mixture until n_eff_target or
+     * max_samples; if the first of them alone has n_eff below
      * fallback_neff, the run continues with the adaptive sampler.  The
-     * estimate covers the chunks after training only. */
+     * estimate covers the chunks after refinement only. */
     ile_prop *prop;
     double eps;              /* defensive weight (< 0: 0.1)                   */
     double fallback_neff;    /* (< 0: 1000; 0: never fall back)               */
     int32_t train_steps, train_batch;
     double lr;
+    int32_t refine_rounds;   /* (< 0: 8; 0: none)                             */
+    int32_t refine_steps;    /* (<= 0: 300)                                   */
+    double refine_eff;       /* (<= 0: 0.05)                                  */
 } ile_run_opts;
 
 /* Monte Carlo estimate of ln L_marg: chunk after chunk, draw on the device,
@@ -254,13 +262,16 @@ typedef struct {
 ile_status ile_run(ile_ctx *ctx, const ile_run_opts *opts, ile_result *out,
                    int64_t *n_chunks_out);
 
-/* Result of the last ile_run with sampler LEARNED: samples drawn before
- * training (adaptive rounds), after training, and whether it fell back. */
+/* Result of the last ile_run with sampler LEARNED: samples of each phase,
+ * whether it fell back, training time and the last refinement efficiency. */
 typedef struct {
-    int64_t n_train_samples, n_learned_samples;
+    int64_t n_train_samples;   /* adaptive rounds                            */
+    int64_t n_refine_samples;  /* refinement chunks                          */
+    int64_t n_learned_samples; /* estimation chunks from the mixture         */
     int32_t fell_back;
-    double train_ms;           /* device time of the training steps          */
+    double train_ms;           /* device time of all training steps          */
     double final_loss;
+    double last_refine_eff;    /* n_eff / n of the last refinement chunk     */
 } ile_learned_info;
 ile_status ile_last_learned_info(const ile_ctx *ctx, ile_learned_info *out);
 
@@ -318,8 +329,10 @@ ile_status ile_hist_refit_dev(ile_ctx *ctx, const int32_t *bins_dev, int64_t ld,
  *
  * Training minimizes -sum w ln q(z~) / sum w with Adam (0.9, 0.999, 1e-8)
  * on minibatches drawn from the training set with probability proportional
- * to the tempered weights w = exp(beta (ln w - max)), beta = min(1, temper
- * / (max - mean)); each workgroup's gradient is one partial row, summed in
+ * to the tempered weights w = exp(beta (ln w - max)) over the finite ln w:
+ * beta = 1 if the Kish effective size (sum w)^2 / sum w^2 reaches
+ * max(1, ess_frac * count), else the largest beta (30 halvings of [0, 1])
+ * that reaches it.  Each workgroup's gradient is one partial row, summed in
  * a fixed order, so training is bit-reproducible. */
 #define ILE_PROP_NPARAM 60880
 
@@ -335,7 +348,8 @@ typedef struct {
     int32_t steps;           /* Adam steps (<= 0: 1000)                       */
     int32_t batch;           /* minibatch (<= 0: 4096)                        */
     double lr;               /* (<= 0: 1e-3)                                  */
-    double temper;           /* tempering scale (<= 0: 10)                    */
+    double ess_frac;         /* tempering target, fraction of the samples
+                                (<= 0: 0.01)                                  */
     uint64_t seed;           /* minibatch draws                               */
     int32_t fit_transform;   /* 1: fit the transform to the data first:
                                 weighted circular means of ra, psi, phi as
@@ -352,9 +366,10 @@ ile_status ile_prop_set_transform(ile_prop *p, const double origin[3], const dou
                                   const double scale[7]);
 ile_status ile_prop_get_transform(ile_prop *p, double origin[3], double mean[7],
                                   double scale[7]);
-/* Fit the transform to device samples x_dev[7][ld] with log-weights lnw_dev. */
+/* Fit the transform to device samples x_dev[7][ld] with log-weights
+ * lnw_dev, tempered as for training (ess_frac <= 0: 0.01). */
 ile_status ile_prop_fit_transform_dev(ile_prop *p, const double *x_dev, int64_t ld,
-                                      const double *lnw_dev, int64_t n, double temper);
+                                      const double *lnw_dev, int64_t n, double ess_frac);
 /* Loss -sum w ln q(z~) / sum w of n device samples (w_dev NULL: all 1) and
  * its gradient (device float grad_dev[ILE_PROP_NPARAM], may be NULL; masked
  * entries 0); loss to the host (may be NULL).  n <= 2^20. */
@@ -401,7 +416,8 @@ typedef struct {
 } ile_batch_config;
 
 typedef struct {
-    int32_t threads;          /* 256 or 512                                  */
+    int32_t threads;          /* positions per block: 256 or 512; 128 or 192
+                                 with the matrix cores                       */
     int32_t wgs_per_cu;       /* persistent workgroups per compute unit, 1..4 */
     int32_t order;            /* 0: queue by decreasing cost, 1: point order  */
     int32_t engine;           /* 1 matrix cores, 0 vector FMA (not for BF16)  */
@@ -444,9 +460,12 @@ typedef enum {
     ILE_OPT_SORT = 0,    /* 1: order samples by window position before the
                             contraction (default), 0: keep input order */
     ILE_OPT_ENGINE = 1,  /* contraction engine: 1 = matrix cores (default;
-                            the only BF16 engine), 0 = vector FMA */
-    ILE_OPT_THREADS = 2  /* threads per workgroup = positions per block:
-                            256 (default) or 512 */
+                            the only BF16 engine), 0 = vector FMA (a block
+                            width of 128 or 192 becomes 256) */
+    ILE_OPT_THREADS = 2  /* positions per block: 256 or 512, or 128 or 192
+                            with the matrix cores (workgroups of twice as
+                            many threads: producers + consumers); default
+                            192 for FP64, 128 for FP32 and BF16 */
 } ile_option;
 ile_status ile_set_option(ile_ctx *ctx, ile_option opt, int64_t value);
 

@@ -252,22 +252,49 @@ void orc_mdn_loss_grad(const double *params, const orc_mdn_transform *tr, const 
     *loss = lsum;
 }
 
-void orc_mdn_fit_transform(const double *x, int64_t ld, const double *lnw, int64_t n,
-                           double temper, orc_mdn_transform *tr)
+/* Kish effective size of the weights exp(beta (lnw - m)) over the finite lnw */
+static double ess_at(const double *lnw, int64_t n, double m, double beta)
 {
-    /* samples whose ln w is not finite carry no weight */
-    double mx = -INFINITY;
-    long double mean = 0.0L;
-    int64_t cnt = 0;
+    double s1 = 0.0, s2 = 0.0;
     for (int64_t i = 0; i < n; i++) {
         if (!isfinite(lnw[i])) continue;
-        mx = fmax(mx, lnw[i]);
-        mean += lnw[i];
-        cnt++;
+        double e = exp(beta * (lnw[i] - m));
+        s1 += e;
+        s2 += e * e;
     }
-    mean = cnt > 0 ? mean / (long double)cnt : 0.0L;
-    double spread = mx - (double)mean;
-    double beta = spread > 0 ? fmin(1.0, temper / spread) : 1.0;
+    return s2 > 0 ? s1 * s1 / s2 : 0.0;
+}
+
+double orc_mdn_tempering(const double *lnw, int64_t n, double ess_frac, double *max_out)
+{
+    double mx = -INFINITY;
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < n; i++)
+        if (isfinite(lnw[i])) {
+            mx = fmax(mx, lnw[i]);
+            cnt++;
+        }
+    if (max_out) *max_out = mx;
+    if (cnt == 0) return 1.0;
+    const double target = fmax(1.0, ess_frac * (double)cnt);
+    if (ess_at(lnw, n, mx, 1.0) >= target) return 1.0;
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 30; it++) {
+        double mid = 0.5 * (lo + hi);
+        if (ess_at(lnw, n, mx, mid) >= target)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+void orc_mdn_fit_transform(const double *x, int64_t ld, const double *lnw, int64_t n,
+                           double ess_frac, orc_mdn_transform *tr)
+{
+    /* samples whose ln w is not finite carry no weight */
+    double mx;
+    double beta = orc_mdn_tempering(lnw, n, ess_frac, &mx);
     double *w = (double *)malloc(sizeof(double) * (size_t)n);
     for (int64_t i = 0; i < n; i++) w[i] = isfinite(lnw[i]) ? exp(beta * (lnw[i] - mx)) : 0.0;
     /* circular means of the periodic dimensions */
@@ -311,4 +338,20 @@ void orc_mdn_fit_transform(const double *x, int64_t ld, const double *lnw, int64
         tr->scale[d] = fmax(sqrt(fmax(v, 0.0)), 1e-3);
     }
     free(w);
+}
+
+void orc_mdn_outputs(const double *params, const orc_mdn_transform *tr, const double *x,
+                     int64_t ld, int64_t n, double *z_out, double *o_out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) {
+        double xi[7], z[7];
+        for (int d = 0; d < 7; d++) xi[d] = x[d * ld + i];
+        if (orc_mdn_to_z(tr, xi, z) == -INFINITY)
+            for (int d = 0; d < 7; d++) z[d] = NAN;
+        fwd_state s;
+        forward(params, z, &s);
+        for (int d = 0; d < 7; d++) z_out[i * 7 + d] = z[d];
+        for (int o = 0; o < ORC_MDN_O; o++) o_out[i * ORC_MDN_O + o] = s.o[o];
+    }
 }

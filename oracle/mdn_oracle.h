@@ -77,6 +77,12 @@ double orc_mdn_lnq_z(const double *params, const orc_mdn_transform *tr,
 void orc_mdn_logpdf(const double *params, const orc_mdn_transform *tr,
                     const double *x, int64_t ld, int64_t n, double *lnq);
 
+/* z~ (z_out[n][7]) and the 336 network outputs (o_out[n][336]) of n samples
+ * x[7][ld]; for each dimension d the outputs 48d.. give the conditional
+ * mixture given z~_0..z~_{d-1}. */
+void orc_mdn_outputs(const double *params, const orc_mdn_transform *tr, const double *x,
+                     int64_t ld, int64_t n, double *z_out, double *o_out);
+
 /* Weighted negative log-likelihood in z~ space,
  *   loss = -sum_i w_i ln q(z~_i) / sum_i w_i     (w = NULL: all 1),
  * and its gradient with respect to every parameter (masked entries 0), by
@@ -85,13 +91,19 @@ void orc_mdn_loss_grad(const double *params, const orc_mdn_transform *tr,
                        const double *x, int64_t ld, int64_t n, const double *w,
                        double *loss, double *grad);
 
-/* Transform fit from weighted samples: tempered weights
- * w = exp(beta (lnw - max)), beta = min(1, temper/(max - mean)); origins =
- * weighted circular means; mean/scale = weighted mean and standard
- * deviation of z (scale floored at 1e-3); max and mean over the finite
- * ln w, non-finite ones weigh 0. Sums in index order (long double). */
+/* Tempering of training weights w = exp(beta (lnw - max)) over the finite
+ * lnw: beta = 1 if the Kish effective size (sum w)^2 / sum w^2 is at least
+ * max(1, ess_frac * count), else the bisection of [0, 1] (30 halvings,
+ * keeping the lower end) for the largest beta whose effective size reaches
+ * that target.  Returns beta; *max_out (may be NULL) = max lnw. */
+double orc_mdn_tempering(const double *lnw, int64_t n, double ess_frac, double *max_out);
+
+/* Transform fit from weighted samples with the tempered weights above:
+ * origins = weighted circular means; mean/scale = weighted mean and
+ * standard deviation of z (scale floored at 1e-3); non-finite ln w weigh
+ * 0.  Moment sums in index order (long double). */
 void orc_mdn_fit_transform(const double *x, int64_t ld, const double *lnw,
-                           int64_t n, double temper, orc_mdn_transform *tr);
+                           int64_t n, double ess_frac, orc_mdn_transform *tr);
 
 #ifdef __cplusplus
 }

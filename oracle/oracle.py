@@ -364,7 +364,16 @@ def mdn_loss_grad(params, tr, x, w=None):
     return loss.value, g
 
 
-def mdn_fit_transform(x, lnw, temper=10.0, d_min=10.0, d_max=1000.0, t_ref_max=0.01,
+def mdn_tempering(lnw, ess_frac=0.01):
+    L = lib()
+    L.orc_mdn_tempering.restype = C.c_double
+    lnw = np.ascontiguousarray(lnw, np.float64)
+    m = C.c_double()
+    b = L.orc_mdn_tempering(_p(lnw), C.c_int64(lnw.size), C.c_double(ess_frac), C.byref(m))
+    return b, m.value
+
+
+def mdn_fit_transform(x, lnw, ess_frac=0.01, d_min=10.0, d_max=1000.0, t_ref_max=0.01,
                       sigma_floor=1e-3):
     x = np.ascontiguousarray(x, np.float64)
     lnw = np.ascontiguousarray(lnw, np.float64)
@@ -372,5 +381,16 @@ def mdn_fit_transform(x, lnw, temper=10.0, d_min=10.0, d_max=1000.0, t_ref_max=0
     tr = mdn_transform(d_min=d_min, d_max=d_max, t_ref_max=t_ref_max,
                        sigma_floor=sigma_floor)
     lib().orc_mdn_fit_transform(_p(x), C.c_int64(n), _p(lnw), C.c_int64(n),
-                                C.c_double(temper), C.byref(tr))
+                                C.c_double(ess_frac), C.byref(tr))
     return tr
+
+
+def mdn_outputs(params, tr, x):
+    """(z~ [n][7], network outputs [n][336]) of samples x[7][n]."""
+    P = np.ascontiguousarray(params, np.float64)
+    x = np.ascontiguousarray(x, np.float64)
+    n = x.shape[1]
+    z = np.zeros((n, 7))
+    o = np.zeros((n, 336))
+    lib().orc_mdn_outputs(_p(P), C.byref(tr), _p(x), C.c_int64(n), C.c_int64(n), _p(z), _p(o))
+    return z, o

@@ -411,7 +411,8 @@ ile_status ile_batch_set_tuning(ile_batch *b, const ile_batch_tuning *t)
 {
     if (!b) return ILE_E_ARG;
     b->err.clear();
-    if (!t || (t->threads != 256 && t->threads != 512) || t->wgs_per_cu < 1 ||
+    if (!t || (t->threads != 128 && t->threads != 192 && t->threads != 256 && t->threads != 512) ||
+        t->wgs_per_cu < 1 ||
         t->wgs_per_cu > 4 || (t->order != 0 && t->order != 1) ||
         (t->engine != 0 && t->engine != 1))
         return bfail(b, ILE_E_ARG, "bad tuning");
@@ -452,7 +453,7 @@ ile_status ile_batch_autotune(ile_batch *b, int64_t n, const char *cache_path)
     }
     std::vector<ile_batch_tuning> cand;
     const int engines = b->cfg.precision == ILE_BF16 ? 1 : 2;
-    for (int th : {256, 512})
+    for (int th : {192, 256, 512})
         for (int w : {1, 2, 3})
             for (int o : {0, 1})
                 for (int en = 0; en < engines; en++) cand.push_back({th, w, o, 1 - en});

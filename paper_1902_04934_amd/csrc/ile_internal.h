@@ -198,10 +198,15 @@ hipError_t ile_launch_mdn_sample(const ile_mdn_dev &M, const ile_mdn_mix &mix,
                                  uint64_t seed, int64_t first, int64_t n, double *x,
                                  int64_t ld, double *ln_p, double *ln_q, int grid,
                                  hipStream_t st);
-// Training pieces.  fit: transform + tempering from (x, lnw); prepare: z~
-// and tempered weights; cdf: inclusive prefix sums of the weights.
+// Training pieces.  prepare: z~ and tempered weights; cdf: inclusive
+// prefix sums of the weights.
+// fit: tempering (ESS target ess_frac of the finite samples) into stats =
+// {max ln w, beta}, and (if fit_transform) the transform into tr; ws is a
+// workspace of ile_mdn_fit_ws_doubles() doubles.
 hipError_t ile_launch_mdn_fit(const double *x, int64_t ld, const double *lnw, int64_t n,
-                              double temper, ile_mdn_tr *tr, double *stats, hipStream_t st);
+                              double ess_frac, ile_mdn_tr *tr, double *stats, double *ws,
+                              bool fit_transform, hipStream_t st);
+size_t ile_mdn_fit_ws_doubles();
 hipError_t ile_launch_mdn_prepare(const ile_mdn_tr *tr, const double *x, int64_t ld,
                                   const double *lnw, int64_t n, const double *stats,
                                   float *z, double *w, hipStream_t st);

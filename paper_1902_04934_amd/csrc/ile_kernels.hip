@@ -1267,8 +1267,12 @@ size_t ile_contract_lds_bytes(const ile_geom &g, ile_precision prec,
 bool ile_tune_supported(ile_precision prec, const ile_tune &tu)
 {
     if (tu.tile_samples != 16) return false;
-    if (tu.threads != 256 && tu.threads != 512) return false;
+    // positions per block: 256 or 512 for both engines; the matrix-core
+    // engines also take 128 and 192 (smaller LDS, more workgroups per CU)
+    const bool mf_only = tu.threads == 128 || tu.threads == 192;
+    if (tu.threads != 256 && tu.threads != 512 && !mf_only) return false;
     if (prec == ILE_BF16) return tu.engine == ENG_MFMA;   // BF16 runs on the matrix cores only
+    if (mf_only) return tu.engine == ENG_MFMA;
     return tu.engine == ENG_MFMA || tu.engine == ENG_VALU;
 }
 
@@ -1286,6 +1290,8 @@ hipError_t ile_launch_contract(const ile_geom &g, ile_precision prec,
         if (tu.engine == ENG_MFMA) {
             // producer + consumer halves: threads = 2 x positions per block
             if (tu.threads == 512) ILE_CONTRACT(double, 1024, ENG_MFMA);
+            if (tu.threads == 192) ILE_CONTRACT(double, 384, ENG_MFMA);
+            if (tu.threads == 128) ILE_CONTRACT(double, 256, ENG_MFMA);
             ILE_CONTRACT(double, 512, ENG_MFMA);
         }
         if (tu.threads == 512) ILE_CONTRACT(double, 512, ENG_VALU);
@@ -1293,10 +1299,14 @@ hipError_t ile_launch_contract(const ile_geom &g, ile_precision prec,
     }
     if (prec == ILE_BF16) {
         if (tu.threads == 512) ILE_CONTRACT(float, 1024, ENG_BF16);
+        if (tu.threads == 192) ILE_CONTRACT(float, 384, ENG_BF16);
+        if (tu.threads == 128) ILE_CONTRACT(float, 256, ENG_BF16);
         ILE_CONTRACT(float, 512, ENG_BF16);
     }
     if (tu.engine == ENG_MFMA) {
         if (tu.threads == 512) ILE_CONTRACT(float, 1024, ENG_MFMA);
+        if (tu.threads == 192) ILE_CONTRACT(float, 384, ENG_MFMA);
+        if (tu.threads == 128) ILE_CONTRACT(float, 256, ENG_MFMA);
         ILE_CONTRACT(float, 512, ENG_MFMA);
     }
     if (tu.threads == 512) ILE_CONTRACT(float, 512, ENG_VALU);
@@ -1328,6 +1338,8 @@ hipError_t ile_launch_contract_batched(ile_precision prec, const ile_tune &tu,
     if (prec == ILE_FP64) {
         if (tu.engine == ENG_MFMA) {
             if (tu.threads == 512) ILE_BATCHED(double, 1024, ENG_MFMA);
+            if (tu.threads == 192) ILE_BATCHED(double, 384, ENG_MFMA);
+            if (tu.threads == 128) ILE_BATCHED(double, 256, ENG_MFMA);
             ILE_BATCHED(double, 512, ENG_MFMA);
         }
         if (tu.threads == 512) ILE_BATCHED(double, 512, ENG_VALU);
@@ -1335,10 +1347,14 @@ hipError_t ile_launch_contract_batched(ile_precision prec, const ile_tune &tu,
     }
     if (prec == ILE_BF16) {
         if (tu.threads == 512) ILE_BATCHED(float, 1024, ENG_BF16);
+        if (tu.threads == 192) ILE_BATCHED(float, 384, ENG_BF16);
+        if (tu.threads == 128) ILE_BATCHED(float, 256, ENG_BF16);
         ILE_BATCHED(float, 512, ENG_BF16);
     }
     if (tu.engine == ENG_MFMA) {
         if (tu.threads == 512) ILE_BATCHED(float, 1024, ENG_MFMA);
+        if (tu.threads == 192) ILE_BATCHED(float, 384, ENG_MFMA);
+        if (tu.threads == 128) ILE_BATCHED(float, 256, ENG_MFMA);
         ILE_BATCHED(float, 512, ENG_MFMA);
     }
     if (tu.threads == 512) ILE_BATCHED(float, 512, ENG_VALU);

@@ -733,76 +733,170 @@ __global__ __launch_bounds__(256) void k_mdn_update(ile_mdn_dev M, const float *
 // ------------------------------------------------- training-set pieces
 constexpr int FT = 1024;
 
-// fixed-order block sum of one value per thread (FT threads)
-__device__ inline double block_sum(double v, double *red)
+// Transform fit, multi-block with fixed partitions and fixed-order merges
+// (bit-reproducible).  Tempering of the training weights w = exp(beta (ln w
+// - max)) over the finite ln w: beta = 1 if the Kish effective size
+// (sum w)^2 / sum w^2 reaches max(1, ess_frac * count), else 30 halvings of
+// [0, 1] keeping the lower end whose effective size reaches it.  Then the
+// weighted circular means of ra, psi, phi (origins) and the weighted mean
+// and standard deviation of z = logit(u) (scale >= 1e-3).
+//
+// Workspace ws: [0, 16) the state below, [16, 16 + FB * 16) block partials.
+constexpr int FB = 256;   // blocks of the partial-sum kernels
+enum { S_MAX = 0, S_TARGET, S_LO, S_HI, S_BEVAL, S_BETA, S_DONE, S_CNT };
+
+// fixed-order tree sum of `nv` values per thread over a 256-thread block;
+// thread 0 writes them to out[0..nv)
+template <int NV>
+__device__ inline void block_sums256(double (&v)[NV], double *red, double *out)
 {
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = FT / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    for (int q = 0; q < NV; q++) {
+        red[threadIdx.x] = v[q];
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[q] = red[0];
         __syncthreads();
     }
-    const double out = red[0];
-    __syncthreads();
-    return out;
 }
-__device__ inline double block_max(double v, double *red)
+
+__global__ __launch_bounds__(256) void k_fit_max(const double *__restrict__ lnw, int64_t n,
+                                                 double *ws)
 {
-    red[threadIdx.x] = v;
+    __shared__ double red[256];
+    double mx = -INFINITY, cnt = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)FB * 256)
+        if (isfinite(lnw[i])) {
+            mx = fmax(mx, lnw[i]);
+            cnt += 1.0;
+        }
+    red[threadIdx.x] = mx;
     __syncthreads();
-    for (int s = FT / 2; s > 0; s >>= 1) {
+    for (int s = 128; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
         __syncthreads();
     }
-    const double out = red[0];
+    const double bm = red[0];
     __syncthreads();
-    return out;
+    double c1[1] = {cnt};
+    double *P = ws + 16 + blockIdx.x * 16;
+    block_sums256<1>(c1, red, P + 1);
+    if (threadIdx.x == 0) P[0] = bm;
 }
 
-// Transform fit (one workgroup): tempering beta = min(1, temper/(max -
-// mean)) over the finite ln w; weighted circular means of ra, psi, phi;
-// weighted mean and standard deviation of z = logit(u) (scale >= 1e-3).
-// stats = {max ln w, beta}.
-__global__ __launch_bounds__(FT) void k_mdn_fit(const double *__restrict__ x, int64_t ld,
-                                                const double *__restrict__ lnw, int64_t n,
-                                                double temper, ile_mdn_tr *tr, double *stats)
+__global__ void k_fit_init(double *ws, double ess_frac)
 {
-    __shared__ double red[FT];
-    __shared__ ile_mdn_tr T;
-    if (threadIdx.x == 0) T = *tr;
-    double mx = -INFINITY, sm = 0.0, cnt = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += FT)
-        if (isfinite(lnw[i])) {
-            mx = fmax(mx, lnw[i]);
-            sm += lnw[i];
-            cnt += 1.0;
+    if (threadIdx.x != 0) return;
+    double mx = -INFINITY, cnt = 0.0;
+    for (int b = 0; b < FB; b++) {
+        mx = fmax(mx, ws[16 + b * 16]);
+        cnt += ws[16 + b * 16 + 1];
+    }
+    ws[S_MAX] = mx;
+    ws[S_CNT] = cnt;
+    ws[S_TARGET] = fmax(1.0, ess_frac * cnt);
+    ws[S_LO] = 0.0;
+    ws[S_HI] = 1.0;
+    ws[S_BEVAL] = 1.0;
+    ws[S_BETA] = 1.0;
+    ws[S_DONE] = cnt > 0 ? 0.0 : 1.0;
+}
+
+__global__ __launch_bounds__(256) void k_fit_ess_part(const double *__restrict__ lnw, int64_t n,
+                                                      double *ws)
+{
+    __shared__ double red[256];
+    if (ws[S_DONE] != 0.0) return;   // uniform across the grid
+    const double m = ws[S_MAX], beta = ws[S_BEVAL];
+    double v[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)FB * 256) {
+        if (!isfinite(lnw[i])) continue;
+        const double e = exp(beta * (lnw[i] - m));
+        v[0] += e;
+        v[1] += e * e;
+    }
+    block_sums256<2>(v, red, ws + 16 + blockIdx.x * 16);
+}
+
+// it = 0 judges beta = 1; it = 1..30 halve [lo, hi]
+__global__ void k_fit_ess_step(double *ws, int it)
+{
+    if (threadIdx.x != 0 || ws[S_DONE] != 0.0) return;
+    double s1 = 0.0, s2 = 0.0;
+    for (int b = 0; b < FB; b++) {
+        s1 += ws[16 + b * 16];
+        s2 += ws[16 + b * 16 + 1];
+    }
+    const bool ok = s2 > 0.0 && s1 * s1 / s2 >= ws[S_TARGET];
+    if (it == 0) {
+        if (ok) {
+            ws[S_BETA] = 1.0;
+            ws[S_DONE] = 1.0;
+            return;
         }
-    mx = block_max(mx, red);
-    sm = block_sum(sm, red);
-    cnt = block_sum(cnt, red);
-    const double mean = cnt > 0 ? sm / cnt : 0.0;
-    const double spread = mx - mean;
-    const double beta = spread > 0 ? fmin(1.0, temper / spread) : 1.0;
+    } else if (ok) {
+        ws[S_LO] = ws[S_BEVAL];
+    } else {
+        ws[S_HI] = ws[S_BEVAL];
+    }
+    ws[S_BETA] = ws[S_LO];
+    ws[S_BEVAL] = 0.5 * (ws[S_LO] + ws[S_HI]);
+}
+
+__device__ inline double fit_weight(const double *ws, double l)
+{
+    return isfinite(l) ? exp(ws[S_BETA] * (l - ws[S_MAX])) : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_fit_circ_part(const double *__restrict__ x, int64_t ld,
+                                                       const double *__restrict__ lnw, int64_t n,
+                                                       double *ws)
+{
+    __shared__ double red[256];
     const int pd[3] = {0, 2, 3};
+    const double per[3] = {kTwoPi, kPi, kTwoPi};
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)FB * 256) {
+        const double wi = fit_weight(ws, lnw[i]);
+        if (wi == 0.0) continue;
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            double sn, cs;
+            sincos(kTwoPi * x[pd[j] * ld + i] / per[j], &sn, &cs);
+            v[2 * j] += wi * cs;
+            v[2 * j + 1] += wi * sn;
+        }
+    }
+    block_sums256<6>(v, red, ws + 16 + blockIdx.x * 16);
+}
+
+__global__ void k_fit_circ_fin(double *ws, ile_mdn_tr *tr)
+{
+    if (threadIdx.x != 0) return;
     const double per[3] = {kTwoPi, kPi, kTwoPi};
     for (int j = 0; j < 3; j++) {
         double sc = 0.0, ss = 0.0;
-        for (int64_t i = threadIdx.x; i < n; i += FT) {
-            if (!isfinite(lnw[i])) continue;
-            const double wi = exp(beta * (lnw[i] - mx));
-            const double a = kTwoPi * x[pd[j] * ld + i] / per[j];
-            sc += wi * cos(a);
-            ss += wi * sin(a);
+        for (int b = 0; b < FB; b++) {
+            sc += ws[16 + b * 16 + 2 * j];
+            ss += ws[16 + b * 16 + 2 * j + 1];
         }
-        sc = block_sum(sc, red);
-        ss = block_sum(ss, red);
-        if (threadIdx.x == 0) T.origin[j] = atan2(ss, sc) * per[j] / kTwoPi;
+        tr->origin[j] = atan2(ss, sc) * per[j] / kTwoPi;
     }
-    __syncthreads();
-    double sw = 0.0, s1[7], s2[7];
-    for (int d = 0; d < D; d++) s1[d] = s2[d] = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += FT) {
-        if (!isfinite(lnw[i])) continue;
+}
+
+__global__ __launch_bounds__(256) void k_fit_mom_part(const double *__restrict__ x, int64_t ld,
+                                                      const double *__restrict__ lnw, int64_t n,
+                                                      const ile_mdn_tr *__restrict__ trp, double *ws)
+{
+    __shared__ double red[256];
+    const ile_mdn_tr T = *trp;
+    double v[15];
+    for (int q = 0; q < 15; q++) v[q] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)FB * 256) {
+        const double wi = fit_weight(ws, lnw[i]);
+        if (wi == 0.0) continue;
         double zz[7];
         bool ok = true;
         for (int d = 0; d < D; d++) {
@@ -812,29 +906,38 @@ __global__ __launch_bounds__(FT) void k_mdn_fit(const double *__restrict__ x, in
             else zz[d] = log(u) - log1p(-u);
         }
         if (!ok) continue;
-        const double wi = exp(beta * (lnw[i] - mx));
-        sw += wi;
+        v[0] += wi;
         for (int d = 0; d < D; d++) {
-            s1[d] += wi * zz[d];
-            s2[d] += wi * zz[d] * zz[d];
+            v[1 + d] += wi * zz[d];
+            v[8 + d] += wi * zz[d] * zz[d];
         }
     }
-    sw = block_sum(sw, red);
+    block_sums256<15>(v, red, ws + 16 + blockIdx.x * 16);
+}
+
+__global__ void k_fit_stats_only(const double *ws, double *stats)
+{
+    if (threadIdx.x != 0) return;
+    stats[0] = ws[S_MAX];
+    stats[1] = ws[S_BETA];
+}
+
+__global__ void k_fit_mom_fin(double *ws, ile_mdn_tr *tr, double *stats)
+{
+    if (threadIdx.x != 0) return;
+    double v[15];
+    for (int q = 0; q < 15; q++) {
+        v[q] = 0.0;
+        for (int b = 0; b < FB; b++) v[q] += ws[16 + b * 16 + q];
+    }
     for (int d = 0; d < D; d++) {
-        const double a1 = block_sum(s1[d], red), a2 = block_sum(s2[d], red);
-        if (threadIdx.x == 0) {
-            const double m = sw > 0 ? a1 / sw : 0.0;
-            const double var = sw > 0 ? a2 / sw - m * m : 1.0;
-            T.mean[d] = m;
-            T.scale[d] = fmax(sqrt(fmax(var, 0.0)), 1e-3);
-        }
+        const double m = v[0] > 0 ? v[1 + d] / v[0] : 0.0;
+        const double var = v[0] > 0 ? v[8 + d] / v[0] - m * m : 1.0;
+        tr->mean[d] = m;
+        tr->scale[d] = fmax(sqrt(fmax(var, 0.0)), 1e-3);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        *tr = T;
-        stats[0] = mx;
-        stats[1] = beta;
-    }
+    stats[0] = ws[S_MAX];
+    stats[1] = ws[S_BETA];
 }
 
 // z~ (FP32, [7][n]) and training weights: tempered exp(beta (ln w - max))
@@ -944,11 +1047,29 @@ hipError_t ile_launch_mdn_sample(const ile_mdn_dev &M, const ile_mdn_mix &mix, u
 }
 
 hipError_t ile_launch_mdn_fit(const double *x, int64_t ld, const double *lnw, int64_t n,
-                              double temper, ile_mdn_tr *tr, double *stats, hipStream_t st)
+                              double ess_frac, ile_mdn_tr *tr, double *stats, double *ws,
+                              bool fit_transform, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mdn_fit, dim3(1), dim3(FT), 0, st, x, ld, lnw, n, temper, tr, stats);
+    if (n <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fit_max, dim3(FB), dim3(256), 0, st, lnw, n, ws);
+    hipLaunchKernelGGL(k_fit_init, dim3(1), dim3(64), 0, st, ws, ess_frac);
+    for (int it = 0; it <= 30; it++) {
+        hipLaunchKernelGGL(k_fit_ess_part, dim3(FB), dim3(256), 0, st, lnw, n, ws);
+        hipLaunchKernelGGL(k_fit_ess_step, dim3(1), dim3(64), 0, st, ws, it);
+    }
+    if (fit_transform) {
+        hipLaunchKernelGGL(k_fit_circ_part, dim3(FB), dim3(256), 0, st, x, ld, lnw, n, ws);
+        hipLaunchKernelGGL(k_fit_circ_fin, dim3(1), dim3(64), 0, st, ws, tr);
+        hipLaunchKernelGGL(k_fit_mom_part, dim3(FB), dim3(256), 0, st, x, ld, lnw, n,
+                           (const ile_mdn_tr *)tr, ws);
+        hipLaunchKernelGGL(k_fit_mom_fin, dim3(1), dim3(64), 0, st, ws, tr, stats);
+    } else {
+        hipLaunchKernelGGL(k_fit_stats_only, dim3(1), dim3(64), 0, st, ws, stats);
+    }
     return hipGetLastError();
 }
+
+size_t ile_mdn_fit_ws_doubles() { return 16 + (size_t)FB * 16; }
 
 hipError_t ile_launch_mdn_prepare(const ile_mdn_tr *tr, const double *x, int64_t ld,
                                   const double *lnw, int64_t n, const double *stats, float *z,

@@ -25,7 +25,7 @@ struct ile_prop {
     ile_mdn_tr tr{};             // host copy of the device transform
     // training scratch
     void *part = nullptr, *idx = nullptr, *z = nullptr, *w = nullptr, *cdf = nullptr,
-         *stats = nullptr, *loss = nullptr;
+         *stats = nullptr, *loss = nullptr, *ws = nullptr;
     size_t part_b = 0, idx_b = 0, z_b = 0, w_b = 0, cdf_b = 0;
     hipEvent_t ev[2] = {nullptr, nullptr};
     double last_ms = 0.0;
@@ -186,6 +186,7 @@ ile_status ile_prop_create(const ile_prop_config *cfg, ile_prop **out)
               hipMalloc((void **)&p->M.W3t, ILE_MDN_H * ILE_MDN_W3T_LD * 2) == hipSuccess &&
               hipMalloc((void **)&p->M.tr, sizeof(ile_mdn_tr)) == hipSuccess &&
               hipMalloc(&p->stats, 4 * sizeof(double)) == hipSuccess &&
+              hipMalloc(&p->ws, ile_mdn_fit_ws_doubles() * sizeof(double)) == hipSuccess &&
               hipMalloc(&p->loss, sizeof(double)) == hipSuccess &&
               hipEventCreate(&p->ev[0]) == hipSuccess && hipEventCreate(&p->ev[1]) == hipSuccess;
     if (!ok) return bail(ILE_E_NOMEM);
@@ -268,15 +269,17 @@ ile_status ile_prop_get_transform(ile_prop *p, double origin[3], double mean[7],
 }
 
 ile_status ile_prop_fit_transform_dev(ile_prop *p, const double *x, int64_t ld, const double *lnw,
-                                      int64_t n, double temper)
+                                      int64_t n, double ess_frac)
 {
     if (!p) return ILE_E_ARG;
     ile_status s = check_x(p, x, ld, n);
     if (s) return s;
     if (n <= 0 || !lnw) return pfail(p, ILE_E_ARG, "need n > 0 samples and their ln w");
-    if (!(temper > 0)) temper = 10.0;
+    if (!(ess_frac > 0)) ess_frac = 0.01;
+    if (ess_frac > 1) return pfail(p, ILE_E_ARG, "ess_frac must be in (0, 1]");
     PHIP(p, hipSetDevice(p->cfg.device));
-    PHIP(p, ile_launch_mdn_fit(x, ld, lnw, n, temper, p->M.tr, (double *)p->stats, p->stream));
+    PHIP(p, ile_launch_mdn_fit(x, ld, lnw, n, ess_frac, p->M.tr, (double *)p->stats,
+                               (double *)p->ws, true, p->stream));
     return download_tr(p);
 }
 
@@ -315,8 +318,8 @@ ile_status ile_prop_train_dev(ile_prop *p, const double *x, int64_t ld, const do
     const int steps = d.steps > 0 ? d.steps : 1000;
     const int batch = d.batch > 0 ? d.batch : 4096;
     const double lr = d.lr > 0 ? d.lr : 1e-3;
-    const double temper = d.temper > 0 ? d.temper : 10.0;
-    if (batch > (1 << 20)) return pfail(p, ILE_E_ARG, "batch too large");
+    const double ess_frac = d.ess_frac > 0 ? d.ess_frac : 0.01;
+    if (batch > (1 << 20) || ess_frac > 1) return pfail(p, ILE_E_ARG, "batch or ess_frac");
     PHIP(p, hipSetDevice(p->cfg.device));
     const int nblk = (batch + ILE_MDN_TILE - 1) / ILE_MDN_TILE;
     if ((s = grow(p, p->z, p->z_b, (size_t)n * 7 * sizeof(float)))) return s;
@@ -324,16 +327,8 @@ ile_status ile_prop_train_dev(ile_prop *p, const double *x, int64_t ld, const do
     if ((s = grow(p, p->cdf, p->cdf_b, (size_t)n * sizeof(double)))) return s;
     if ((s = grow(p, p->idx, p->idx_b, (size_t)batch * sizeof(int32_t)))) return s;
     if ((s = grow(p, p->part, p->part_b, (size_t)nblk * ILE_MDN_NPART * sizeof(float)))) return s;
-    if (d.fit_transform)
-        PHIP(p, ile_launch_mdn_fit(x, ld, lnw, n, temper, p->M.tr, (double *)p->stats, p->stream));
-    else {
-        // tempering statistics only: fit into a scratch copy of the transform
-        // would change it, so compute them with the current transform kept
-        ile_mdn_tr keep = p->tr;
-        PHIP(p, ile_launch_mdn_fit(x, ld, lnw, n, temper, p->M.tr, (double *)p->stats, p->stream));
-        p->tr = keep;
-        if ((s = upload_tr(p))) return s;
-    }
+    PHIP(p, ile_launch_mdn_fit(x, ld, lnw, n, ess_frac, p->M.tr, (double *)p->stats,
+                               (double *)p->ws, d.fit_transform != 0, p->stream));
     PHIP(p, ile_launch_mdn_prepare(p->M.tr, x, ld, lnw, n, (const double *)p->stats,
                                    (float *)p->z, (double *)p->w, p->stream));
     PHIP(p, ile_launch_mdn_cdf((const double *)p->w, n, (double *)p->cdf, p->stream));
@@ -413,7 +408,7 @@ void ile_prop_destroy(ile_prop *p)
     (void)hipSetDevice(p->cfg.device);
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     void *bufs[] = {p->M.theta, p->M.m, p->M.v, p->M.W2b, p->M.W3b, p->M.W2t, p->M.W3t, p->M.tr,
-                    p->part, p->idx, p->z, p->w, p->cdf, p->stats, p->loss};
+                    p->part, p->idx, p->z, p->w, p->cdf, p->stats, p->loss, p->ws};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (hipEvent_t e : p->ev)

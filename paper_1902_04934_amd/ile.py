@@ -62,12 +62,16 @@ class RunOpts(C.Structure):
                 ("n_bins", C.c_int32), ("floor", C.c_double), ("temper", C.c_double),
                 ("adapt_chunks", C.c_int32), ("reset", C.c_int32),
                 ("prop", C.c_void_p), ("eps", C.c_double), ("fallback_neff", C.c_double),
-                ("train_steps", C.c_int32), ("train_batch", C.c_int32), ("lr", C.c_double)]
+                ("train_steps", C.c_int32), ("train_batch", C.c_int32), ("lr", C.c_double),
+                ("refine_rounds", C.c_int32), ("refine_steps", C.c_int32),
+                ("refine_eff", C.c_double)]
 
 
 class LearnedInfo(C.Structure):
-    _fields_ = [("n_train_samples", C.c_int64), ("n_learned_samples", C.c_int64),
-                ("fell_back", C.c_int32), ("train_ms", C.c_double), ("final_loss", C.c_double)]
+    _fields_ = [("n_train_samples", C.c_int64), ("n_refine_samples", C.c_int64),
+                ("n_learned_samples", C.c_int64), ("fell_back", C.c_int32),
+                ("train_ms", C.c_double), ("final_loss", C.c_double),
+                ("last_refine_eff", C.c_double)]
 
 
 class PropConfig(C.Structure):
@@ -78,7 +82,7 @@ class PropConfig(C.Structure):
 
 class PropTrainOpts(C.Structure):
     _fields_ = [("steps", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double),
-                ("temper", C.c_double), ("seed", C.c_uint64), ("fit_transform", C.c_int32)]
+                ("ess_frac", C.c_double), ("seed", C.c_uint64), ("fit_transform", C.c_int32)]
 
 
 PROP_NPARAM = 60880
@@ -115,6 +119,14 @@ def lib():
             raise ImportError(
                 f"{LIB_PATH} is missing: build the HIP library first "
                 "(python -c 'import __graft_entry__ as g; g.build()')")
+        # PyTorch (device memory and streams for the _dev calls) bundles its
+        # own HIP runtime under the same soname as the one libile links to:
+        # load PyTorch first so that both bind to that one runtime (a
+        # process holding two cannot hand device pointers between them).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         L.ile_create.argtypes = [C.POINTER(Config), C.POINTER(_vp)]
         L.ile_set_data.argtypes = [_vp, _dp, C.c_int64, C.c_double, _dp, _dp,
@@ -287,12 +299,14 @@ def ile_run_prior(h, seed, n, chunk, d_min=10.0, d_max=1000.0):
 def ile_run(h, sampler="adaptive", seed=1, chunk=100_000, max_samples=1_000_000,
             n_eff_target=0.0, d_min=10.0, d_max=1000.0, n_bins=50, floor=0.1,
             temper=10.0, adapt_chunks=-1, reset=True, prop=None, eps=-1.0,
-            fallback_neff=-1.0, train_steps=0, train_batch=0, lr=0.0):
+            fallback_neff=-1.0, train_steps=0, train_batch=0, lr=0.0, refine_rounds=-1,
+            refine_steps=0, refine_eff=0.0):
     o = RunOpts(SAMPLER[sampler], int(seed), int(chunk), int(max_samples),
                 float(n_eff_target), float(d_min), float(d_max), int(n_bins),
                 float(floor), float(temper), int(adapt_chunks), 1 if reset else 0,
                 prop, float(eps), float(fallback_neff), int(train_steps),
-                int(train_batch), float(lr))
+                int(train_batch), float(lr), int(refine_rounds), int(refine_steps),
+                float(refine_eff))
     r = Result()
     nc = C.c_int64()
     _check(lib().ile_run(h, C.byref(o), C.byref(r), C.byref(nc)), h)
@@ -594,9 +608,9 @@ class Proposal:
                 self.h)
         return o, m, s
 
-    def fit_transform_dev(self, x_dev, ld, lnw_dev, n, temper=10.0):
+    def fit_transform_dev(self, x_dev, ld, lnw_dev, n, ess_frac=0.01):
         _pcheck(lib().ile_prop_fit_transform_dev(self.h, _dev(x_dev), int(ld), _dev(lnw_dev),
-                                                 int(n), float(temper)), self.h)
+                                                 int(n), float(ess_frac)), self.h)
 
     def grad_dev(self, x_dev, ld, n, w_dev=None, grad_dev=None):
         loss = C.c_double()
@@ -605,8 +619,8 @@ class Proposal:
         return loss.value
 
     def train_dev(self, x_dev, ld, lnw_dev, n, *, steps=1000, batch=4096, lr=1e-3,
-                  temper=10.0, seed=1, fit_transform=True):
-        o = PropTrainOpts(int(steps), int(batch), float(lr), float(temper), int(seed),
+                  ess_frac=0.01, seed=1, fit_transform=True):
+        o = PropTrainOpts(int(steps), int(batch), float(lr), float(ess_frac), int(seed),
                           1 if fit_transform else 0)
         loss = C.c_double()
         _pcheck(lib().ile_prop_train_dev(self.h, _dev(x_dev), int(ld), _dev(lnw_dev), int(n),

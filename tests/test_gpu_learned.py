@@ -118,7 +118,6 @@ def test_learned_beats_plain_to_neff_1e4(torch):
     sig = np.hypot(plain["sigma_ln_L"], lrn["sigma_ln_L"])
     assert abs(plain["ln_L_marg"] - lrn["ln_L_marg"]) < 4 * sig + 1e-3
     # same samples, same weights: device vs oracle ln L_marg
-    inst = ctx.inst
     cfg = synth.config4_parts()
     base = _base(cfg)
     want_inst, _, _ = O.injection_instance(base, cfg["h_lm"], cfg["theta_inj"], snr=cfg["snr"])

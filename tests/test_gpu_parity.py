@@ -105,7 +105,7 @@ def test_config1_fp64_all_samples(torch, c1, sort):
 
 @pytest.mark.parametrize("sort,engine,threads", [
     (True, "mfma", 256), (False, "mfma", 256), (True, "mfma", 512), (False, "mfma", 512),
-    (True, "valu", 256), (False, "valu", 512)])
+    (True, "mfma", 192), (False, "mfma", 128), (True, "valu", 256), (False, "valu", 512)])
 def test_config2_shape_fp64(torch, c2_small, sort, engine, threads):
     from oracle import oracle as O
     inst, s, lp, want = c2_small
@@ -115,7 +115,8 @@ def test_config2_shape_fp64(torch, c2_small, sort, engine, threads):
     print(f"config2 shape, 3001 samples, sort={sort} {engine} {threads}: max err {err:.3e}")
 
 
-@pytest.mark.parametrize("engine,threads", [("mfma", 256), ("mfma", 512), ("valu", 256)])
+@pytest.mark.parametrize("engine,threads", [("mfma", 256), ("mfma", 512), ("mfma", 192),
+                                            ("valu", 256)])
 def test_sorted_and_unsorted_bit_identical(torch, c2_small, engine, threads):
     """A sample's result does not depend on which tile it lands in: at a
     fixed workgroup width the bins a thread owns, and so the order of the
@@ -142,19 +143,21 @@ def test_series_per_bin(torch):
             assert i in _flagged(octx, s, [i])
 
 
-@pytest.mark.parametrize("precision,engine", [("fp32", "mfma"), ("fp32", "valu"), ("bf16", "mfma")])
-def test_reduced_precision_config2_shape(torch, c2_small, precision, engine):
+@pytest.mark.parametrize("precision,engine,threads", [
+    ("fp32", "mfma", 256), ("fp32", "mfma", 192), ("fp32", "valu", 256), ("bf16", "mfma", 256),
+    ("bf16", "mfma", 192), ("bf16", "mfma", 128)])
+def test_reduced_precision_config2_shape(torch, c2_small, precision, engine, threads):
     """FP32 and BF16 hi/lo bulk contraction with FP64 log-sum-exp: per-sample
     ln L_margT within 1e-4 relative, ln L_marg within 1e-3."""
     from oracle import oracle as O
     inst, s, lp, want = c2_small
-    with ile.Context(inst, precision=precision, engine=engine) as ctx:
+    with ile.Context(inst, precision=precision, engine=engine, threads=threads) as ctx:
         got = ctx.eval(s)
         res = ctx.integrate(s, lp, lp)
     err = check_margT(got, want, s, O.Ctx(inst), inst, tol=1e-4, rel=True)
     ref = O.integrate(want, lp, lp)
     assert abs(res["ln_L_marg"] - ref["ln_L_marg"]) <= 1e-3
-    print(f"{precision}/{engine}: max rel err {err:.3e}, "
+    print(f"{precision}/{engine}/{threads}: max rel err {err:.3e}, "
           f"d ln L_marg {res['ln_L_marg'] - ref['ln_L_marg']:.3e}")
 
 

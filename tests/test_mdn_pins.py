@@ -175,8 +175,9 @@ def test_fit_transform_moments():
     x[2] = np.mod(rng.vonmises(3.0 * 2, 4.0, n) / 2, np.pi)
     x[3] = np.mod(rng.vonmises(6.2, 4.0, n), 2 * np.pi)
     lnw = rng.normal(0.0, 0.5, n)
-    tr = O.mdn_fit_transform(x, lnw, temper=10.0)
-    # beta = min(1, 10/(max - mean)) = 1 here
+    tr = O.mdn_fit_transform(x, lnw, ess_frac=0.01)
+    # ln w ~ N(0, 0.5): the untempered weights already have a large effective size
+    assert O.mdn_tempering(lnw, 0.01)[0] == 1.0
     w = np.exp(lnw - lnw.max())
     for j, (d, P) in enumerate(((0, 2 * np.pi), (2, np.pi), (3, 2 * np.pi))):
         a = 2 * np.pi * x[d] / P
@@ -199,14 +200,40 @@ def test_fit_transform_moments():
         assert abs(tr.mean[d] - m) < 1e-9 and abs(tr.scale[d] - s) < 1e-9, d
 
 
-def test_fit_transform_tempering():
-    """With a spread of ln w above the scale, the weights are tempered:
-    beta = temper / (max - mean)."""
-    x, _ = synth.prior_samples(1000, 15)
-    lnw = np.linspace(0.0, 100.0, 1000)
-    tr = O.mdn_fit_transform(x, lnw, temper=10.0)
-    beta = 10.0 / (100.0 - 50.0)
-    w = np.exp(beta * (lnw - 100.0))
+def _kish(lnw, beta):
+    w = np.exp(beta * (lnw - lnw.max()))
+    return w.sum() ** 2 / (w * w).sum()
+
+
+@pytest.mark.parametrize("spread", [5.0, 60.0, 400.0])
+def test_tempering_reaches_target_effective_size(spread):
+    """beta is the largest tempering (to 2^-30) whose Kish effective size
+    reaches ess_frac of the samples; the fit uses exactly those weights."""
+    rng = np.random.default_rng(int(spread))
+    n = 5000
+    lnw = rng.normal(0.0, spread, n)
+    frac = 0.02
+    beta, m = O.mdn_tempering(lnw, frac)
+    assert m == lnw.max()
+    target = frac * n
+    if beta < 1.0:
+        assert _kish(lnw, beta) >= target * (1 - 1e-12)
+        assert _kish(lnw, beta + 2.0 ** -29) < target
+    else:
+        assert _kish(lnw, 1.0) >= target
+    # larger spreads need stronger tempering
+    assert (beta < 1.0) == (_kish(lnw, 1.0) < target)
+    x, _ = synth.prior_samples(n, 16)
+    tr = O.mdn_fit_transform(x, lnw, ess_frac=frac)
+    w = np.exp(beta * (lnw - lnw.max()))
     u4 = (x[4] + 1) / 2
     z4 = np.log(u4) - np.log1p(-u4)
     assert abs(tr.mean[4] - np.average(z4, weights=w)) < 1e-9
+
+
+def test_tempering_ignores_non_finite():
+    lnw = np.array([0.0, -np.inf, 1.0, np.nan, 2.0])
+    beta, m = O.mdn_tempering(lnw, 0.5)
+    assert m == 2.0
+    # the same as the finite values alone (the target counts finite values)
+    assert beta == O.mdn_tempering(np.array([0.0, 1.0, 2.0]), 0.5)[0]
