@@ -28,6 +28,41 @@ FP32_PEAK_TFLOPS = 157.3
 BF16_PEAK_TFLOPS = 2500.0  # dense matrix peak
 
 
+KERNEL_SOURCES = ("paper_1902_04934_amd/csrc/ile_kernels.hip",
+                  "paper_1902_04934_amd/csrc/ile_internal.h")
+
+
+def kernel_source_hash():
+    """sha256 of the contraction kernel's sources (identifies the kernel the
+    committed counter readings belong to)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic(precision, threads):
+    """HBM bytes of one contraction launch from the committed rocprofv3
+    summary of this workload (FETCH_SIZE + WRITE_SIZE, calibrated), if it was
+    taken on the current kernel sources and launch shape; else None."""
+    import glob
+    want = kernel_source_hash()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "k_contract_*.md"))):
+        fields = {}
+        with open(path) as fh:
+            for line in fh:
+                if line.startswith("traffic-record: "):
+                    for kv in line[len("traffic-record: "):].split():
+                        k, _, v = kv.partition("=")
+                        fields[k] = v
+        if (fields.get("source_sha256") == want and fields.get("precision") == precision
+                and fields.get("threads") == str(threads) and "bytes" in fields):
+            return int(fields["bytes"])
+    return None
+
+
 def flops_per_sample(n_det, n_lm, n_t):
     """Algorithmic flops of one sample: the window contraction (Re(conj(c) Q)
     = 2 FMA = 4 flop per detector, mode and bin) plus the quadratic term
@@ -144,6 +179,8 @@ def main():
     dt = time.perf_counter() - t0
     ms_step = 1e3 * dt / args.steps
     kernel_ms = sum(kms) / len(kms)
+    threads = args.threads or (256 if args.engine == "valu" else
+                               192 if args.precision == "fp64" else 128)
     fl = flops_per_sample(inst.n_det, inst.n_lm, inst.n_t) * n
     achieved = fl / (kernel_ms * 1e-3) / 1e12
     peak = {"fp64": FP64_PEAK_TFLOPS, "fp32": FP32_PEAK_TFLOPS,
@@ -163,9 +200,10 @@ def main():
                    "n_samples": n, "n_t": inst.n_t, "n_det": inst.n_det,
                    "n_lm": inst.n_lm, "precision": args.precision,
                    "engine": args.engine or "mfma",
-                   "threads": args.threads or (192 if args.precision == "fp64" else 128)},
+                   "threads": threads},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": committed_traffic(args.precision, threads),
                      "kernel": "k_contract", "kernel_ms": kernel_ms,
                      "flops_per_launch": fl},
         "result": {"ln_L_marg": res["ln_L_marg"], "n_eff": res["n_eff"],

@@ -250,8 +250,10 @@ typedef struct {
     int32_t train_steps, train_batch;
     double lr;
     int32_t refine_rounds;   /* (< 0: 8; 0: none)                             */
-    int32_t refine_steps;    /* (<= 0: 300)                                   */
+    int32_t refine_steps;    /* (<= 0: 600)                                   */
     double refine_eff;       /* (<= 0: 0.05)                                  */
+    double train_ess;        /* tempering target of the training weights, as
+                                ess_frac of ile_prop_train_opts (<= 0: 0.01) */
 } ile_run_opts;
 
 /* Monte Carlo estimate of ln L_marg: chunk after chunk, draw on the device,
@@ -272,6 +274,7 @@ typedef struct {
     double train_ms;           /* device time of all training steps          */
     double final_loss;
     double last_refine_eff;    /* n_eff / n of the last refinement chunk     */
+    double refine_eff[32];     /* n_eff / n of refinement chunks 0..31       */
 } ile_learned_info;
 ile_status ile_last_learned_info(const ile_ctx *ctx, ile_learned_info *out);
 

@@ -901,7 +901,7 @@ static ile_status run_learned(ile_ctx *c, const ile_run_opts *o, ile_result *out
     const double eps = o->eps >= 0 ? o->eps : 0.1;
     const double fb = o->fallback_neff >= 0 ? o->fallback_neff : 1000.0;
     const int refine_rounds = o->refine_rounds >= 0 ? o->refine_rounds : 8;
-    const int refine_steps = o->refine_steps > 0 ? o->refine_steps : 300;
+    const int refine_steps = o->refine_steps > 0 ? o->refine_steps : 600;
     const double refine_eff = o->refine_eff > 0 ? o->refine_eff : 0.05;
     if (floor_w > 1 || eps >= 1) return fail(c, ILE_E_ARG, "floor > 1 or eps >= 1");
     const int64_t ntr = (int64_t)rounds * chunk;
@@ -944,7 +944,7 @@ static ile_status run_learned(ile_ctx *c, const ile_run_opts *o, ile_result *out
     to.steps = o->train_steps;
     to.batch = o->train_batch;
     to.lr = o->lr;
-    to.ess_frac = 0.01;
+    to.ess_frac = o->train_ess > 0 ? o->train_ess : 0.01;
     to.seed = o->seed;
     to.fit_transform = 1;
     double loss = 0.0;
@@ -978,6 +978,7 @@ static ile_status run_learned(ile_ctx *c, const ile_run_opts *o, ile_result *out
         HIP_TRY(c, hipMemcpy(r, c->res.p, sizeof(r), hipMemcpyDeviceToHost));
         c->learned.n_refine_samples += chunk;
         c->learned.last_refine_eff = r[1] / (double)chunk;
+        if (rr < 32) c->learned.refine_eff[rr] = c->learned.last_refine_eff;
         if (r[1] >= refine_eff * (double)chunk) break;
         if (ile_prop_train_dev(o->prop, trx, ntr, trw, ntr, &to, &loss) != ILE_OK)
             return fail(c, ILE_E_DEVICE, "refit failed: %s", ile_prop_last_error(o->prop));

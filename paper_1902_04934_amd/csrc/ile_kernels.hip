@@ -597,6 +597,34 @@ __device__ __forceinline__ bool pipe_last_of_chunk(const PipeIt &it, int nd, int
     return it.k == nd - 1 && it.blk + NP >= it.Jc + spread_last;
 }
 
+// Deterministic reduction of the per-thread log-sum-exp states over the
+// workgroup, in two halves separated by barriers: each wave writes its
+// per-sample maximum (then its per-sample sum of s e^{m - M}) to s_red[wave]
+// by a fixed butterfly; the M (then the result) are formed over the waves
+// in wave order.  Threads with no state contribute -inf (then 0).
+template <int TS>
+__device__ inline void lse_wave_max(const double *m, double (*s_red)[TS], int lane, int wv)
+{
+#pragma unroll
+    for (int al = 0; al < TS; al++) {
+        double v = m ? m[al] : -INFINITY;
+        for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+        if (lane == 0) s_red[wv][al] = v;
+    }
+}
+template <int TS>
+__device__ inline void lse_wave_sum(const double *m, const double *sacc, const double *s_M,
+                                    double (*s_red)[TS], int lane, int wv)
+{
+#pragma unroll
+    for (int al = 0; al < TS; al++) {
+        double v = 0.0;
+        if (m) v = (m[al] == -INFINITY) ? 0.0 : sacc[al] * exp(m[al] - s_M[al]);
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) s_red[wv][al] = v;
+    }
+}
+
 // One tile: samples perm[base .. base + TS) of a point (those below N).
 template <typename TQ, int TS, int NT, int ENG, bool DUMP>
 __device__ __forceinline__ void contract_tile(
@@ -786,15 +814,20 @@ __device__ __forceinline__ void contract_tile(
     int J = NP - smax_all;
     if (J < 64) J = 64;
 
-    double m[TS], sacc[TS];
-#pragma unroll
-    for (int al = 0; al < TS; al++) {
-        m[al] = -INFINITY;
-        sacc[al] = 0.0;
-    }
     const int lane = tid & 63, wv = tid >> 6;
+    // the result of sample al: (M - q) + log S - log n_t, S = the block sum
+    const auto finish_sample = [&](int al, double S) {
+        if (s_idx[al] >= 0)
+            out[s_idx[al]] = s_ok[al] ? (s_M[al] - s_q[al]) + log(S) - log((double)g.n_t) : NAN;
+    };
 
     if constexpr (ENG == ENG_VALU) {
+        double m[TS], sacc[TS];
+#pragma unroll
+        for (int al = 0; al < TS; al++) {
+            m[al] = -INFINITY;
+            sacc[al] = 0.0;
+        }
         for (int j0 = 0; j0 < g.n_t; j0 += J) {
             const int Jc = min(J, g.n_t - j0);
             // thread tid owns the bins j == tid (mod NT); its bin in this chunk
@@ -854,6 +887,21 @@ __device__ __forceinline__ void contract_tile(
                 lse_update<TQ, TS>(L, m, sacc);
             }
         }
+        lse_wave_max<TS>(m, s_red, lane, wv);
+        __syncthreads();
+        if (tid < TS) {
+            double M = s_red[0][tid];
+            for (int w = 1; w < NW; w++) M = fmax(M, s_red[w][tid]);
+            s_M[tid] = M;
+        }
+        __syncthreads();
+        lse_wave_sum<TS>(m, sacc, s_M, s_red, lane, wv);
+        __syncthreads();
+        if (tid < TS) {
+            double S = s_red[0][tid];
+            for (int w = 1; w < NW; w++) S += s_red[w][tid];
+            finish_sample(tid, S);
+        }
     } else {
         // Producer/consumer pipeline over the items (chunk, detector, block):
         // at step s the producer waves compute item s into Gs buffer s % 2
@@ -887,8 +935,31 @@ __device__ __forceinline__ void contract_tile(
                 if (step > 0 && ci.valid) pipe_next(ci, J, g.n_t, nd, s_spread, NP);
                 __syncthreads();
             }
+            // epilogue: producers hold no log-sum-exp state; threads tid < TS
+            // (all producers) form M and the results
+            lse_wave_max<TS>(nullptr, s_red, lane, wv);
+            __syncthreads();
+            if (tid < TS) {
+                double M = s_red[0][tid];
+                for (int w = 1; w < NW; w++) M = fmax(M, s_red[w][tid]);
+                s_M[tid] = M;
+            }
+            __syncthreads();
+            lse_wave_sum<TS>(nullptr, nullptr, s_M, s_red, lane, wv);
+            __syncthreads();
+            if (tid < TS) {
+                double S = s_red[0][tid];
+                for (int w = 1; w < NW; w++) S += s_red[w][tid];
+                finish_sample(tid, S);
+            }
         } else {
             const int tc = tid - NP;   // consumer index
+            double m[TS], sacc[TS];
+#pragma unroll
+            for (int al = 0; al < TS; al++) {
+                m[al] = -INFINITY;
+                sacc[al] = 0.0;
+            }
             TQ L[TS];
 #pragma unroll
             for (int al = 0; al < TS; al++) L[al] = (TQ)0;
@@ -925,35 +996,13 @@ __device__ __forceinline__ void contract_tile(
                 if (pi.valid) pipe_next(pi, J, g.n_t, nd, s_spread, NP);
                 __syncthreads();
             }
+            // epilogue: the same three barriers as the producers
+            lse_wave_max<TS>(m, s_red, lane, wv);
+            __syncthreads();
+            __syncthreads();
+            lse_wave_sum<TS>(m, sacc, s_M, s_red, lane, wv);
+            __syncthreads();
         }
-    }
-
-    // deterministic block reduction: max, then sum of s e^{m - M}
-#pragma unroll
-    for (int al = 0; al < TS; al++) {
-        double v = m[al];
-        for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-        if (lane == 0) s_red[wv][al] = v;
-    }
-    __syncthreads();
-    if (tid < TS) {
-        double M = s_red[0][tid];
-        for (int w = 1; w < NW; w++) M = fmax(M, s_red[w][tid]);
-        s_M[tid] = M;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int al = 0; al < TS; al++) {
-        const double M = s_M[al];
-        double v = (m[al] == -INFINITY) ? 0.0 : sacc[al] * exp(m[al] - M);
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == 0) s_red[wv][al] = v;
-    }
-    __syncthreads();
-    if (tid < TS && s_idx[tid] >= 0) {
-        double S = s_red[0][tid];
-        for (int w = 1; w < NW; w++) S += s_red[w][tid];
-        out[s_idx[tid]] = s_ok[tid] ? (s_M[tid] - s_q[tid]) + log(S) - log((double)g.n_t) : NAN;
     }
 }
 

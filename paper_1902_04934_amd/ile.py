@@ -64,14 +64,14 @@ class RunOpts(C.Structure):
                 ("prop", C.c_void_p), ("eps", C.c_double), ("fallback_neff", C.c_double),
                 ("train_steps", C.c_int32), ("train_batch", C.c_int32), ("lr", C.c_double),
                 ("refine_rounds", C.c_int32), ("refine_steps", C.c_int32),
-                ("refine_eff", C.c_double)]
+                ("refine_eff", C.c_double), ("train_ess", C.c_double)]
 
 
 class LearnedInfo(C.Structure):
     _fields_ = [("n_train_samples", C.c_int64), ("n_refine_samples", C.c_int64),
                 ("n_learned_samples", C.c_int64), ("fell_back", C.c_int32),
                 ("train_ms", C.c_double), ("final_loss", C.c_double),
-                ("last_refine_eff", C.c_double)]
+                ("last_refine_eff", C.c_double), ("refine_eff", C.c_double * 32)]
 
 
 class PropConfig(C.Structure):
@@ -300,13 +300,13 @@ def ile_run(h, sampler="adaptive", seed=1, chunk=100_000, max_samples=1_000_000,
             n_eff_target=0.0, d_min=10.0, d_max=1000.0, n_bins=50, floor=0.1,
             temper=10.0, adapt_chunks=-1, reset=True, prop=None, eps=-1.0,
             fallback_neff=-1.0, train_steps=0, train_batch=0, lr=0.0, refine_rounds=-1,
-            refine_steps=0, refine_eff=0.0):
+            refine_steps=0, refine_eff=0.0, train_ess=0.0):
     o = RunOpts(SAMPLER[sampler], int(seed), int(chunk), int(max_samples),
                 float(n_eff_target), float(d_min), float(d_max), int(n_bins),
                 float(floor), float(temper), int(adapt_chunks), 1 if reset else 0,
                 prop, float(eps), float(fallback_neff), int(train_steps),
                 int(train_batch), float(lr), int(refine_rounds), int(refine_steps),
-                float(refine_eff))
+                float(refine_eff), float(train_ess))
     r = Result()
     nc = C.c_int64()
     _check(lib().ile_run(h, C.byref(o), C.byref(r), C.byref(nc)), h)
@@ -315,7 +315,8 @@ def ile_run(h, sampler="adaptive", seed=1, chunk=100_000, max_samples=1_000_000,
     if sampler == "learned":
         li = LearnedInfo()
         _check(lib().ile_last_learned_info(h, C.byref(li)), h)
-        d.update({f: getattr(li, f) for f, _ in li._fields_})
+        d.update({f: getattr(li, f) for f, _ in li._fields_ if f != "refine_eff"})
+        d["refine_eff"] = [li.refine_eff[i] for i in range(32) if li.refine_eff[i] > 0]
     return d
 
 
