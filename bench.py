@@ -92,11 +92,16 @@ def cpu_baseline(inst, n_total, seed, target_s=12.0):
                       f"FP64 C oracle with OpenMP ({dt:.1f} s)"}
 
 
+LEARNED_SEEDS = tuple(range(41, 49))
+
+
 def learned_leg(target=1e4):
     """The learned proposal against the plain adaptive sampler on the zero-noise
     injection workload (3 detectors, 9 modes, 16384 points at 16384 Hz, 1601
     bins, network SNR 20): wall time of each to n_eff = target, n_eff/s, and
-    their ln L_marg."""
+    their ln L_marg.  The learned sampler (run defaults) is timed on eight
+    run seeds: each seed trains its own network on its own draws, so the
+    spread over seeds is the spread a user sees; the headline is the median."""
     import numpy as np
     from paper_1902_04934_amd import ile, synth
     c = synth.config4_parts()
@@ -106,29 +111,41 @@ def learned_leg(target=1e4):
     out = {"workload": "zero-noise injection at network SNR 20: 3 detectors, 9 modes "
                        "(l=2,3), Q 16384 complex points at 16384 Hz, 1601 time bins, FP64",
            "n_eff_target": target}
+    def entry(r, dt):
+        return {"seconds": dt, "n_eff": r["n_eff"], "n_eff_per_s": r["n_eff"] / dt,
+                "ln_L_marg": r["ln_L_marg"], "sigma_ln_L": r["sigma_ln_L"],
+                "samples": r["n_samples"]}
+
     with ile.Context(base) as ctx:
         rho2, dinj = ile.ile_inject(ctx.h, c["h_lm"], base.t0_s, base.dets, c["theta_inj"],
                                     c["snr"])
         ctx.run(sampler="prior", seed=1, chunk=100_000, max_samples=100_000)   # warm-up
-        for name, kw in (("plain", dict(sampler="adaptive", adapt_chunks=-1,
-                                        max_samples=50_000_000)),
-                         ("learned", dict(sampler="learned", adapt_chunks=3,
-                                          max_samples=20_000_000, eps=0.1,
-                                          train_steps=1000, train_batch=4096))):
-            prop = ile.Proposal(ctx, seed=3) if name == "learned" else None
-            t0 = time.perf_counter()
-            r = ctx.run(seed=41, chunk=100_000, n_eff_target=target, prop=prop, **kw)
-            dt = time.perf_counter() - t0
-            entry = {"seconds": dt, "n_eff": r["n_eff"], "n_eff_per_s": r["n_eff"] / dt,
-                     "ln_L_marg": r["ln_L_marg"], "sigma_ln_L": r["sigma_ln_L"],
-                     "samples": r["n_samples"]}
-            if prop is not None:
-                entry.update(train_samples=r["n_train_samples"], train_ms=r["train_ms"],
-                             fell_back=r["fell_back"])
-                prop.close()
-            out[name] = entry
-    out["gain_n_eff_per_s"] = out["learned"]["n_eff_per_s"] / max(out["plain"]["n_eff_per_s"], 1e-30)
-    out["d_ln_L_marg"] = out["learned"]["ln_L_marg"] - out["plain"]["ln_L_marg"]
+        t0 = time.perf_counter()
+        r = ctx.run(sampler="adaptive", adapt_chunks=-1, max_samples=50_000_000, seed=41,
+                    chunk=100_000, n_eff_target=target)
+        out["plain"] = entry(r, time.perf_counter() - t0)
+        runs = []
+        for seed in LEARNED_SEEDS:
+            with ile.Proposal(ctx, seed=3) as prop:
+                t0 = time.perf_counter()
+                r = ctx.run(sampler="learned", adapt_chunks=3, max_samples=20_000_000, eps=0.1,
+                            seed=seed, chunk=100_000, n_eff_target=target, prop=prop)
+                e = entry(r, time.perf_counter() - t0)
+            e.update(seed=seed, train_samples=r["n_train_samples"], train_ms=r["train_ms"],
+                     fell_back=r["fell_back"])
+            runs.append(e)
+    import statistics
+    ok = [e for e in runs if not e["fell_back"] and e["n_eff"] >= target]
+    med = statistics.median(e["n_eff_per_s"] for e in runs)
+    out["learned"] = {"seeds": list(LEARNED_SEEDS), "reached_target": len(ok),
+                      "fell_back": sum(e["fell_back"] for e in runs),
+                      "median_n_eff_per_s": med, "runs": runs}
+    out["gain_n_eff_per_s_median"] = med / max(out["plain"]["n_eff_per_s"], 1e-30)
+    if ok:
+        lnls = [e["ln_L_marg"] for e in ok]
+        out["ln_L_marg_learned_median"] = statistics.median(lnls)
+        out["ln_L_marg_learned_spread"] = max(lnls) - min(lnls)
+        out["d_ln_L_marg_vs_plain"] = statistics.median(lnls) - out["plain"]["ln_L_marg"]
     return out
 
 

@@ -235,7 +235,7 @@ typedef struct {
     /* sampler LEARNED only: adapt_chunks (<= 0: 3) adaptive rounds of
      * `chunk` samples fill a training ring of as many chunks and train
      * `prop` (train_steps Adam steps of train_batch, learning rate lr;
-     * <= 0: defaults of ile_prop_train_dev).  Refinement: up to
+     * <= 0: 300, 16384, 2e-3).  Refinement: up to
      * refine_rounds chunks are drawn from (1 - eps) q_net + eps q_hist (the
      * histograms as left by the rounds); each replaces the oldest chunk of
      * the ring and the network is refit (transform and refine_steps warm
@@ -250,10 +250,17 @@ typedef struct {
     int32_t train_steps, train_batch;
     double lr;
     int32_t refine_rounds;   /* (< 0: 8; 0: none)                             */
-    int32_t refine_steps;    /* (<= 0: 600)                                   */
+    int32_t refine_steps;    /* (<= 0: 150)                                   */
     double refine_eff;       /* (<= 0: 0.05)                                  */
     double train_ess;        /* tempering target of the training weights, as
                                 ess_frac of ile_prop_train_opts (<= 0: 0.01) */
+    double refine_kish;      /* also stop refining once a chunk's Kish size
+                                (sum w)^2 / sum w^2 reaches this fraction of
+                                it (<= 0: no such test, the default: a Kish
+                                size can look healthy while the n_eff of the
+                                chunks after it is not)                       */
+    double sigma_scale;      /* kappa set on prop for the refinement and
+                                estimation draws (<= 0: 1.25)                 */
 } ile_run_opts;
 
 /* Monte Carlo estimate of ln L_marg: chunk after chunk, draw on the device,
@@ -275,6 +282,7 @@ typedef struct {
     double final_loss;
     double last_refine_eff;    /* n_eff / n of the last refinement chunk     */
     double refine_eff[32];     /* n_eff / n of refinement chunks 0..31       */
+    double refine_kish[32];    /* Kish size / n of refinement chunks 0..31  */
 } ile_learned_info;
 ile_status ile_last_learned_info(const ile_ctx *ctx, ile_learned_info *out);
 
@@ -319,7 +327,9 @@ ile_status ile_hist_refit_dev(ile_ctx *ctx, const int32_t *bins_dev, int64_t ld,
  * W2[k2][k1] iff deg(k1) <= deg(k2), W3[o][k] iff deg(k) < o / 48; masked
  * entries are held at zero.  Dimension d is a 16-component Gaussian mixture
  * in z~_d with logits o[48d + c], means o[48d + 16 + c] and scales
- * sigma_floor + softplus(o[48d + 32 + c]).
+ * kappa (sigma_floor + softplus(o[48d + 32 + c])): kappa (sigma_scale, 1
+ * by default) widens every component when drawing and evaluating ln q, an
+ * exact density of its own; training always fits the kappa = 1 model.
  *
  * Device arithmetic: layer 1 FP32; layers 2 and 3 BF16 on the matrix cores
  * with FP32 accumulation; mixture densities FP32; transform, Jacobian,
@@ -345,6 +355,7 @@ typedef struct {
     uint64_t seed;           /* initial weights                               */
     int32_t device;
     void *stream;            /* hipStream_t, or NULL for a new one            */
+    double sigma_scale;      /* kappa of the draws and densities (<= 0: 1)    */
 } ile_prop_config;
 
 typedef struct {
@@ -369,6 +380,8 @@ ile_status ile_prop_set_transform(ile_prop *p, const double origin[3], const dou
                                   const double scale[7]);
 ile_status ile_prop_get_transform(ile_prop *p, double origin[3], double mean[7],
                                   double scale[7]);
+/* kappa > 0 for the following draws and densities (ILE_E_ARG otherwise). */
+ile_status ile_prop_set_sigma_scale(ile_prop *p, double kappa);
 /* Fit the transform to device samples x_dev[7][ld] with log-weights
  * lnw_dev, tempered as for training (ess_frac <= 0: 0.01). */
 ile_status ile_prop_fit_transform_dev(ile_prop *p, const double *x_dev, int64_t ld,

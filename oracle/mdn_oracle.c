@@ -140,14 +140,14 @@ static double lse(const double *v, int n)
 
 /* ln q_d of one dimension from its 48 outputs; if g is not NULL, writes
  * d ln q_d / d o for these 48 outputs. */
-static double mixture_dim(const double *o, double zd, double sigma_floor, double *g)
+static double mixture_dim(const double *o, double zd, double sigma_floor, double kappa, double *g)
 {
     const int C = ORC_MDN_C;
     const double *alpha = o, *mu = o + C, *rho = o + 2 * C;
     double la = lse(alpha, C);
     double l[ORC_MDN_C], sig[ORC_MDN_C], r[ORC_MDN_C];
     for (int c = 0; c < C; c++) {
-        sig[c] = sigma_floor + softplus(rho[c]);
+        sig[c] = kappa * (sigma_floor + softplus(rho[c]));
         r[c] = (zd - mu[c]) / sig[c];
         l[c] = alpha[c] - la - 0.5 * r[c] * r[c] - log(sig[c]) - 0.5 * log(2 * PI);
     }
@@ -171,7 +171,8 @@ double orc_mdn_lnq_z(const double *params, const orc_mdn_transform *tr, const do
     forward(params, z, &s);
     double tot = 0.0;
     for (int d = 0; d < ORC_MDN_D; d++) {
-        double v = mixture_dim(s.o + 3 * ORC_MDN_C * d, z[d], tr->sigma_floor, NULL);
+        double v = mixture_dim(s.o + 3 * ORC_MDN_C * d, z[d], tr->sigma_floor, tr->sigma_scale,
+                               NULL);
         if (lnq_dim) lnq_dim[d] = v;
         tot += v;
     }
@@ -213,7 +214,7 @@ void orc_mdn_loss_grad(const double *params, const orc_mdn_transform *tr, const 
         double go[ORC_MDN_O];
         for (int d = 0; d < ORC_MDN_D; d++) {
             double *g = go + 3 * ORC_MDN_C * d;
-            lsum -= wi * mixture_dim(s.o + 3 * ORC_MDN_C * d, z[d], tr->sigma_floor, g);
+            lsum -= wi * mixture_dim(s.o + 3 * ORC_MDN_C * d, z[d], tr->sigma_floor, 1.0, g);
             for (int c = 0; c < 3 * ORC_MDN_C; c++) g[c] *= -wi;
         }
         /* layer 3 */

@@ -24,7 +24,9 @@
  *     M3[o][k] = (m(k) < o / 48)
  *   dimension d uses o[48d + c] (mixture logit), o[48d + 16 + c] (mean),
  *   o[48d + 32 + c] (scale pre-activation rho), c = 0..15;
- *   sigma = sigma_floor + softplus(rho).
+ *   sigma = kappa (sigma_floor + softplus(rho)), kappa = sigma_scale: a
+ *   widening of every component for drawing and evaluating; the training
+ *   loss is that of the kappa = 1 model.
  *   ln q(z~) = sum_d log sum_c softmax(logits)_c N(z~_d; mean_c, sigma_c)
  *
  * Transform x -> z~ (x = ra, dec, psi, phi, cos iota, D, t_ref):
@@ -59,6 +61,7 @@ typedef struct {
     double mean[7], scale[7];
     double d_min, d_max, t_ref_max;
     double sigma_floor;
+    double sigma_scale;   /* kappa of the density (training uses 1) */
 } orc_mdn_transform;
 
 /* Mask value of parameter index j (1 = trainable, 0 = held at zero). */
@@ -83,7 +86,8 @@ void orc_mdn_logpdf(const double *params, const orc_mdn_transform *tr,
 void orc_mdn_outputs(const double *params, const orc_mdn_transform *tr, const double *x,
                      int64_t ld, int64_t n, double *z_out, double *o_out);
 
-/* Weighted negative log-likelihood in z~ space,
+/* Weighted negative log-likelihood in z~ space of the kappa = 1 model
+ * (tr->sigma_scale is not used),
  *   loss = -sum_i w_i ln q(z~_i) / sum_i w_i     (w = NULL: all 1),
  * and its gradient with respect to every parameter (masked entries 0), by
  * hand-written back-propagation. */

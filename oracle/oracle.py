@@ -299,11 +299,11 @@ class MdnTransform(C.Structure):
     _fields_ = [("origin", C.c_double * 3), ("mean", C.c_double * 7),
                 ("scale", C.c_double * 7), ("d_min", C.c_double),
                 ("d_max", C.c_double), ("t_ref_max", C.c_double),
-                ("sigma_floor", C.c_double)]
+                ("sigma_floor", C.c_double), ("sigma_scale", C.c_double)]
 
 
 def mdn_transform(origin=(0.0, 0.0, 0.0), mean=None, scale=None, d_min=10.0,
-                  d_max=1000.0, t_ref_max=0.01, sigma_floor=1e-3):
+                  d_max=1000.0, t_ref_max=0.01, sigma_floor=1e-3, sigma_scale=1.0):
     tr = MdnTransform()
     for j in range(3):
         tr.origin[j] = origin[j]
@@ -312,6 +312,7 @@ def mdn_transform(origin=(0.0, 0.0, 0.0), mean=None, scale=None, d_min=10.0,
         tr.scale[d] = 1.0 if scale is None else scale[d]
     tr.d_min, tr.d_max, tr.t_ref_max = d_min, d_max, t_ref_max
     tr.sigma_floor = sigma_floor
+    tr.sigma_scale = sigma_scale
     return tr
 
 

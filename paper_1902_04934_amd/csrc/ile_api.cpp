@@ -901,9 +901,13 @@ static ile_status run_learned(ile_ctx *c, const ile_run_opts *o, ile_result *out
     const double eps = o->eps >= 0 ? o->eps : 0.1;
     const double fb = o->fallback_neff >= 0 ? o->fallback_neff : 1000.0;
     const int refine_rounds = o->refine_rounds >= 0 ? o->refine_rounds : 8;
-    const int refine_steps = o->refine_steps > 0 ? o->refine_steps : 600;
+    const int refine_steps = o->refine_steps > 0 ? o->refine_steps : 150;
     const double refine_eff = o->refine_eff > 0 ? o->refine_eff : 0.05;
+    const double kappa = o->sigma_scale > 0 ? o->sigma_scale : 1.25;
     if (floor_w > 1 || eps >= 1) return fail(c, ILE_E_ARG, "floor > 1 or eps >= 1");
+    if (!std::isfinite(kappa)) return fail(c, ILE_E_ARG, "bad sigma scale");
+    if (ile_prop_set_sigma_scale(o->prop, kappa) != ILE_OK)
+        return fail(c, ILE_E_DEVICE, "sigma scale: %s", ile_prop_last_error(o->prop));
     const int64_t ntr = (int64_t)rounds * chunk;
     if (ntr > ((int64_t)1 << 30)) return fail(c, ILE_E_ARG, "training set too large");
     const int64_t max_chunks = (o->max_samples + chunk - 1) / chunk;
@@ -941,9 +945,9 @@ static ile_status run_learned(ile_ctx *c, const ile_run_opts *o, ile_result *out
     }
     // 2. training
     ile_prop_train_opts to{};
-    to.steps = o->train_steps;
-    to.batch = o->train_batch;
-    to.lr = o->lr;
+    to.steps = o->train_steps > 0 ? o->train_steps : 300;
+    to.batch = o->train_batch > 0 ? o->train_batch : 16384;
+    to.lr = o->lr > 0 ? o->lr : 2e-3;
     to.ess_frac = o->train_ess > 0 ? o->train_ess : 0.01;
     to.seed = o->seed;
     to.fit_transform = 1;
@@ -978,8 +982,12 @@ static ile_status run_learned(ile_ctx *c, const ile_run_opts *o, ile_result *out
         HIP_TRY(c, hipMemcpy(r, c->res.p, sizeof(r), hipMemcpyDeviceToHost));
         c->learned.n_refine_samples += chunk;
         c->learned.last_refine_eff = r[1] / (double)chunk;
-        if (rr < 32) c->learned.refine_eff[rr] = c->learned.last_refine_eff;
+        if (rr < 32) {
+            c->learned.refine_eff[rr] = c->learned.last_refine_eff;
+            c->learned.refine_kish[rr] = r[2] / (double)chunk;
+        }
         if (r[1] >= refine_eff * (double)chunk) break;
+        if (o->refine_kish > 0 && r[2] >= o->refine_kish * (double)chunk) break;
         if (ile_prop_train_dev(o->prop, trx, ntr, trw, ntr, &to, &loss) != ILE_OK)
             return fail(c, ILE_E_DEVICE, "refit failed: %s", ile_prop_last_error(o->prop));
         c->learned.train_ms += ile_prop_last_ms(o->prop);

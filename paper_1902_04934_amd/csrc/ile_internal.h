@@ -171,6 +171,7 @@ struct ile_mdn_tr {
     double origin[3];   // ra, psi, phi origins
     double mean[7], scale[7];
     double d_min, d_max, t_ref_max, sigma_floor;
+    double sigma_scale;   // kappa of draws and densities (training: 1)
 };
 
 // Device state of one proposal.
@@ -214,9 +215,12 @@ hipError_t ile_launch_mdn_prepare(const ile_mdn_tr *tr, const double *x, int64_t
 hipError_t ile_launch_mdn_prepare_w(const ile_mdn_tr *tr, const double *x, int64_t ld,
                                     const double *w_in, int64_t n, float *z, double *w,
                                     hipStream_t st);
-hipError_t ile_launch_mdn_cdf(const double *w, int64_t n, double *cdf, hipStream_t st);
-hipError_t ile_launch_mdn_draw_idx(uint64_t seed, int64_t step, int batch, const double *cdf,
-                                   int64_t n, int32_t *idx, hipStream_t st);
+hipError_t ile_launch_mdn_cdf(const double *w, int64_t n, double *cdf, double *ws,
+                              hipStream_t st);   // ws: ile_mdn_fit_ws_doubles() doubles
+// count minibatch draws (index i with probability w_i / sum w), Philox
+// counters (draw, 0, 0x4D444E54) of key seed
+hipError_t ile_launch_mdn_draw_idx(uint64_t seed, int64_t count, const double *cdf, int64_t n,
+                                   int32_t *idx, hipStream_t st);
 // Forward + backward of a batch: per-workgroup partials [grid][NPART].
 hipError_t ile_launch_mdn_grad(const ile_mdn_dev &M, const float *z, int64_t ldz,
                                const int32_t *idx, const double *w, int batch, float *part,

@@ -58,19 +58,61 @@ __device__ inline v4f mfma(v8bf a, v8bf b, v4f c)
 __device__ inline float softplusf(float x) { return fmaxf(x, 0.f) + log1pf(expf(-fabsf(x))); }
 __device__ inline float sigmoidf(float x) { return 1.f / (1.f + expf(-x)); }
 
-// 16-lane butterflies: every lane of the group ends with the same value
-// (each step adds the same two operands in either order)
+// Branch-free functions at the hardware's transcendental rate for the
+// training gradient (a few ulp; the BF16 operands of the products dominate
+// its error).  exp and log through the base-2 instructions.
+__device__ inline float fexp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+__device__ inline float flog(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
+__device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// tanh: odd Taylor series through x^9 for |x| < 0.2 (truncation < 1e-9
+// relative), else (1 - e) / (1 + e) with e = exp(-2|x|)
+__device__ inline float ftanh(float x)
+{
+    const float ax = fabsf(x), x2 = x * x;
+    const float poly = ax + ax * x2 * (-1.f / 3.f + x2 * (2.f / 15.f + x2 * (-17.f / 315.f +
+                                                                        x2 * (62.f / 2835.f))));
+    const float e = fexp(-2.f * ax);
+    const float big = (1.f - e) * frcp(1.f + e);
+    return copysignf(ax < 0.2f ? poly : big, x);
+}
+__device__ inline float fsoftplus(float x) { return fmaxf(x, 0.f) + flog(1.f + fexp(-fabsf(x))); }
+__device__ inline float fsigmoid(float x) { return frcp(1.f + fexp(-x)); }
+
+// 16-lane reductions by DPP rotations within a row (8, 4, 2, 1 lanes):
+// after the rotation by n the partial values repeat with period n, so
+// lane i meets the same partner value as in an xor butterfly, and every
+// lane of the group ends with the same bits (each step combines the same
+// two operands in either order).  DPP moves data between lanes in the
+// VALU, without the LDS round trip of a permute.
+template <int N>
+__device__ inline float row_ror(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+        0, __builtin_bit_cast(int, x), 0x120 + N, 0xF, 0xF, false));
+}
 __device__ inline float gmax(float x)
 {
-#pragma unroll
-    for (int m = 8; m; m >>= 1) x = fmaxf(x, __shfl_xor(x, m, 16));
-    return x;
+    x = fmaxf(x, row_ror<8>(x));
+    x = fmaxf(x, row_ror<4>(x));
+    x = fmaxf(x, row_ror<2>(x));
+    return fmaxf(x, row_ror<1>(x));
 }
 __device__ inline float gsum(float x)
 {
-#pragma unroll
-    for (int m = 8; m; m >>= 1) x += __shfl_xor(x, m, 16);
-    return x;
+    x += row_ror<8>(x);
+    x += row_ror<4>(x);
+    x += row_ror<2>(x);
+    return x + row_ror<1>(x);
+}
+
+// Ordering point for LDS data handed between lanes of one wave: a wave's
+// LDS accesses are performed in issue order, so it is enough that the
+// compiler moves no access across this point (no workgroup barrier).
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // ------------------------------------------------------------ transform
@@ -168,6 +210,7 @@ __device__ inline double ln_hist_ratio(const double *P, int nb, double ra, doubl
 
 // ---------------------------------------------------------- the layers
 // Layer 1 for sample r: units k = 32 ks + 8 g + i as BF16 A fragments.
+template <bool FAST = false>
 __device__ inline void layer1(const float *W1, int w1ld, const float *b1, const float z[7],
                               int g, v8bf A[4])
 {
@@ -179,7 +222,7 @@ __device__ inline void layer1(const float *W1, int w1ld, const float *b1, const 
             float a = b1[k];
 #pragma unroll
             for (int d = 0; d < D; d++) a = fmaf(W1[k * w1ld + d], z[d], a);
-            A[ks][i] = (__bf16)tanhf(a);
+            A[ks][i] = (__bf16)(FAST ? ftanh(a) : tanhf(a));
         }
     }
 }
@@ -201,6 +244,16 @@ __device__ inline void layer2(const v8bf A[4], const __bf16 *W2, int ld, int r, 
     }
 }
 
+// B fragments of the three layer-3 output tiles of dimension d, [4 ks][3 j].
+__device__ inline void load_w3_dim(const __bf16 *W3, int ld, int d, int r, int g, v8bf B[12])
+{
+#pragma unroll
+    for (int ks = 0; ks < 4; ks++)
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+            B[3 * ks + j] = *(const v8bf *)(W3 + (48 * d + 16 * j + r) * ld + 32 * ks + 8 * g);
+}
+
 // Three output tiles 3d, 3d+1, 3d+2 (dimension d) of layer 3.
 __device__ inline void layer3_dim(const v8bf A2[4], const __bf16 *W3, int ld, int d, int r,
                                   int g, v4f t3[3])
@@ -220,16 +273,30 @@ __device__ inline void layer3_dim(const v8bf A2[4], const __bf16 *W3, int ld, in
 // ln q_d of one sample from its component (lane r of the group): returns
 // the log density; sig, rr = (z - mu)/sig, ell = log weight + log normal
 // of this component, la = log-sum-exp of the logits.
-__device__ inline float mix_lnq(float a, float mu, float rho, float z, float sfloor, float &sig,
-                                float &rr, float &ell, float &la)
+__device__ inline float mix_lnq(float a, float mu, float rho, float z, float sfloor, float kappa,
+                                float &sig, float &rr, float &ell, float &la)
 {
     const float ma = gmax(a);
     la = ma + logf(gsum(expf(a - ma)));
-    sig = sfloor + softplusf(rho);
+    sig = kappa * (sfloor + softplusf(rho));
     rr = (z - mu) / sig;
     ell = a - la - 0.5f * rr * rr - logf(sig) - kHalfLn2Pi;
     const float ml = gmax(ell);
     return ml + logf(gsum(expf(ell - ml)));
+}
+
+// mix_lnq with the branch-free functions (training gradient); rs = 1/sig
+__device__ inline float mix_lnq_fast(float a, float mu, float rho, float z, float sfloor,
+                                     float &rs, float &rr, float &ell, float &la)
+{
+    const float ma = gmax(a);
+    la = ma + flog(gsum(fexp(a - ma)));
+    const float sig = sfloor + fsoftplus(rho);
+    rs = frcp(sig);
+    rr = (z - mu) * rs;
+    ell = a - la - 0.5f * rr * rr - flog(sig) - kHalfLn2Pi;
+    const float ml = gmax(ell);
+    return ml + flog(gsum(fexp(ell - ml)));
 }
 
 // ----------------------------------------------------------- inference
@@ -281,7 +348,7 @@ __global__ __launch_bounds__(256) void k_mdn_infer(
     }
     if (tid == 0) sT = *trp;
     __syncthreads();
-    const float sfloor = (float)sT.sigma_floor;
+    const float sfloor = (float)sT.sigma_floor, kappa = (float)sT.sigma_scale;
     __bf16 *Hs = sH[w];
     float *Zs = sZ[w], *Rs = sR[w];
 
@@ -361,7 +428,7 @@ __global__ __launch_bounds__(256) void k_mdn_infer(
                     const unsigned long long bal = __ballot(cum > Rs[s * 16 + d] * tot);
                     const unsigned bits = (unsigned)(bal >> (16 * g)) & 0xffffu;
                     const int cs = bits ? __ffs(bits) - 1 : 15;
-                    const float sig = sfloor + softplusf(rho);
+                    const float sig = kappa * (sfloor + softplusf(rho));
                     const float mus = __shfl(mu, cs, 16), sgs = __shfl(sig, cs, 16);
                     if (r == 0) Zs[s * 8 + d] = mus + sgs * Rs[s * 16 + 7 + d];
                 }
@@ -422,7 +489,7 @@ __global__ __launch_bounds__(256) void k_mdn_infer(
                     float sig, rr, ell, la;
                     lqz[v] += mix_lnq(t3[0][v] + sb3[48 * d + r], t3[1][v] + sb3[48 * d + 16 + r],
                                       t3[2][v] + sb3[48 * d + 32 + r], Zs[(4 * g + v) * 8 + d],
-                                      sfloor, sig, rr, ell, la);
+                                      sfloor, kappa, sig, rr, ell, la);
                 }
             }
             if (r == 0)
@@ -466,15 +533,23 @@ __global__ __launch_bounds__(256) void k_mdn_grad(
     __shared__ __attribute__((aligned(16))) __bf16 sHs[4][16 * WLD]; // per wave: h2, then dL/da2 [s][unit]
     __shared__ __attribute__((aligned(16))) __bf16 sDOc[4][16 * CLD];// per wave: 96 outputs of dL/do [s][o]
     __shared__ float sLoss[4];
+    __shared__ float sPar[OFF_W2 + H + O];   // FP32 W1, b1, b2, b3
 
-    const float *W1 = theta + OFF_W1, *b1 = theta + OFF_B1, *b2 = theta + OFF_B2,
-                *b3 = theta + OFF_B3;
+    const float *W1 = sPar, *b1 = sPar + OFF_B1, *b2 = sPar + OFF_W2,
+                *b3 = sPar + OFF_W2 + H;
     const float sfloor = (float)trp->sigma_floor;
     const int tid = threadIdx.x, lane = tid & 63, r = lane & 15, g = lane >> 4;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int s0 = 16 * w;
     __bf16 *Hs = sHs[w], *DOc = sDOc[w];
 
+    // layer-2 fragments first: their loads overlap the staging below
+    v8bf B2f[32];
+#pragma unroll
+    for (int ks = 0; ks < 4; ks++)
+#pragma unroll
+        for (int t = 0; t < 8; t++)
+            B2f[8 * ks + t] = *(const v8bf *)(W2b + (16 * t + r) * H + 32 * ks + 8 * g);
     if (g == 0) {
         const int64_t b = (int64_t)blockIdx.x * 64 + s0 + r;
         const bool valid = b < batch;
@@ -482,6 +557,9 @@ __global__ __launch_bounds__(256) void k_mdn_grad(
         for (int d = 0; d < 8; d++) sZ[(s0 + r) * 8 + d] = (valid && d < D) ? zt[d * ldz + row] : 0.f;
         sWt[s0 + r] = valid ? (wts ? (float)wts[row] : 1.f) : 0.f;
     }
+    for (int e = tid; e < OFF_W2 + H + O; e += 256)
+        sPar[e] = e < OFF_W2 ? theta[OFF_W1 + e]
+                : e < OFF_W2 + H ? theta[OFF_B2 + e - OFF_W2] : theta[OFF_B3 + e - OFF_W2 - H];
     __syncthreads();
 
     // ---- forward
@@ -490,7 +568,7 @@ __global__ __launch_bounds__(256) void k_mdn_grad(
         float z[7];
 #pragma unroll
         for (int d = 0; d < D; d++) z[d] = sZ[(s0 + r) * 8 + d];
-        layer1(W1, D, b1, z, g, A1);
+        layer1<true>(W1, D, b1, z, g, A1);
     }
 #pragma unroll
     for (int ks = 0; ks < 4; ks++)
@@ -499,14 +577,19 @@ __global__ __launch_bounds__(256) void k_mdn_grad(
     float h2v[8][4];
     {
         v4f acc[8];
-        layer2(A1, W2b, H, r, g, acc);
+#pragma unroll
+        for (int t = 0; t < 8; t++) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ks++)
+#pragma unroll
+            for (int t = 0; t < 8; t++) acc[t] = mfma(A1[ks], B2f[8 * ks + t], acc[t]);
 #pragma unroll
         for (int t = 0; t < 8; t++) {
             const float bb = b2[16 * t + r];
             v4bf pk;
 #pragma unroll
             for (int v = 0; v < 4; v++) {
-                const float h = tanhf(acc[t][v] + bb);
+                const float h = ftanh(acc[t][v] + bb);
                 h2v[t][v] = h;
                 pk[v] = (__bf16)h;
                 Hs[(4 * g + v) * WLD + 16 * t + r] = pk[v];
@@ -514,22 +597,43 @@ __global__ __launch_bounds__(256) void k_mdn_grad(
             *(v4bf *)(sH2T + (16 * t + r) * SLD + s0 + 4 * g) = pk;
         }
     }
-    __syncthreads();
+    wave_lds_sync();   // Hs is the wave's own; sH2T is read after later barriers
     v8bf A2[4];
 #pragma unroll
     for (int ks = 0; ks < 4; ks++) A2[ks] = *(const v8bf *)(Hs + r * WLD + 32 * ks + 8 * g);
 
-    // ---- layer 3, mixture gradients and dL/dh2, two dimensions at a time
+    // ---- layer 3, mixture gradients and dL/dh2, two dimensions at a time.
+    // The W3 fragments of the next dimension and the W3^T fragments of the
+    // current pair are loaded ahead of the arithmetic that needs them.
     v4f dh2[8];
 #pragma unroll
     for (int t = 0; t < 8; t++) dh2[t] = v4f{0.f, 0.f, 0.f, 0.f};
     float lacc = 0.f;
+    v8bf Bn[12];
+    load_w3_dim(W3b, H, 0, r, g, Bn);
+#pragma unroll 1
     for (int p = 0; p < 4; p++) {
+        v8bf Bt[24];
+#pragma unroll
+        for (int ks = 0; ks < 3; ks++)
+#pragma unroll
+            for (int t = 0; t < 8; t++)
+                Bt[8 * ks + t] = *(const v8bf *)(W3t + (16 * t + r) * W3T_LD + 96 * p + 32 * ks + 8 * g);
+#pragma unroll
         for (int dd = 0; dd < 2; dd++) {
             const int d = 2 * p + dd;
             if (d < D) {
+                v8bf Bc[12];
+#pragma unroll
+                for (int j = 0; j < 12; j++) Bc[j] = Bn[j];
+                if (d + 1 < D) load_w3_dim(W3b, H, d + 1, r, g, Bn);
                 v4f t3[3];
-                layer3_dim(A2, W3b, H, d, r, g, t3);
+#pragma unroll
+                for (int j = 0; j < 3; j++) t3[j] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < 4; ks++)
+#pragma unroll
+                    for (int j = 0; j < 3; j++) t3[j] = mfma(A2[ks], Bc[3 * ks + j], t3[j]);
                 v4bf ga, gm, gr;
 #pragma unroll
                 for (int v = 0; v < 4; v++) {
@@ -538,13 +642,13 @@ __global__ __launch_bounds__(256) void k_mdn_grad(
                     const float mu = t3[1][v] + b3[48 * d + 16 + r];
                     const float rho = t3[2][v] + b3[48 * d + 32 + r];
                     const float ws = sWt[s0 + s];
-                    float sig, rr, ell, la;
-                    const float lq = mix_lnq(al, mu, rho, sZ[(s0 + s) * 8 + d], sfloor, sig, rr, ell, la);
-                    const float gam = expf(ell - lq), pi = expf(al - la);
+                    float rs, rr, ell, la;
+                    const float lq = mix_lnq_fast(al, mu, rho, sZ[(s0 + s) * 8 + d], sfloor, rs, rr, ell, la);
+                    const float gam = fexp(ell - lq), pi = fexp(al - la);
                     if (r == 0) lacc -= ws * lq;
                     ga[v] = (__bf16)(-ws * (gam - pi));
-                    gm[v] = (__bf16)(-ws * gam * rr / sig);
-                    gr[v] = (__bf16)(-ws * gam * (rr * rr - 1.f) / sig * sigmoidf(rho));
+                    gm[v] = (__bf16)(-ws * gam * rr * rs);
+                    gr[v] = (__bf16)(-ws * gam * (rr * rr - 1.f) * rs * fsigmoid(rho));
                     DOc[s * CLD + 48 * dd + r] = ga[v];
                     DOc[s * CLD + 48 * dd + 16 + r] = gm[v];
                     DOc[s * CLD + 48 * dd + 32 + r] = gr[v];
@@ -559,20 +663,23 @@ __global__ __launch_bounds__(256) void k_mdn_grad(
                     for (int j = 0; j < 3; j++) DOc[(4 * g + v) * CLD + 48 * dd + 16 * j + r] = (__bf16)0.f;
             }
         }
-        __syncthreads();
+        wave_lds_sync();   // DOc is the wave's own
 #pragma unroll
         for (int ks = 0; ks < 3; ks++) {
             const v8bf a = *(const v8bf *)(DOc + r * CLD + 32 * ks + 8 * g);
 #pragma unroll
-            for (int t = 0; t < 8; t++) {
-                const v8bf b = *(const v8bf *)(W3t + (16 * t + r) * W3T_LD + 96 * p + 32 * ks + 8 * g);
-                dh2[t] = mfma(a, b, dh2[t]);
-            }
+            for (int t = 0; t < 8; t++) dh2[t] = mfma(a, Bt[8 * ks + t], dh2[t]);
         }
-        __syncthreads();
+        wave_lds_sync();
     }
 
     // ---- dL/da2 = dL/dh2 (1 - h2^2)
+    v8bf B2[32];
+#pragma unroll
+    for (int ks = 0; ks < 4; ks++)
+#pragma unroll
+        for (int t = 0; t < 8; t++)
+            B2[8 * ks + t] = *(const v8bf *)(W2t + (16 * t + r) * H + 32 * ks + 8 * g);
 #pragma unroll
     for (int t = 0; t < 8; t++) {
         v4bf pk;
@@ -583,7 +690,7 @@ __global__ __launch_bounds__(256) void k_mdn_grad(
         }
         *(v4bf *)(sDA2T + (16 * t + r) * SLD + s0 + 4 * g) = pk;
     }
-    __syncthreads();
+    wave_lds_sync();   // Hs is the wave's own; sDA2T is read after later barriers
 
     // ---- dL/dh1 = W2^T dL/da2, dL/da1 = dL/dh1 (1 - h1^2), h1 recomputed in FP32
     {
@@ -596,10 +703,7 @@ __global__ __launch_bounds__(256) void k_mdn_grad(
 #pragma unroll
         for (int ks = 0; ks < 4; ks++)
 #pragma unroll
-            for (int t = 0; t < 8; t++) {
-                const v8bf b = *(const v8bf *)(W2t + (16 * t + r) * H + 32 * ks + 8 * g);
-                dh1[t] = mfma(Ad[ks], b, dh1[t]);
-            }
+            for (int t = 0; t < 8; t++) dh1[t] = mfma(Ad[ks], B2[8 * ks + t], dh1[t]);
 #pragma unroll
         for (int t = 0; t < 8; t++) {
             const int k = 16 * t + r;
@@ -614,7 +718,7 @@ __global__ __launch_bounds__(256) void k_mdn_grad(
                 float a = bk;
 #pragma unroll
                 for (int d = 0; d < D; d++) a = fmaf(wk[d], sZ[s * 8 + d], a);
-                const float h = tanhf(a);
+                const float h = ftanh(a);
                 pk[v] = (__bf16)(dh1[t][v] * (1.f - h * h));
             }
             *(v4bf *)(sDA1T + k * SLD + s0 + 4 * g) = pk;
@@ -627,6 +731,8 @@ __global__ __launch_bounds__(256) void k_mdn_grad(
 
     // ---- weight gradients over the workgroup's 64 samples
     float *P = part + (size_t)blockIdx.x * NPART;
+    // (products taken as (dL/dW)^T tiles, so that each lane holds four
+    // consecutive k of one output row: one 16-byte store per lane and tile)
     for (int q = w; q < 21 * 8; q += 4) {
         const int ot = q >> 3, kt = q & 7;
         v4f a = v4f{0.f, 0.f, 0.f, 0.f};
@@ -634,10 +740,9 @@ __global__ __launch_bounds__(256) void k_mdn_grad(
         for (int ks = 0; ks < 2; ks++) {
             const v8bf A = *(const v8bf *)(sDOT + (16 * ot + r) * SLD + 32 * ks + 8 * g);
             const v8bf B = *(const v8bf *)(sH2T + (16 * kt + r) * SLD + 32 * ks + 8 * g);
-            a = mfma(A, B, a);
+            a = mfma(B, A, a);
         }
-#pragma unroll
-        for (int v = 0; v < 4; v++) P[OFF_W3 + (16 * ot + 4 * g + v) * H + 16 * kt + r] = a[v];
+        *(v4f *)(P + OFF_W3 + (16 * ot + r) * H + 16 * kt + 4 * g) = a;
     }
     for (int q = w; q < 8 * 8; q += 4) {
         const int ot = q >> 3, kt = q & 7;
@@ -646,10 +751,9 @@ __global__ __launch_bounds__(256) void k_mdn_grad(
         for (int ks = 0; ks < 2; ks++) {
             const v8bf A = *(const v8bf *)(sDA2T + (16 * ot + r) * SLD + 32 * ks + 8 * g);
             const v8bf B = *(const v8bf *)(sH1T + (16 * kt + r) * SLD + 32 * ks + 8 * g);
-            a = mfma(A, B, a);
+            a = mfma(B, A, a);
         }
-#pragma unroll
-        for (int v = 0; v < 4; v++) P[OFF_W2 + (16 * ot + 4 * g + v) * H + 16 * kt + r] = a[v];
+        *(v4f *)(P + OFF_W2 + (16 * ot + r) * H + 16 * kt + 4 * g) = a;
     }
     for (int o = tid; o < O; o += 256) {
         float acc = 0.f;
@@ -708,7 +812,10 @@ __global__ __launch_bounds__(256) void k_mdn_update(ile_mdn_dev M, const float *
 {
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= NPARAM) return;
+    // sums in row order; the loads are independent, so unrolling lets many
+    // be in flight at once
     float ws = 0.f, gs = 0.f;
+#pragma unroll 16
     for (int t = 0; t < np; t++) {
         ws += part[(size_t)t * NPART + NPARAM + 1];
         gs += part[(size_t)t * NPART + j];
@@ -731,7 +838,6 @@ __global__ __launch_bounds__(256) void k_mdn_update(ile_mdn_dev M, const float *
 }
 
 // ------------------------------------------------- training-set pieces
-constexpr int FT = 1024;
 
 // Transform fit, multi-block with fixed partitions and fixed-order merges
 // (bit-reproducible).  Tempering of the training weights w = exp(beta (ln w
@@ -962,43 +1068,74 @@ __global__ __launch_bounds__(256) void k_mdn_prepare(const ile_mdn_tr *__restric
     w[i] = lj == -INFINITY ? 0.0 : wi;
 }
 
-// inclusive prefix sums (one workgroup, contiguous chunks per thread)
-__global__ __launch_bounds__(FT) void k_mdn_cdf(const double *__restrict__ w, int64_t n,
-                                                double *cdf)
+// inclusive prefix sums: CB blocks of 256 threads, each thread a contiguous
+// chunk; chunk totals are scanned in order by one thread, then each chunk
+// is written from its offset (fixed order: bit-reproducible)
+constexpr int CB = 64;
+__global__ __launch_bounds__(256) void k_mdn_cdf_part(const double *__restrict__ w, int64_t n,
+                                                      double *tot)
 {
-    __shared__ double sc[FT];
-    const int64_t per = (n + FT - 1) / FT;
-    const int64_t lo0 = (int64_t)threadIdx.x * per;
-    const int64_t lo = lo0 < n ? lo0 : n, hi = lo + per < n ? lo + per : n;
+    const int64_t T = (int64_t)CB * 256, per = (n + T - 1) / T;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t lo = t * per < n ? t * per : n, hi = lo + per < n ? lo + per : n;
     double s = 0.0;
     for (int64_t i = lo; i < hi; i++) s += w[i];
-    sc[threadIdx.x] = s;
+    tot[t] = s;
+}
+
+// exclusive scan of the CB * 256 chunk totals: each of 256 threads scans 64
+// consecutive totals, thread 0 scans the 256 thread sums, each thread adds
+// its offset (fixed order)
+__global__ __launch_bounds__(256) void k_mdn_cdf_scan(double *tot)
+{
+    __shared__ double ts[256];
+    constexpr int PER = CB;   // CB * 256 totals over 256 threads
+    double *mine = tot + (size_t)threadIdx.x * PER;
+    double run = 0.0;
+    for (int i = 0; i < PER; i++) {
+        const double v = mine[i];
+        mine[i] = run;
+        run += v;
+    }
+    ts[threadIdx.x] = run;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double run = 0.0;
-        for (int t = 0; t < FT; t++) {
-            const double v = sc[t];
-            sc[t] = run;
-            run += v;
+        double acc = 0.0;
+        for (int t = 0; t < 256; t++) {
+            const double v = ts[t];
+            ts[t] = acc;
+            acc += v;
         }
     }
     __syncthreads();
-    double run = sc[threadIdx.x];
+    const double off = ts[threadIdx.x];
+    for (int i = 0; i < PER; i++) mine[i] += off;
+}
+
+__global__ __launch_bounds__(256) void k_mdn_cdf_write(const double *__restrict__ w, int64_t n,
+                                                       const double *__restrict__ tot, double *cdf)
+{
+    const int64_t T = (int64_t)CB * 256, per = (n + T - 1) / T;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t lo = t * per < n ? t * per : n, hi = lo + per < n ? lo + per : n;
+    double run = tot[t];
     for (int64_t i = lo; i < hi; i++) {
         run += w[i];
         cdf[i] = run;
     }
 }
 
-// minibatch slot b: training index drawn with probability w_i / sum w
-__global__ __launch_bounds__(256) void k_mdn_draw_idx(uint64_t seed, int64_t step, int batch,
+// draw b of a training call: training index drawn with probability
+// w_i / sum w (independent draws; step t of the call uses draws
+// t*batch .. t*batch + batch - 1)
+__global__ __launch_bounds__(256) void k_mdn_draw_idx(uint64_t seed, int64_t count,
                                                       const double *__restrict__ cdf, int64_t n,
                                                       int32_t *idx)
 {
-    const int b = blockIdx.x * 256 + threadIdx.x;
-    if (b >= batch) return;
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= count) return;
     uint32_t q[4];
-    ile_rng::block(seed, (uint64_t)b, (uint32_t)step, ile_rng::kTagTrain, q);
+    ile_rng::block(seed, (uint64_t)b, 0u, ile_rng::kTagTrain, q);
     const double target = ile_rng::u53(q[0], q[1]) * cdf[n - 1];
     int64_t lo = 0, hi = n - 1;   // first i with cdf[i] > target
     while (lo < hi) {
@@ -1069,7 +1206,7 @@ hipError_t ile_launch_mdn_fit(const double *x, int64_t ld, const double *lnw, in
     return hipGetLastError();
 }
 
-size_t ile_mdn_fit_ws_doubles() { return 16 + (size_t)FB * 16; }
+size_t ile_mdn_fit_ws_doubles() { return std::max<size_t>(16 + (size_t)FB * 16, (size_t)CB * 256); }
 
 hipError_t ile_launch_mdn_prepare(const ile_mdn_tr *tr, const double *x, int64_t ld,
                                   const double *lnw, int64_t n, const double *stats, float *z,
@@ -1091,17 +1228,22 @@ hipError_t ile_launch_mdn_prepare_w(const ile_mdn_tr *tr, const double *x, int64
     return hipGetLastError();
 }
 
-hipError_t ile_launch_mdn_cdf(const double *w, int64_t n, double *cdf, hipStream_t st)
+hipError_t ile_launch_mdn_cdf(const double *w, int64_t n, double *cdf, double *ws,
+                              hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mdn_cdf, dim3(1), dim3(FT), 0, st, w, n, cdf);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mdn_cdf_part, dim3(CB), dim3(256), 0, st, w, n, ws);
+    hipLaunchKernelGGL(k_mdn_cdf_scan, dim3(1), dim3(256), 0, st, ws);
+    hipLaunchKernelGGL(k_mdn_cdf_write, dim3(CB), dim3(256), 0, st, w, n, (const double *)ws, cdf);
     return hipGetLastError();
 }
 
-hipError_t ile_launch_mdn_draw_idx(uint64_t seed, int64_t step, int batch, const double *cdf,
-                                   int64_t n, int32_t *idx, hipStream_t st)
+hipError_t ile_launch_mdn_draw_idx(uint64_t seed, int64_t count, const double *cdf, int64_t n,
+                                   int32_t *idx, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mdn_draw_idx, dim3((batch + 255) / 256), dim3(256), 0, st, seed, step,
-                       batch, cdf, n, idx);
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mdn_draw_idx, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
+                       seed, count, cdf, n, idx);
     return hipGetLastError();
 }
 

@@ -196,6 +196,7 @@ ile_status ile_prop_create(const ile_prop_config *cfg, ile_prop **out)
     p->tr.d_max = cfg->d_max_mpc;
     p->tr.t_ref_max = cfg->t_ref_max_s;
     p->tr.sigma_floor = cfg->sigma_floor > 0 ? cfg->sigma_floor : 1e-3;
+    p->tr.sigma_scale = cfg->sigma_scale > 0 ? cfg->sigma_scale : 1.0;
     std::vector<float> P0 = initial_params(cfg->seed);
     // the zero tail of the transposed W3 copy (outputs 336..383) is never written again
     if (hipMemsetAsync(p->M.W3t, 0, ILE_MDN_H * ILE_MDN_W3T_LD * 2, p->stream) != hipSuccess ||
@@ -268,6 +269,17 @@ ile_status ile_prop_get_transform(ile_prop *p, double origin[3], double mean[7],
     return ILE_OK;
 }
 
+ile_status ile_prop_set_sigma_scale(ile_prop *p, double kappa)
+{
+    if (!p) return ILE_E_ARG;
+    if (!(kappa > 0) || !std::isfinite(kappa)) return pfail(p, ILE_E_ARG, "sigma scale must be > 0");
+    PHIP(p, hipSetDevice(p->cfg.device));
+    ile_status s = download_tr(p);   // keep what a fit left on the device
+    if (s) return s;
+    p->tr.sigma_scale = kappa;
+    return upload_tr(p);
+}
+
 ile_status ile_prop_fit_transform_dev(ile_prop *p, const double *x, int64_t ld, const double *lnw,
                                       int64_t n, double ess_frac)
 {
@@ -319,25 +331,28 @@ ile_status ile_prop_train_dev(ile_prop *p, const double *x, int64_t ld, const do
     const int batch = d.batch > 0 ? d.batch : 4096;
     const double lr = d.lr > 0 ? d.lr : 1e-3;
     const double ess_frac = d.ess_frac > 0 ? d.ess_frac : 0.01;
-    if (batch > (1 << 20) || ess_frac > 1) return pfail(p, ILE_E_ARG, "batch or ess_frac");
+    if (batch > (1 << 20) || ess_frac > 1 || (int64_t)batch * steps > ((int64_t)1 << 28))
+        return pfail(p, ILE_E_ARG, "batch, steps or ess_frac out of range");
     PHIP(p, hipSetDevice(p->cfg.device));
     const int nblk = (batch + ILE_MDN_TILE - 1) / ILE_MDN_TILE;
     if ((s = grow(p, p->z, p->z_b, (size_t)n * 7 * sizeof(float)))) return s;
     if ((s = grow(p, p->w, p->w_b, (size_t)n * sizeof(double)))) return s;
     if ((s = grow(p, p->cdf, p->cdf_b, (size_t)n * sizeof(double)))) return s;
-    if ((s = grow(p, p->idx, p->idx_b, (size_t)batch * sizeof(int32_t)))) return s;
+    if ((s = grow(p, p->idx, p->idx_b, (size_t)batch * steps * sizeof(int32_t)))) return s;
     if ((s = grow(p, p->part, p->part_b, (size_t)nblk * ILE_MDN_NPART * sizeof(float)))) return s;
     PHIP(p, ile_launch_mdn_fit(x, ld, lnw, n, ess_frac, p->M.tr, (double *)p->stats,
                                (double *)p->ws, d.fit_transform != 0, p->stream));
     PHIP(p, ile_launch_mdn_prepare(p->M.tr, x, ld, lnw, n, (const double *)p->stats,
                                    (float *)p->z, (double *)p->w, p->stream));
-    PHIP(p, ile_launch_mdn_cdf((const double *)p->w, n, (double *)p->cdf, p->stream));
+    PHIP(p, ile_launch_mdn_cdf((const double *)p->w, n, (double *)p->cdf, (double *)p->ws,
+                               p->stream));
     PHIP(p, hipEventRecord(p->ev[0], p->stream));
+    PHIP(p, ile_launch_mdn_draw_idx(d.seed, (int64_t)batch * steps, (const double *)p->cdf, n,
+                                    (int32_t *)p->idx, p->stream));
     for (int t = 0; t < steps; t++) {
-        PHIP(p, ile_launch_mdn_draw_idx(d.seed, t, batch, (const double *)p->cdf, n,
-                                        (int32_t *)p->idx, p->stream));
-        PHIP(p, ile_launch_mdn_grad(p->M, (const float *)p->z, n, (const int32_t *)p->idx,
-                                    nullptr, batch, (float *)p->part, p->stream));
+        PHIP(p, ile_launch_mdn_grad(p->M, (const float *)p->z, n,
+                                    (const int32_t *)p->idx + (size_t)t * batch, nullptr, batch,
+                                    (float *)p->part, p->stream));
         PHIP(p, ile_launch_mdn_update(p->M, (const float *)p->part, nblk, nullptr,
                                       t == steps - 1 ? (double *)p->loss : nullptr, true, t + 1,
                                       lr, p->stream));

@@ -64,20 +64,23 @@ class RunOpts(C.Structure):
                 ("prop", C.c_void_p), ("eps", C.c_double), ("fallback_neff", C.c_double),
                 ("train_steps", C.c_int32), ("train_batch", C.c_int32), ("lr", C.c_double),
                 ("refine_rounds", C.c_int32), ("refine_steps", C.c_int32),
-                ("refine_eff", C.c_double), ("train_ess", C.c_double)]
+                ("refine_eff", C.c_double), ("train_ess", C.c_double),
+                ("refine_kish", C.c_double), ("sigma_scale", C.c_double)]
 
 
 class LearnedInfo(C.Structure):
     _fields_ = [("n_train_samples", C.c_int64), ("n_refine_samples", C.c_int64),
                 ("n_learned_samples", C.c_int64), ("fell_back", C.c_int32),
                 ("train_ms", C.c_double), ("final_loss", C.c_double),
-                ("last_refine_eff", C.c_double), ("refine_eff", C.c_double * 32)]
+                ("last_refine_eff", C.c_double), ("refine_eff", C.c_double * 32),
+                ("refine_kish", C.c_double * 32)]
 
 
 class PropConfig(C.Structure):
     _fields_ = [("d_min_mpc", C.c_double), ("d_max_mpc", C.c_double),
                 ("t_ref_max_s", C.c_double), ("sigma_floor", C.c_double),
-                ("seed", C.c_uint64), ("device", C.c_int32), ("stream", C.c_void_p)]
+                ("seed", C.c_uint64), ("device", C.c_int32), ("stream", C.c_void_p),
+                ("sigma_scale", C.c_double)]
 
 
 class PropTrainOpts(C.Structure):
@@ -174,6 +177,7 @@ def lib():
         L.ile_prop_get_params.argtypes = [_vp, _fp]
         L.ile_prop_set_transform.argtypes = [_vp, _dp, _dp, _dp]
         L.ile_prop_get_transform.argtypes = [_vp, _dp, _dp, _dp]
+        L.ile_prop_set_sigma_scale.argtypes = [_vp, C.c_double]
         L.ile_prop_fit_transform_dev.argtypes = [_vp, _vp, C.c_int64, _vp, C.c_int64,
                                                  C.c_double]
         L.ile_prop_grad_dev.argtypes = [_vp, _vp, C.c_int64, _vp, C.c_int64, _vp, _dp]
@@ -300,13 +304,13 @@ def ile_run(h, sampler="adaptive", seed=1, chunk=100_000, max_samples=1_000_000,
             n_eff_target=0.0, d_min=10.0, d_max=1000.0, n_bins=50, floor=0.1,
             temper=10.0, adapt_chunks=-1, reset=True, prop=None, eps=-1.0,
             fallback_neff=-1.0, train_steps=0, train_batch=0, lr=0.0, refine_rounds=-1,
-            refine_steps=0, refine_eff=0.0, train_ess=0.0):
+            refine_steps=0, refine_eff=0.0, train_ess=0.0, refine_kish=0.0, sigma_scale=0.0):
     o = RunOpts(SAMPLER[sampler], int(seed), int(chunk), int(max_samples),
                 float(n_eff_target), float(d_min), float(d_max), int(n_bins),
                 float(floor), float(temper), int(adapt_chunks), 1 if reset else 0,
                 prop, float(eps), float(fallback_neff), int(train_steps),
                 int(train_batch), float(lr), int(refine_rounds), int(refine_steps),
-                float(refine_eff), float(train_ess))
+                float(refine_eff), float(train_ess), float(refine_kish), float(sigma_scale))
     r = Result()
     nc = C.c_int64()
     _check(lib().ile_run(h, C.byref(o), C.byref(r), C.byref(nc)), h)
@@ -315,8 +319,11 @@ def ile_run(h, sampler="adaptive", seed=1, chunk=100_000, max_samples=1_000_000,
     if sampler == "learned":
         li = LearnedInfo()
         _check(lib().ile_last_learned_info(h, C.byref(li)), h)
-        d.update({f: getattr(li, f) for f, _ in li._fields_ if f != "refine_eff"})
-        d["refine_eff"] = [li.refine_eff[i] for i in range(32) if li.refine_eff[i] > 0]
+        d.update({f: getattr(li, f) for f, _ in li._fields_
+                  if f not in ("refine_eff", "refine_kish")})
+        nr = d["n_refine_samples"] // max(int(chunk), 1)
+        d["refine_eff"] = [li.refine_eff[i] for i in range(min(nr, 32))]
+        d["refine_kish"] = [li.refine_kish[i] for i in range(min(nr, 32))]
     return d
 
 
@@ -572,12 +579,12 @@ class Proposal:
     its histograms (for the defensive mixture)."""
 
     def __init__(self, ctx=None, *, d_min=10.0, d_max=1000.0, t_ref_max=0.01,
-                 sigma_floor=1e-3, seed=1, device=0, stream=None):
+                 sigma_floor=1e-3, seed=1, device=0, stream=None, sigma_scale=1.0):
         if ctx is not None and stream is None:
             stream = ctx.stream()
         self.ctx = ctx
         cfg = PropConfig(float(d_min), float(d_max), float(t_ref_max), float(sigma_floor),
-                         int(seed), int(device), stream)
+                         int(seed), int(device), stream, float(sigma_scale))
         h = _vp()
         st = lib().ile_prop_create(C.byref(cfg), C.byref(h))
         if st != ILE_OK:
@@ -601,6 +608,9 @@ class Proposal:
         m, mp = _f64(mean)
         s, sp = _f64(scale)
         _pcheck(lib().ile_prop_set_transform(self.h, op, mp, sp), self.h)
+
+    def set_sigma_scale(self, kappa):
+        _pcheck(lib().ile_prop_set_sigma_scale(self.h, float(kappa)), self.h)
 
     def get_transform(self):
         o, m, s = np.zeros(3), np.zeros(7), np.zeros(7)

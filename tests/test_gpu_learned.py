@@ -96,9 +96,9 @@ def test_learned_beats_plain_to_neff_1e4(torch):
         t_plain = time.perf_counter() - t0
         with ile.Proposal(ctx, seed=3) as p:
             t0 = time.perf_counter()
+            # the run's defaults: 300 + 150-step refits of 16384, lr 2e-3, kappa 1.25
             lrn = ctx.run(sampler="learned", seed=42, chunk=100_000, max_samples=20_000_000,
-                          n_eff_target=target, adapt_chunks=3, prop=p, eps=0.1,
-                          train_steps=1000, train_batch=4096, lr=1e-3)
+                          n_eff_target=target, adapt_chunks=3, prop=p, eps=0.1)
             t_lrn = time.perf_counter() - t0
             # one more chunk of the trained mixture: same-sample parity
             n = 20_000

@@ -63,7 +63,7 @@ def _emulated_lnq(O, P, tr, x):
         tot = 0.0
         for d in range(7):
             al, mu, rho = o[48 * d:48 * d + 16], o[48 * d + 16:48 * d + 32], o[48 * d + 32:48 * d + 48]
-            sig = tr.sigma_floor + np.logaddexp(0.0, rho)
+            sig = tr.sigma_scale * (tr.sigma_floor + np.logaddexp(0.0, rho))
             tot += logsumexp(al - logsumexp(al) + stats.norm.logpdf(zf[d], mu, sig))
         out[i] = tot + lj
     return out
@@ -74,20 +74,20 @@ def _transform():
                 scale=[1.5, 0.7, 1.0, 2.0, 0.9, 1.1, 0.8])
 
 
-def _prop(inst=None, seed=3):
-    return ile.Proposal(seed=seed)
+def _prop(inst=None, seed=3, kappa=1.0):
+    return ile.Proposal(seed=seed, sigma_scale=kappa)
 
 
-@pytest.mark.parametrize("n", [1, 64, 1000, 4099])
-def test_logpdf_matches_oracle(torch, n):
+@pytest.mark.parametrize("n,kappa", [(1, 1.0), (64, 1.0), (1000, 1.0), (4099, 1.0), (1000, 1.25)])
+def test_logpdf_matches_oracle(torch, n, kappa):
     from oracle import oracle as O
     P = synth.mdn_params(21, gain=1.0)
     T = _transform()
-    tr = O.mdn_transform(**T)
+    tr = O.mdn_transform(**T, sigma_scale=kappa)
     x, _ = synth.prior_samples(n, 500 + n)
     want = O.mdn_logpdf(P.astype(np.float64), tr, x)
     emu = _emulated_lnq(O, P.astype(np.float64), tr, x[:, :min(n, 400)])
-    with _prop() as p:
+    with _prop(kappa=kappa) as p:
         p.set_params(P)
         p.set_transform(**T)
         xd = torch.from_numpy(x).cuda()
@@ -114,7 +114,8 @@ def test_gradient_matches_oracle(torch):
     x, _ = synth.prior_samples(n, 601)
     w = np.random.default_rng(5).uniform(0.05, 2.0, n)
     loss_o, g_o = O.mdn_loss_grad(P, tr, x, w)
-    with _prop() as p:
+    # the proposal's sigma scale does not enter training
+    with _prop(kappa=1.3) as p:
         p.set_params(P.astype(np.float32))
         p.set_transform(**T)
         xd = torch.from_numpy(x).cuda()
@@ -159,8 +160,8 @@ def _sample(torch, p, seed, first, n, eps=0.0):
     return xd, lp, lq
 
 
-@pytest.mark.parametrize("eps", [0.0, 0.1])
-def test_sample_lnq_is_logpdf_bitwise(torch, eps):
+@pytest.mark.parametrize("eps,kappa", [(0.0, 1.0), (0.1, 1.0), (0.1, 1.25)])
+def test_sample_lnq_is_logpdf_bitwise(torch, eps, kappa):
     """P12 (device): ln q of each draw equals logpdf of the drawn sample."""
     inst = synth.config1()
     n = 20_011
@@ -169,7 +170,7 @@ def test_sample_lnq_is_logpdf_bitwise(torch, eps):
         P_ra = rng.gamma(1.5, size=50)
         P_sd = rng.gamma(1.5, size=50)
         ile.ile_hist_set(ctx.h, P_ra / P_ra.sum(), P_sd / P_sd.sum())
-        with ile.Proposal(ctx, seed=4) as p:
+        with ile.Proposal(ctx, seed=4, sigma_scale=kappa) as p:
             p.set_params(synth.mdn_params(23, gain=0.8))
             p.set_transform(**_transform())
             xd, lp, lq = _sample(torch, p, 99, 1000, n, eps)
@@ -191,16 +192,18 @@ def test_sample_lnq_is_logpdf_bitwise(torch, eps):
     assert np.all(np.abs(x[6]) <= 0.01)
 
 
-def test_draws_follow_the_conditionals(torch):
+@pytest.mark.parametrize("kappa", [1.0, 1.25])
+def test_draws_follow_the_conditionals(torch, kappa):
     """Probability integral transform: for draws of the network alone, each
     dimension's conditional CDF (mixture from the oracle's outputs at the
-    draw's earlier dimensions) evaluated at the draw is uniform (KS)."""
+    draw's earlier dimensions, sigmas widened by kappa) evaluated at the
+    draw is uniform (KS)."""
     from oracle import oracle as O
     P = synth.mdn_params(26, gain=0.9)
     T = _transform()
     tr = O.mdn_transform(**T)
     n = 20_000
-    with _prop() as p:
+    with _prop(kappa=kappa) as p:
         p.set_params(P)
         p.set_transform(**T)
         xd, _, _ = _sample(torch, p, 17, 5, n)
@@ -209,7 +212,7 @@ def test_draws_follow_the_conditionals(torch):
     z, o = O.mdn_outputs(P.astype(np.float64), tr, x)
     for d in range(7):
         al, mu, rho = o[:, 48 * d:48 * d + 16], o[:, 48 * d + 16:48 * d + 32], o[:, 48 * d + 32:48 * d + 48]
-        sig = 1e-3 + np.logaddexp(0.0, rho)
+        sig = kappa * (1e-3 + np.logaddexp(0.0, rho))
         w = np.exp(al - logsumexp(al, axis=1, keepdims=True))
         u = np.sum(w * stats.norm.cdf((z[:, d:d + 1] - mu) / sig), axis=1)
         ks = stats.kstest(u, "uniform")
@@ -217,8 +220,8 @@ def test_draws_follow_the_conditionals(torch):
         assert ks.pvalue > 1e-4, d
 
 
-@pytest.mark.parametrize("eps", [0.25])
-def test_draws_integrate_prior(torch, eps):
+@pytest.mark.parametrize("eps,kappa", [(0.25, 1.0), (0.25, 1.25)])
+def test_draws_integrate_prior(torch, eps, kappa):
     """E_q[p/q] = 1 for the defensive mixture (p/q is bounded there): the
     draws follow the density their ln q describes."""
     inst = synth.config1()
@@ -228,7 +231,7 @@ def test_draws_integrate_prior(torch, eps):
         P_ra = rng.gamma(2.0, size=40)
         P_sd = rng.gamma(2.0, size=40)
         ile.ile_hist_set(ctx.h, P_ra / P_ra.sum(), P_sd / P_sd.sum())
-        with ile.Proposal(ctx, seed=5) as p:
+        with ile.Proposal(ctx, seed=5, sigma_scale=kappa) as p:
             p.set_params(synth.mdn_params(24, gain=0.6))
             p.set_transform(origin=[2.0, 1.0, 3.0], mean=[0.0] * 7, scale=[1.0] * 7)
             xd, lp, lq = _sample(torch, p, 123, 0, n, eps)
@@ -237,6 +240,23 @@ def test_draws_integrate_prior(torch, eps):
     m, se = r.mean(), r.std() / math.sqrt(n)
     print(f"eps={eps}: E[p/q]={m:.5f} +- {se:.5f}")
     assert abs(m - 1.0) < 4 * se and se < 0.05
+
+
+def test_sigma_scale_keeps_fitted_transform(torch):
+    """Setting kappa after a device fit keeps the fitted transform; kappa
+    must be positive."""
+    n = 5000
+    x, _ = synth.prior_samples(n, 604)
+    lnw = np.random.default_rng(9).normal(0, 1.0, n)
+    with _prop() as p:
+        p.fit_transform_dev(torch.from_numpy(x).cuda(), n, torch.from_numpy(lnw).cuda(), n)
+        before = p.get_transform()
+        p.set_sigma_scale(1.3)
+        after = p.get_transform()
+        for a, b in zip(before, after):
+            assert np.array_equal(a, b)
+        with pytest.raises(ile.IleError):
+            p.set_sigma_scale(0.0)
 
 
 def test_first_dimension_marginal(torch):

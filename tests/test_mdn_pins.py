@@ -7,7 +7,9 @@ so what pins it is mathematics, not printed values:
   * P12: the density is normalized: E_prior[q/p] = 1 within 4 sigma, and
     each conditional integrates to 1 by quadrature;
   * the masks make the model autoregressive (ln q_d ignores z~_j, j >= d);
-  * with W3 = 0 every conditional is the fixed mixture b3 (scipy's normal);
+  * with W3 = 0 every conditional is the fixed mixture b3 (scipy's normal),
+    with every sigma multiplied by the sigma scale kappa;
+  * the training loss and gradient are those of the kappa = 1 model;
   * the transform fit gives circular means and weighted moments.
 """
 import math
@@ -58,27 +60,29 @@ def test_autoregressive():
             assert np.any(d2[j + 1:] != base[j + 1:])
 
 
-def test_constant_outputs_reduce_to_scipy_mixture():
+@pytest.mark.parametrize("kappa", [1.0, 1.25])
+def test_constant_outputs_reduce_to_scipy_mixture(kappa):
     P = params(4)
     P[OFF_W3:OFF_B3] = 0.0
     b3 = P[OFF_B3:]
-    tr = O.mdn_transform(sigma_floor=1e-3)
+    tr = O.mdn_transform(sigma_floor=1e-3, sigma_scale=kappa)
     z = np.array([0.3, -1.2, 0.0, 2.1, -0.4, 0.9, -2.5])
     _, dims = O.mdn_lnq_z(P, tr, z)
     for d in range(7):
         o = b3[48 * d:48 * d + 48]
         logits, mu, rho = o[:16], o[16:32], o[32:]
-        sig = 1e-3 + np.logaddexp(0.0, rho)
+        sig = kappa * (1e-3 + np.logaddexp(0.0, rho))
         lw = logits - logsumexp(logits)
         ref = logsumexp(lw + stats.norm.logpdf(z[d], mu, sig))
         assert abs(dims[d] - ref) <= 1e-13 * max(1.0, abs(ref)), d
 
 
-def test_conditionals_integrate_to_one():
+@pytest.mark.parametrize("kappa", [1.0, 1.3])
+def test_conditionals_integrate_to_one(kappa):
     """For fixed earlier dimensions, each conditional density integrates to
-    1 over z~_d (trapezoid on a fine grid)."""
+    1 over z~_d (trapezoid on a fine grid), widened or not."""
     P = params(5, gain=1.5)
-    tr = O.mdn_transform()
+    tr = O.mdn_transform(sigma_scale=kappa)
     rng = np.random.default_rng(1)
     z = rng.standard_normal(7)
     grid = np.linspace(-30, 30, 24001)
@@ -92,10 +96,11 @@ def test_conditionals_integrate_to_one():
         assert abs(integral - 1.0) < 1e-6, (d, integral)
 
 
-def test_normalization_under_prior():
+@pytest.mark.parametrize("kappa", [1.0, 1.25])
+def test_normalization_under_prior(kappa):
     """P12 (oracle side): E_prior[q/p] = 1 within 4 standard errors."""
     P = params(6, gain=0.5)
-    tr = O.mdn_transform(origin=(1.0, 0.5, 4.0))
+    tr = O.mdn_transform(origin=(1.0, 0.5, 4.0), sigma_scale=kappa)
     x, lp = synth.prior_samples(60_000, 77)
     lq = O.mdn_logpdf(P, tr, x)
     r = np.exp(lq - lp)
@@ -151,6 +156,21 @@ def test_gradient_matches_finite_differences(weighted):
         Pm[j] -= h
         fd = (O.mdn_loss_grad(Pp, tr, x, w)[0] - O.mdn_loss_grad(Pm, tr, x, w)[0]) / (2 * h)
         assert abs(fd - g[j]) <= 1e-6 * max(abs(g[j]), 1e-3), (j, fd, g[j])
+
+
+def test_loss_ignores_sigma_scale():
+    """Training fits the kappa = 1 model: the loss and gradient do not
+    depend on the sigma scale, and the loss is the kappa = 1 density's."""
+    P = params(10, gain=1.1)
+    x, _ = synth.prior_samples(7, 15)
+    w = np.random.default_rng(6).uniform(0.2, 1.5, 7)
+    l1, g1 = O.mdn_loss_grad(P, O.mdn_transform(), x, w)
+    l2, g2 = O.mdn_loss_grad(P, O.mdn_transform(sigma_scale=1.4), x, w)
+    assert l1 == l2 and np.array_equal(g1, g2)
+    # and the widened density differs from it
+    tr = O.mdn_transform(sigma_scale=1.4)
+    z, _ = O.mdn_to_z(tr, x[:, 0])
+    assert O.mdn_lnq_z(P, tr, z)[0] != O.mdn_lnq_z(P, O.mdn_transform(), z)[0]
 
 
 def test_loss_is_weighted_mean_nll():
