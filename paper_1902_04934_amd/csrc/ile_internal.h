@@ -47,10 +47,10 @@ struct ile_point_dev {
     double *out;              // lnLmargT [N]
 };
 
-// K steps of the matrix-core contraction (4 real rows = 2 modes each),
-// rounded up to a multiple of 3; the device Q holds 4 * ksp_of(n_lm) rows
-// per detector (rows 2a and 2a+1 = Re, Im of mode a, the rest zero).
-__host__ __device__ inline int ksp_of(int n_lm) { return 3 * (((2 * n_lm + 3) / 4 + 2) / 3); }
+// K steps of the matrix-core contraction (4 real rows = 2 modes each); the
+// device Q holds 4 * ksp_of(n_lm) rows per detector (rows 2a and 2a+1 = Re,
+// Im of mode a, the rest zero).
+__host__ __device__ inline int ksp_of(int n_lm) { return (2 * n_lm + 3) / 4; }
 
 // K steps (32 rows each) of the BF16 hi/lo contraction: the rows are
 // [Q_hi (2 n_lm); Q_lo (2 n_lm); Q_hi (2 n_lm)], zero-padded; the device Q

@@ -397,9 +397,8 @@ template <> struct mfma_acc<float> {
 // with a lane-layout probe): lane l supplies A[l%16][l/16] and B[l/16][l%16]
 // and receives D[l/16 + 4v][l%16], v = 0..3.  Wave wv computes the N-tiles
 // wv, wv+NW, ... (NU of them, wave-uniform) of 16 positions.  Q rows are
-// padded with zeros to 4 KSP in memory (KSP = k-steps rounded up to a
-// multiple of 3), so every lane loads a valid row; columns past the end of
-// Q are clamped (their results are never read).
+// padded with zeros to 4 KSP in memory, so every lane loads a valid row;
+// columns past the end of Q are clamped (their results are never read).
 template <typename TQ, int NT, int NU>
 __device__ inline void mfma_tiles(TQ *Gs, const TQ *coefA, const TQ *Qk, int nq,
                                   int KSP, int P0, int lane, int wv)
@@ -415,23 +414,24 @@ __device__ inline void mfma_tiles(TQ *Gs, const TQ *coefA, const TQ *Qk, int nq,
         qb[u] = Qk + (int64_t)row * nq + min(P0 + 16 * (wv + NW * u) + col, nq - 1);
     }
     const int64_t step = 4 * (int64_t)nq;
-    // KSP is a multiple of 3 (zero-padded coefficients and Q rows): three
-    // operand buffers, each reloaded right after its MFMAs consumed it, so
-    // every load is in flight for two k-steps and the loop body has no
-    // branches (prefetch indices past the end are clamped and unused)
-    TQ a0 = coefA[lane], a1 = coefA[64 + lane], a2, b0[NU], b1[NU], b2[NU];
+    // three operand buffers, each reloaded right after its MFMAs consumed
+    // it, so every load is in flight for two k-steps; the k-steps past KSP
+    // of the last round are skipped by wave-uniform tests (prefetch indices
+    // past the end are clamped and unused)
+    const int kl = KSP - 1;
+    TQ a0 = coefA[lane], a1 = coefA[min(1, kl) * 64 + lane], a2, b0[NU], b1[NU], b2[NU];
 #pragma unroll
     for (int u = 0; u < NU; u++) {
         b0[u] = qb[u][0];
-        b1[u] = qb[u][step];
+        b1[u] = qb[u][min(1, kl) * step];
     }
     // sched_barrier(0) keeps the compiler from folding the prefetch back
     // next to its use
     for (int ks = 0; ks < KSP; ks += 3) {
-        const int k3 = min(ks + 3, KSP - 1), k4 = min(ks + 4, KSP - 1);
-        a2 = coefA[(ks + 2) * 64 + lane];
+        const int k2 = min(ks + 2, kl), k3 = min(ks + 3, kl), k4 = min(ks + 4, kl);
+        a2 = coefA[k2 * 64 + lane];
 #pragma unroll
-        for (int u = 0; u < NU; u++) b2[u] = qb[u][(ks + 2) * step];
+        for (int u = 0; u < NU; u++) b2[u] = qb[u][k2 * step];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < NU; u++)
@@ -441,17 +441,21 @@ __device__ inline void mfma_tiles(TQ *Gs, const TQ *coefA, const TQ *Qk, int nq,
 #pragma unroll
         for (int u = 0; u < NU; u++) b0[u] = qb[u][k3 * step];
         __builtin_amdgcn_sched_barrier(0);
+        if (ks + 1 < KSP) {
 #pragma unroll
-        for (int u = 0; u < NU; u++)
-            acc[u] = M::step(a1, b1[u], acc[u]);
+            for (int u = 0; u < NU; u++)
+                acc[u] = M::step(a1, b1[u], acc[u]);
+        }
         __builtin_amdgcn_sched_barrier(0);
         a1 = coefA[k4 * 64 + lane];
 #pragma unroll
         for (int u = 0; u < NU; u++) b1[u] = qb[u][k4 * step];
         __builtin_amdgcn_sched_barrier(0);
+        if (ks + 2 < KSP) {
 #pragma unroll
-        for (int u = 0; u < NU; u++)
-            acc[u] = M::step(a2, b2[u], acc[u]);
+            for (int u = 0; u < NU; u++)
+                acc[u] = M::step(a2, b2[u], acc[u]);
+        }
         __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
@@ -625,6 +629,50 @@ __device__ inline void lse_wave_sum(const double *m, const double *sacc, const d
     }
 }
 
+// 16-lane reductions of doubles by DPP row rotations (8, 4, 2, 1 lanes) of
+// both 32-bit halves: lane i meets the partner value of an xor butterfly
+// (after the rotation by n the partials repeat with period n), so every lane
+// of the row ends with the same bits.
+template <int N>
+__device__ inline double row_ror64(double x)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, 0x120 + N, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), 0x120 + N, 0xF, 0xF,
+                                               false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ inline double row_max64(double x)
+{
+    x = fmax(x, row_ror64<8>(x));
+    x = fmax(x, row_ror64<4>(x));
+    x = fmax(x, row_ror64<2>(x));
+    return fmax(x, row_ror64<1>(x));
+}
+__device__ inline double row_sum64(double x)
+{
+    x += row_ror64<8>(x);
+    x += row_ror64<4>(x);
+    x += row_ror64<2>(x);
+    return x + row_ror64<1>(x);
+}
+
+// Matrix-core epilogue: the consumers' per-sample states go through LDS R
+// (the free G buffers, [TS][NP] doubles); 16 lanes per sample (threads
+// tid < 16 TS) combine the NP entries of their sample in a fixed order, then
+// across the 16 lanes.  Pass 1 gives M = max m, pass 2 S = sum s e^{m - M}.
+template <int TS, int NP>
+__device__ inline double epi_reduce(const double *R, int tid, bool is_max)
+{
+    const int al = tid >> 4, l16 = tid & 15;
+    double v = is_max ? -INFINITY : 0.0;
+    for (int c = l16; c < NP; c += 16) {
+        const double x = R[al * NP + c];
+        v = is_max ? fmax(v, x) : v + x;
+    }
+    return is_max ? row_max64(v) : row_sum64(v);
+}
+
 // One tile: samples perm[base .. base + TS) of a point (those below N).
 template <typename TQ, int TS, int NT, int ENG, bool DUMP>
 __device__ __forceinline__ void contract_tile(
@@ -716,10 +764,25 @@ __device__ __forceinline__ void contract_tile(
         for (int t = tid; t < nd * KSB * 64 * 8; t += NT) cz[t] = 0;
         __syncthreads();
     }
+    //    per detector; U_k and V_k are first copied to LDS after the
+    //    scratch when the G buffers have room for them (one round trip
+    //    instead of a dependent global load per term)
     const int nlp = ENG == ENG_MFMA ? 2 * KSP : nl;
-    for (int t = tid; t < TS * nd * nlp; t += NT) {
-        const int al = t % TS, r = t / TS;
-        const int k = r / nlp, a = r - k * nlp;
+    const size_t uv_off = (scr_bytes + 15) & ~(size_t)15;
+    const bool stage_uv = scr == reinterpret_cast<double *>(Gs) &&
+                          uv_off + 2 * (size_t)nl * nl * sizeof(double2) <= sizeof(Gs);
+    double2 *s_U = reinterpret_cast<double2 *>(reinterpret_cast<unsigned char *>(Gs) + uv_off);
+    double2 *s_V = s_U + nl * nl;
+    for (int k = 0; k < nd; k++) {
+      if (stage_uv) {
+        for (int e = tid; e < nl * nl; e += NT) {
+            s_U[e] = U[(int64_t)k * nl * nl + e];
+            s_V[e] = V[(int64_t)k * nl * nl + e];
+        }
+        __syncthreads();
+      }
+      for (int t = tid; t < TS * nlp; t += NT) {
+        const int al = t % TS, a = t / TS;
         double cx = 0.0, cy = 0.0, row = 0.0;
         if (a < nl) {
             double kap = s_ok[al] ? g.d_ref / s_th[5 * TS + al] : 0.0;
@@ -730,8 +793,8 @@ __device__ __forceinline__ void contract_tile(
             cy = kap * fyi;
             // |F|^2 Re(conj(Y_a) (U Y)_a) + Re(F^2 Y_a (V Y)_a)
             double uyr = 0, uyi = 0, vyr = 0, vyi = 0;
-            const double2 *Ur = U + ((int64_t)k * nl + a) * nl;
-            const double2 *Vr = V + ((int64_t)k * nl + a) * nl;
+            const double2 *Ur = stage_uv ? s_U + a * nl : U + ((int64_t)k * nl + a) * nl;
+            const double2 *Vr = stage_uv ? s_V + a * nl : V + ((int64_t)k * nl + a) * nl;
             for (int b = 0; b < nl; b++) {
                 double2 Yb = s_Y[al * nl + b], u = Ur[b], v = Vr[b];
                 uyr += u.x * Yb.x - u.y * Yb.y;
@@ -773,6 +836,8 @@ __device__ __forceinline__ void contract_tile(
             coef[(k * KSP + (r0 >> 2)) * 64 + (r0 & 3) * 16 + al] = (TQ)cx;
             coef[(k * KSP + (r0 >> 2)) * 64 + ((r0 & 3) + 1) * 16 + al] = (TQ)cy;
         }
+      }
+      if (stage_uv) __syncthreads();   // before the next detector's copy
     }
     __syncthreads();
 
@@ -910,6 +975,7 @@ __device__ __forceinline__ void contract_tile(
         // one barrier per step.  Both iterators are advanced identically by
         // every thread, so the loop bounds are uniform.
         const bool producer = __builtin_amdgcn_readfirstlane(tid) < NP;
+        static_assert(TS * NP * sizeof(double) <= sizeof(Gs), "epilogue states fit the G buffers");
         // Separate loops per role (wave-uniform branch) so that the consumer
         // state and the producer's operand buffers are never live together;
         // both loops take the same steps and meet at one barrier per step.
@@ -935,22 +1001,19 @@ __device__ __forceinline__ void contract_tile(
                 if (step > 0 && ci.valid) pipe_next(ci, J, g.n_t, nd, s_spread, NP);
                 __syncthreads();
             }
-            // epilogue: producers hold no log-sum-exp state; threads tid < TS
-            // (all producers) form M and the results
-            lse_wave_max<TS>(nullptr, s_red, lane, wv);
+            // epilogue (the consumers write R between the barriers); threads
+            // tid < 16 TS reduce
+            const double *R = reinterpret_cast<const double *>(Gs);
             __syncthreads();
-            if (tid < TS) {
-                double M = s_red[0][tid];
-                for (int w = 1; w < NW; w++) M = fmax(M, s_red[w][tid]);
-                s_M[tid] = M;
+            if (tid < 16 * TS) {
+                const double M = epi_reduce<TS, NP>(R, tid, true);
+                if ((tid & 15) == 0) s_M[tid >> 4] = M;
             }
             __syncthreads();
-            lse_wave_sum<TS>(nullptr, nullptr, s_M, s_red, lane, wv);
             __syncthreads();
-            if (tid < TS) {
-                double S = s_red[0][tid];
-                for (int w = 1; w < NW; w++) S += s_red[w][tid];
-                finish_sample(tid, S);
+            if (tid < 16 * TS) {
+                const double S = epi_reduce<TS, NP>(R, tid, false);
+                if ((tid & 15) == 0) finish_sample(tid >> 4, S);
             }
         } else {
             const int tc = tid - NP;   // consumer index
@@ -997,11 +1060,23 @@ __device__ __forceinline__ void contract_tile(
                 __syncthreads();
             }
             // epilogue: the same three barriers as the producers
-            lse_wave_max<TS>(m, s_red, lane, wv);
+            double *R = reinterpret_cast<double *>(Gs);
+#pragma unroll
+            for (int al = 0; al < TS; al++) R[al * NP + tc] = m[al];
             __syncthreads();
+            if (tid < 16 * TS) {
+                const double M = epi_reduce<TS, NP>(R, tid, true);
+                if ((tid & 15) == 0) s_M[tid >> 4] = M;
+            }
             __syncthreads();
-            lse_wave_sum<TS>(m, sacc, s_M, s_red, lane, wv);
+#pragma unroll
+            for (int al = 0; al < TS; al++)
+                R[al * NP + tc] = m[al] == -INFINITY ? 0.0 : sacc[al] * exp(m[al] - s_M[al]);
             __syncthreads();
+            if (tid < 16 * TS) {
+                const double S = epi_reduce<TS, NP>(R, tid, false);
+                if ((tid & 15) == 0) finish_sample(tid >> 4, S);
+            }
         }
     }
 }
