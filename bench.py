@@ -196,8 +196,8 @@ def main():
     dt = time.perf_counter() - t0
     ms_step = 1e3 * dt / args.steps
     kernel_ms = sum(kms) / len(kms)
-    threads = args.threads or (256 if args.engine == "valu" else
-                               192 if args.precision == "fp64" else 128)
+    threads = args.threads or (256 if args.engine == "valu" or args.precision == "fp32"
+                               else 128)
     fl = flops_per_sample(inst.n_det, inst.n_lm, inst.n_t) * n
     achieved = fl / (kernel_ms * 1e-3) / 1e12
     peak = {"fp64": FP64_PEAK_TFLOPS, "fp32": FP32_PEAK_TFLOPS,

@@ -481,7 +481,7 @@ typedef enum {
     ILE_OPT_THREADS = 2  /* positions per block: 256 or 512, or 128 or 192
                             with the matrix cores (workgroups of twice as
                             many threads: producers + consumers); default
-                            192 for FP64, 128 for FP32 and BF16 */
+                            128 for FP64 and BF16, 256 for FP32 */
 } ile_option;
 ile_status ile_set_option(ile_ctx *ctx, ile_option opt, int64_t value);
 

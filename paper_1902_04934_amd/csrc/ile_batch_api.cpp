@@ -453,7 +453,7 @@ ile_status ile_batch_autotune(ile_batch *b, int64_t n, const char *cache_path)
     }
     std::vector<ile_batch_tuning> cand;
     const int engines = b->cfg.precision == ILE_BF16 ? 1 : 2;
-    for (int th : {192, 256, 512})
+    for (int th : {128, 192, 256, 512})
         for (int w : {1, 2, 3})
             for (int o : {0, 1})
                 for (int en = 0; en < engines; en++) cand.push_back({th, w, o, 1 - en});
