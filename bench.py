@@ -149,6 +149,54 @@ def learned_leg(target=1e4):
     return out
 
 
+def combined_leg(n_points=32, n=1_000_000, m_oracle=2000):
+    """The combined form at the combined workload's per-point shape (3
+    detectors, 5-21 modes, 201-1601 bins, 16384-point Q in FP32, 1e6 draws
+    per point) on n_points points: a learned proposal per point (plain
+    fallback), the draws of all points evaluated in one batched persistent
+    run.  Reports the batched evaluation's throughput (HIP events around its
+    graph) and ln L_marg against the FP64 oracle on the first m_oracle draws
+    of every point (the device value from a batched run of those draws)."""
+    import numpy as np
+    import torch
+    from oracle import oracle as O
+    from paper_1902_04934_amd import combined, synth
+    points = [synth.combined_point(p) for p in range(n_points)]
+    t0 = time.perf_counter()
+    res, info, X, lp, lq, batch, t = combined.run(points, n)
+    wall = time.perf_counter() - t0
+    work = sum(n * p["n_t"] for p in points)
+    # same-sample check against the oracle on the first m_oracle draws
+    Xs, lps, lqs = X[:, :, :m_oracle].contiguous(), lp[:, :m_oracle].contiguous(), \
+        lq[:, :m_oracle].contiguous()
+    sub = batch.run_dev(m_oracle, Xs, lps, lqs)
+    errs = []
+    t_orc = time.perf_counter()
+    for p, parts in enumerate(points):
+        inst = info[p]["inst"]
+        blank = synth.Instance(dets=inst.dets, modes=inst.modes, srate_hz=inst.srate_hz,
+                               n_t=inst.n_t, Q=np.zeros_like(inst.Q), U=np.zeros_like(inst.U),
+                               V=np.zeros_like(inst.V))
+        want, _, _ = O.injection_instance(blank, parts["h_lm"], parts["theta_inj"],
+                                          snr=parts["snr"])
+        lnL = O.Ctx(want).eval(Xs[p].cpu().numpy())
+        ref = O.integrate(lnL, lps[p].cpu().numpy(), lqs[p].cpu().numpy())
+        errs.append(abs(sub[p]["ln_L_marg"] - ref["ln_L_marg"]))
+    t_orc = time.perf_counter() - t_orc
+    batch.close()
+    return {"workload": f"{n_points} injected points (3 detectors, 5-21 modes, 201-1601 bins, "
+                        f"Q 16384 points FP32), {n} draws per point from per-point learned "
+                        "proposals, one batched persistent evaluation",
+            "points": n_points, "draws_per_point": n,
+            "eval_graph_ms": t["eval_graph_ms"],
+            "eval_sample_bins_per_s": work / (t["eval_graph_ms"] * 1e-3),
+            "train_and_draw_s": t["train_s"], "wall_s": wall,
+            "fell_back": sum(i["fell_back"] for i in info),
+            "n_eff": [r["n_eff"] for r in res], "ln_L_marg": [r["ln_L_marg"] for r in res],
+            "oracle_subset_draws": m_oracle,
+            "max_abs_d_ln_L_marg_vs_oracle": max(errs), "oracle_s": t_orc}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +210,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-plain sampler comparison")
+    ap.add_argument("--no-combined", action="store_true",
+                    help="skip the combined-form leg (per-point learned proposals, batched)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -228,6 +278,7 @@ def main():
     }
     ctx.close()
     out["learned"] = None if args.no_learned else learned_leg()
+    out["combined"] = None if args.no_combined else combined_leg()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, n_total, seed)
     else:

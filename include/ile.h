@@ -235,21 +235,23 @@ typedef struct {
     /* sampler LEARNED only: adapt_chunks (<= 0: 3) adaptive rounds of
      * `chunk` samples fill a training ring of as many chunks and train
      * `prop` (train_steps Adam steps of train_batch, learning rate lr;
-     * <= 0: 300, 16384, 2e-3).  Refinement: up to
-     * refine_rounds chunks are drawn from (1 - eps) q_net + eps q_hist (the
-     * histograms as left by the rounds); each replaces the oldest chunk of
-     * the ring and the network is refit (transform and refine_steps warm
-     * Adam steps), until a chunk's own n_eff reaches refine_eff times its
-     * size.  Then chunks are drawn from the mixture until n_eff_target or
-     * max_samples; if the first of them alone has n_eff below
-     * fallback_neff, the run continues with the adaptive sampler.  The
-     * estimate covers the chunks after refinement only. */
+     * <= 0: 300, 16384, 2e-3).  Refinement: chunks are drawn from
+     * (1 - eps) q_net + eps q_hist (the histograms as left by the rounds);
+     * each replaces the oldest chunk of the ring and the network is refit
+     * (transform and refine_steps warm Adam steps), until a chunk's own
+     * n_eff reaches refine_eff times its size or refine_rounds refits are
+     * spent.  Then a probe chunk of the mixture: if its n_eff is below
+     * fallback_neff, it becomes one more refinement chunk while refits
+     * remain, and refinement resumes; with none left the run continues
+     * with the adaptive sampler.  Then chunks are drawn until n_eff_target
+     * or max_samples.  The estimate covers the chunks after the last probe
+     * only (refinement chunks and probes are never part of it). */
     ile_prop *prop;
     double eps;              /* defensive weight (< 0: 0.1)                   */
     double fallback_neff;    /* (< 0: 1000; 0: never fall back)               */
     int32_t train_steps, train_batch;
     double lr;
-    int32_t refine_rounds;   /* (< 0: 8; 0: none)                             */
+    int32_t refine_rounds;   /* refits after the first training (< 0: 16)     */
     int32_t refine_steps;    /* (<= 0: 150)                                   */
     double refine_eff;       /* (<= 0: 0.05)                                  */
     double train_ess;        /* tempering target of the training weights, as
@@ -260,7 +262,7 @@ typedef struct {
                                 size can look healthy while the n_eff of the
                                 chunks after it is not)                       */
     double sigma_scale;      /* kappa set on prop for the refinement and
-                                estimation draws (<= 0: 1.25)                 */
+                                estimation draws (<= 0: 1.2)                 */
 } ile_run_opts;
 
 /* Monte Carlo estimate of ln L_marg: chunk after chunk, draw on the device,
@@ -451,6 +453,17 @@ ile_status ile_batch_add_point(ile_batch *b, const ile_config *cfg, const double
  * for every point p (host array of ile_batch_n_points entries). */
 ile_status ile_batch_run(ile_batch *b, uint64_t seed, int64_t n_per_point, double d_min,
                          double d_max, ile_result *results);
+/* The same graph over caller-supplied draws (the combined form: each point
+ * drawn from its own proposal): device samples_dev[P][7][n_per_point]
+ * (point p's SoA block at samples_dev + 7 n_per_point p), ln_p_dev and
+ * ln_q_dev [P][n_per_point] (either may be NULL = 0); the per-point
+ * reduction weighs each draw by ln L_margT + ln p - ln q.  The draws are
+ * copied first, so the caller's buffers are free when this returns.
+ * ILE_E_RANGE if a draw is outside a point's prior support or its window
+ * leaves its Q, or if a ln p / ln q is NaN, ln q = -inf or ln p = +inf. */
+ile_status ile_batch_run_dev(ile_batch *b, int64_t n_per_point, const double *samples_dev,
+                             const double *ln_p_dev, const double *ln_q_dev,
+                             ile_result *results);
 /* Per-point ln L_margT of the last run into host out[offset of p + i]
  * (points concatenated, n_per_point each). */
 ile_status ile_batch_lnL(ile_batch *b, double *out, int64_t n_total);

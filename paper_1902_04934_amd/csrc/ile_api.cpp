@@ -902,10 +902,10 @@ static ile_status run_learned(ile_ctx *c, const ile_run_opts *o, ile_result *out
     const double temper = o->temper > 0 ? o->temper : 10.0;
     const double eps = o->eps >= 0 ? o->eps : 0.1;
     const double fb = o->fallback_neff >= 0 ? o->fallback_neff : 1000.0;
-    const int refine_rounds = o->refine_rounds >= 0 ? o->refine_rounds : 8;
+    const int refine_rounds = o->refine_rounds >= 0 ? o->refine_rounds : 16;
     const int refine_steps = o->refine_steps > 0 ? o->refine_steps : 150;
     const double refine_eff = o->refine_eff > 0 ? o->refine_eff : 0.05;
-    const double kappa = o->sigma_scale > 0 ? o->sigma_scale : 1.25;
+    const double kappa = o->sigma_scale > 0 ? o->sigma_scale : 1.2;
     if (floor_w > 1 || eps >= 1) return fail(c, ILE_E_ARG, "floor > 1 or eps >= 1");
     if (!std::isfinite(kappa)) return fail(c, ILE_E_ARG, "bad sigma scale");
     if (ile_prop_set_sigma_scale(o->prop, kappa) != ILE_OK)
@@ -963,40 +963,69 @@ static ile_status run_learned(ile_ctx *c, const ile_run_opts *o, ile_result *out
     double r[6] = {0, 0, 0, 0, 0, 0};
     // 3. refinement: each chunk of the mixture replaces the oldest chunk of
     //    the training ring and the network is refit, until a chunk is
-    //    efficient enough
+    //    efficient enough or the rounds run out.  Then a probe chunk of the
+    //    current mixture, never part of the estimate: if its n_eff is below
+    //    fallback_neff it becomes one more refinement chunk while rounds
+    //    remain, else the run falls back to the adaptive sampler.
     double *rpart = (double *)c->parts.p + 5 * max_chunks;
     int64_t first0 = ntr;
     to.steps = refine_steps;
-    for (int rr = 0; rr < refine_rounds; rr++) {
+    int rr = 0, rec = 0;
+    bool learned = true;
+    // one chunk of the current mixture: draw, evaluate, its own n_eff in r
+    auto mixture_chunk = [&](double *r) -> ile_status {
+        ile_status s2;
         HIP_TRY(c, ile_launch_mdn_sample(ile_prop_dev(o->prop), mix, o->seed, first0, chunk, smp,
                                          chunk, lp, lq, ile_prop_grid(o->prop), c->stream));
         first0 += chunk;
-        if ((s = run_eval(c, smp, chunk, (double *)c->out.p, nullptr))) return s;
+        if ((s2 = run_eval(c, smp, chunk, (double *)c->out.p, nullptr))) return s2;
         HIP_TRY(c, ile_launch_reduce((const double *)c->out.p, lp, lq, chunk,
                                      (double *)c->red_tmp.p, rpart, c->stream));
         HIP_TRY(c, ile_launch_finish(rpart, 1, (double *)c->res.p, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        HIP_TRY(c, hipMemcpy(r, c->res.p, 6 * sizeof(double), hipMemcpyDeviceToHost));
+        c->learned.n_refine_samples += chunk;
+        c->learned.last_refine_eff = r[1] / (double)chunk;
+        if (rec < 32) {
+            c->learned.refine_eff[rec] = c->learned.last_refine_eff;
+            c->learned.refine_kish[rec] = r[2] / (double)chunk;
+        }
+        rec++;
+        return ILE_OK;
+    };
+    // the last chunk into the ring (slot of refinement round rr), then refit
+    auto refit_with_chunk = [&]() -> ile_status {
         const int64_t slot = (int64_t)(rr % rounds) * chunk;
+        rr++;
         HIP_TRY(c, hipMemcpy2DAsync(trx + slot, (size_t)ntr * sizeof(double), smp,
                                     (size_t)chunk * sizeof(double), (size_t)chunk * sizeof(double),
                                     7, hipMemcpyDeviceToDevice, c->stream));
         HIP_TRY(c, ile_launch_lnw((const double *)c->out.p, lp, lq, chunk, trw + slot, c->stream));
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-        HIP_TRY(c, hipMemcpy(r, c->res.p, sizeof(r), hipMemcpyDeviceToHost));
-        c->learned.n_refine_samples += chunk;
-        c->learned.last_refine_eff = r[1] / (double)chunk;
-        if (rr < 32) {
-            c->learned.refine_eff[rr] = c->learned.last_refine_eff;
-            c->learned.refine_kish[rr] = r[2] / (double)chunk;
-        }
-        if (r[1] >= refine_eff * (double)chunk) break;
-        if (o->refine_kish > 0 && r[2] >= o->refine_kish * (double)chunk) break;
         if (ile_prop_train_dev(o->prop, trx, ntr, trw, ntr, &to, &loss) != ILE_OK)
             return fail(c, ILE_E_DEVICE, "refit failed: %s", ile_prop_last_error(o->prop));
         c->learned.train_ms += ile_prop_last_ms(o->prop);
         c->learned.final_loss = loss;
+        return ILE_OK;
+    };
+    for (;;) {
+        while (rr < refine_rounds) {
+            if ((s = mixture_chunk(r))) return s;
+            if (r[1] >= refine_eff * (double)chunk) break;
+            if (o->refine_kish > 0 && r[2] >= o->refine_kish * (double)chunk) break;
+            if ((s = refit_with_chunk())) return s;
+        }
+        if (fb <= 0) break;
+        if ((s = mixture_chunk(r))) return s;   // the probe
+        if (r[1] >= fb) break;
+        if (rr >= refine_rounds) {
+            learned = false;
+            c->learned.fell_back = 1;
+            break;
+        }
+        if ((s = refit_with_chunk())) return s;
     }
-    // 4. estimation chunks from the defensive mixture
-    bool learned = true;
+    // 4. estimation chunks from the defensive mixture, or from the adaptive
+    //    sampler after a fallback
     int64_t done = 0, ci = 0;
     while (done < o->max_samples) {
         const int64_t n = std::min(chunk, o->max_samples - done);
@@ -1024,10 +1053,6 @@ static ile_status run_learned(ile_ctx *c, const ile_run_opts *o, ile_result *out
         if (learned) c->learned.n_learned_samples += n;
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         HIP_TRY(c, hipMemcpy(r, c->res.p, sizeof(r), hipMemcpyDeviceToHost));
-        if (learned && ci == 1 && fb > 0 && r[1] < fb) {
-            learned = false;
-            c->learned.fell_back = 1;
-        }
         if (o->n_eff_target > 0 && r[1] >= o->n_eff_target) break;
     }
     if ((s = finish_call(c))) return s;

@@ -141,26 +141,39 @@ __global__ __launch_bounds__(256) void k_scatter_multi(const uint32_t *keys, con
 // workgroup per point, fixed-order tree: results[p] = {ln L_marg, n_eff,
 // Kish, sigma, max lnLmargT, n}
 constexpr int kRT = 1024;
-__global__ __launch_bounds__(kRT) void k_reduce_points(const double *out, const int64_t *offs,
-                                                       double *res)
+// Per-point reduction: ln w = lnLmargT + (ln p - ln q) (lw = NULL: ln w =
+// lnLmargT, the prior draws), fixed-order block sums; res[6 p ..] =
+// (ln L_marg, n_eff, Kish, sigma, max lnLmargT, n).
+__global__ __launch_bounds__(kRT) void k_reduce_points(const double *out, const double *lw,
+                                                       const int64_t *offs, double *res)
 {
     __shared__ double a[kRT], b[kRT];
     const int p = blockIdx.x, t = threadIdx.x;
     const int64_t o = offs[p], n = offs[p + 1] - o;
-    double M = -INFINITY;
-    for (int64_t i = t; i < n; i += kRT) M = fmax(M, out[o + i]);
+    double M = -INFINITY, ML = -INFINITY;
+    for (int64_t i = t; i < n; i += kRT) {
+        const double x = lw ? out[o + i] + lw[o + i] : out[o + i];
+        M = fmax(M, x);
+        ML = fmax(ML, out[o + i]);
+    }
     a[t] = M;
+    b[t] = ML;
     __syncthreads();
     for (int s = kRT / 2; s > 0; s >>= 1) {
-        if (t < s) a[t] = fmax(a[t], a[t + s]);
+        if (t < s) {
+            a[t] = fmax(a[t], a[t + s]);
+            b[t] = fmax(b[t], b[t + s]);
+        }
         __syncthreads();
     }
     M = a[0];
+    ML = b[0];
     __syncthreads();
     double s1 = 0.0, s2 = 0.0;
     if (M != -INFINITY)
         for (int64_t i = t; i < n; i += kRT) {
-            const double e = exp(out[o + i] - M);
+            const double x = lw ? out[o + i] + lw[o + i] : out[o + i];
+            const double e = exp(x - M);
             s1 += e;
             s2 += e * e;
         }
@@ -187,9 +200,25 @@ __global__ __launch_bounds__(kRT) void k_reduce_points(const double *out, const 
             const double var = b[0] / (a[0] * a[0]) - 1.0 / (double)n;
             r[3] = var > 0.0 ? sqrt(var) : 0.0;
         }
-        r[4] = M;
+        r[4] = ML;
         r[5] = (double)n;
     }
+}
+
+// ln p - ln q of caller-supplied draws (either may be NULL = 0); an invalid
+// pair (NaN, ln q = -inf or ln p = +inf) sets bit 2 of the error flag.
+__global__ __launch_bounds__(256) void k_batch_lw(const double *lp, const double *lq,
+                                                  int64_t n_total, double *lw, int32_t *err)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_total) return;
+    const double p = lp ? lp[i] : 0.0, q = lq ? lq[i] : 0.0;
+    if (isnan(p) || isnan(q) || q == -INFINITY || p == INFINITY) {
+        atomicOr(err, 2);
+        lw[i] = NAN;
+        return;
+    }
+    lw[i] = p - q;
 }
 
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -224,9 +253,18 @@ hipError_t ile_launch_scatter_multi(const uint32_t *keys, const int64_t *offs, i
     return hipGetLastError();
 }
 
-hipError_t ile_launch_reduce_points(const double *out, const int64_t *offs, int n_points,
-                                    double *res, hipStream_t st)
+hipError_t ile_launch_reduce_points(const double *out, const double *lw, const int64_t *offs,
+                                    int n_points, double *res, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce_points, dim3(n_points), dim3(kRT), 0, st, out, offs, res);
+    hipLaunchKernelGGL(k_reduce_points, dim3(n_points), dim3(kRT), 0, st, out, lw, offs, res);
+    return hipGetLastError();
+}
+
+hipError_t ile_launch_batch_lw(const double *lp, const double *lq, int64_t n_total, double *lw,
+                               int32_t *err, hipStream_t st)
+{
+    if (n_total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_lw, dim3(nblk(n_total, 256)), dim3(256), 0, st, lp, lq, n_total,
+                       lw, err);
     return hipGetLastError();
 }

@@ -45,11 +45,12 @@ struct ile_batch {
     int cu_count = 0, lds_max = 0;
     std::string dev_name;
     Buf geoms, pdev, items, offs, seed, counter, smp, out, shifts, keys, perm, hist, scan_tmp,
-        errflag, res;
+        errflag, res, lw;
     // graph of one run and what it was built for
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int64_t g_n = -1;
+    int g_ext = -1;   // 1: the graph evaluates caller-supplied draws
     double g_dmin = 0, g_dmax = 0;
     ile_batch_tuning g_tune{0, 0, 0, 0};
     size_t g_points = 0;
@@ -128,8 +129,10 @@ ile_geom batched_geom(const ile_ctx *c)
     return g;
 }
 
-// Build buffers, queue and the graph of one run for n samples per point.
-ile_status build(ile_batch *b, int64_t n, double dmin, double dmax)
+// Build buffers, queue and the graph of one run for n samples per point:
+// prior draws (ext = false) or draws the caller copied to smp with their
+// ln p - ln q in lw (ext = true).
+ile_status build(ile_batch *b, int64_t n, double dmin, double dmax, bool ext)
 {
     drop_graph(b);
     const int P = (int)b->pts.size();
@@ -170,6 +173,7 @@ ile_status build(ile_batch *b, int64_t n, double dmin, double dmax)
     if ((s = bensure(b, b->scan_tmp, (size_t)ile_scan_tmp_words(nb) * 4 + 16))) return s;
     if ((s = bensure(b, b->errflag, 16))) return s;
     if ((s = bensure(b, b->res, (size_t)P * 6 * sizeof(double)))) return s;
+    if (ext && (s = bensure(b, b->lw, (size_t)NT * sizeof(double)))) return s;
     double *smp = (double *)b->smp.p, *out = (double *)b->out.p;
     int32_t *sh = (int32_t *)b->shifts.p, *perm = (int32_t *)b->perm.p;
     for (int p = 0; p < P; p++) {
@@ -216,8 +220,9 @@ ile_status build(ile_batch *b, int64_t n, double dmin, double dmax)
     };
     step(ile_launch_fill_u32((uint32_t *)b->counter.p, 0u, 1, st));
     step(ile_launch_fill_u32((uint32_t *)b->hist.p, 0u, nb, st));
-    step(ile_launch_prior_multi((const uint64_t *)b->seed.p, (const int64_t *)b->offs.p, P, NT,
-                                dmin, dmax, tmax, smp, st));
+    if (!ext)
+        step(ile_launch_prior_multi((const uint64_t *)b->seed.p, (const int64_t *)b->offs.p, P,
+                                    NT, dmin, dmax, tmax, smp, st));
     step(ile_launch_prep_multi((const ile_geom *)b->geoms.p, (const int64_t *)b->offs.p, P, NT,
                                smp, sh, (uint32_t *)b->keys.p, (uint32_t *)b->hist.p, B,
                                (int32_t *)b->errflag.p, st));
@@ -228,7 +233,8 @@ ile_status build(ile_batch *b, int64_t n, double dmin, double dmax)
                                      (const ile_point_dev *)b->pdev.p,
                                      (const int2 *)b->items.p, (int)items.size(),
                                      (unsigned *)b->counter.p, grid, dyn, st));
-    step(ile_launch_reduce_points(out, (const int64_t *)b->offs.p, P, (double *)b->res.p, st));
+    step(ile_launch_reduce_points(out, ext ? (const double *)b->lw.p : nullptr,
+                                  (const int64_t *)b->offs.p, P, (double *)b->res.p, st));
     hipGraph_t g = nullptr;
     hipError_t ec = hipStreamEndCapture(st, &g);
     if (e != hipSuccess || ec != hipSuccess) {
@@ -239,6 +245,7 @@ ile_status build(ile_batch *b, int64_t n, double dmin, double dmax)
     b->graph = g;
     BHIP(b, hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
     b->g_n = n;
+    b->g_ext = ext ? 1 : 0;
     b->g_dmin = dmin;
     b->g_dmax = dmax;
     b->g_tune = b->tune;
@@ -252,12 +259,20 @@ bool same_tune(const ile_batch_tuning &a, const ile_batch_tuning &c)
            a.engine == c.engine;
 }
 
-ile_status run_graph(ile_batch *b, uint64_t seed, int64_t n, double dmin, double dmax)
+// (Re)build the graph if the run's shape changed.
+ile_status ensure_graph(ile_batch *b, int64_t n, double dmin, double dmax, bool ext)
+{
+    if (b->g_n != n || b->g_ext != (ext ? 1 : 0) || b->g_dmin != dmin || b->g_dmax != dmax ||
+        !same_tune(b->g_tune, b->tune) || b->g_points != b->pts.size() || !b->exec)
+        return build(b, n, dmin, dmax, ext);
+    return ILE_OK;
+}
+
+ile_status run_graph(ile_batch *b, uint64_t seed, int64_t n, double dmin, double dmax,
+                     bool ext = false)
 {
     ile_status s;
-    if (b->g_n != n || b->g_dmin != dmin || b->g_dmax != dmax || !same_tune(b->g_tune, b->tune) ||
-        b->g_points != b->pts.size() || !b->exec)
-        if ((s = build(b, n, dmin, dmax))) return s;
+    if ((s = ensure_graph(b, n, dmin, dmax, ext))) return s;
     BHIP(b, hipMemcpyAsync(b->seed.p, &seed, sizeof(seed), hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipEventRecord(b->e0, b->stream));
     BHIP(b, hipGraphLaunch(b->exec, b->stream));
@@ -270,7 +285,25 @@ ile_status run_graph(ile_batch *b, uint64_t seed, int64_t n, double dmin, double
     BHIP(b, hipMemcpy(&flag, b->errflag.p, sizeof(flag), hipMemcpyDeviceToHost));
     if (flag) {
         BHIP(b, hipMemset(b->errflag.p, 0, 16));
-        return bfail(b, ILE_E_RANGE, "a sample's window left its Q (its output is NaN)");
+        if (flag & 2) return bfail(b, ILE_E_RANGE, "invalid ln_p/ln_q of a draw");
+        return bfail(b, ILE_E_RANGE,
+                     "a sample is outside the prior support or its window left its Q");
+    }
+    return ILE_OK;
+}
+
+ile_status copy_results(ile_batch *b, ile_result *results)
+{
+    const size_t P = b->pts.size();
+    std::vector<double> r(6 * P);
+    BHIP(b, hipMemcpy(r.data(), b->res.p, r.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (size_t p = 0; p < P; p++) {
+        results[p].ln_L_marg = r[6 * p];
+        results[p].n_eff = r[6 * p + 1];
+        results[p].n_eff_kish = r[6 * p + 2];
+        results[p].sigma_ln_L = r[6 * p + 3];
+        results[p].max_ln_L = r[6 * p + 4];
+        results[p].n_samples = (int64_t)r[6 * p + 5];
     }
     return ILE_OK;
 }
@@ -382,18 +415,28 @@ ile_status ile_batch_run(ile_batch *b, uint64_t seed, int64_t n, double dmin, do
     BHIP(b, hipSetDevice(b->cfg.device));
     ile_status s = run_graph(b, seed, n, dmin, dmax);
     if (s) return s;
-    const size_t P = b->pts.size();
-    std::vector<double> r(6 * P);
-    BHIP(b, hipMemcpy(r.data(), b->res.p, r.size() * sizeof(double), hipMemcpyDeviceToHost));
-    for (size_t p = 0; p < P; p++) {
-        results[p].ln_L_marg = r[6 * p];
-        results[p].n_eff = r[6 * p + 1];
-        results[p].n_eff_kish = r[6 * p + 2];
-        results[p].sigma_ln_L = r[6 * p + 3];
-        results[p].max_ln_L = r[6 * p + 4];
-        results[p].n_samples = (int64_t)r[6 * p + 5];
-    }
-    return ILE_OK;
+    return copy_results(b, results);
+}
+
+ile_status ile_batch_run_dev(ile_batch *b, int64_t n, const double *samples_dev,
+                             const double *ln_p_dev, const double *ln_q_dev,
+                             ile_result *results)
+{
+    if (!b) return ILE_E_ARG;
+    b->err.clear();
+    if (b->pts.empty()) return bfail(b, ILE_E_STATE, "no points");
+    if (n <= 0 || !results || !samples_dev) return bfail(b, ILE_E_ARG, "bad run arguments");
+    BHIP(b, hipSetDevice(b->cfg.device));
+    ile_status s;
+    if ((s = ensure_graph(b, n, 0.0, 0.0, true))) return s;
+    const int64_t NT = n * (int64_t)b->pts.size();
+    // the caller's [P][7][n] layout is the graph's sample buffer layout
+    BHIP(b, hipMemcpyAsync(b->smp.p, samples_dev, (size_t)NT * 7 * sizeof(double),
+                           hipMemcpyDeviceToDevice, b->stream));
+    BHIP(b, ile_launch_batch_lw(ln_p_dev, ln_q_dev, NT, (double *)b->lw.p,
+                                (int32_t *)b->errflag.p, b->stream));
+    if ((s = run_graph(b, 0, n, 0.0, 0.0, true))) return s;
+    return copy_results(b, results);
 }
 
 ile_status ile_batch_lnL(ile_batch *b, double *out, int64_t n_total)

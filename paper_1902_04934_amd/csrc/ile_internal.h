@@ -123,8 +123,10 @@ hipError_t ile_launch_prep_multi(const ile_geom *geoms, const int64_t *offs, int
 hipError_t ile_launch_scatter_multi(const uint32_t *keys, const int64_t *offs, int n_points,
                                     int64_t n_total, uint32_t *pos, int32_t *perm,
                                     hipStream_t st);
-hipError_t ile_launch_reduce_points(const double *out, const int64_t *offs, int n_points,
-                                    double *res, hipStream_t st);
+hipError_t ile_launch_reduce_points(const double *out, const double *lw, const int64_t *offs,
+                                    int n_points, double *res, hipStream_t st);
+hipError_t ile_launch_batch_lw(const double *lp, const double *lq, int64_t n_total, double *lw,
+                               int32_t *err, hipStream_t st);
 hipError_t ile_launch_to_bf16_split(const double *Q, int64_t n, void *dst,
                                     hipStream_t st);
 

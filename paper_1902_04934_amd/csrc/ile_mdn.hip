@@ -56,7 +56,6 @@ __device__ inline v4f mfma(v8bf a, v8bf b, v4f c)
 }
 
 __device__ inline float softplusf(float x) { return fmaxf(x, 0.f) + log1pf(expf(-fabsf(x))); }
-__device__ inline float sigmoidf(float x) { return 1.f / (1.f + expf(-x)); }
 
 // Branch-free functions at the hardware's transcendental rate for the
 // training gradient (a few ulp; the BF16 operands of the products dominate

@@ -156,6 +156,7 @@ def lib():
                                           _dp, _dp, C.POINTER(Detector), C.POINTER(C.c_int32)]
         L.ile_batch_run.argtypes = [_vp, C.c_uint64, C.c_int64, C.c_double, C.c_double,
                                     C.POINTER(Result)]
+        L.ile_batch_run_dev.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, C.POINTER(Result)]
         L.ile_batch_lnL.argtypes = [_vp, _dp, C.c_int64]
         L.ile_batch_n_points.argtypes = [_vp]
         L.ile_batch_set_tuning.argtypes = [_vp, C.POINTER(BatchTuning)]
@@ -525,6 +526,14 @@ class Batch:
         res = (Result * self.n_points)()
         _bcheck(lib().ile_batch_run(self.h, int(seed), int(n_per_point), float(d_min),
                                     float(d_max), res), self.h)
+        return [r.as_dict() for r in res]
+
+    def run_dev(self, n_per_point, samples_dev, ln_p_dev=None, ln_q_dev=None):
+        """Evaluate caller-supplied device draws: samples_dev [P][7][n],
+        ln_p_dev / ln_q_dev [P][n] (None = 0)."""
+        res = (Result * self.n_points)()
+        _bcheck(lib().ile_batch_run_dev(self.h, int(n_per_point), _dev(samples_dev),
+                                        _dev(ln_p_dev), _dev(ln_q_dev), res), self.h)
         return [r.as_dict() for r in res]
 
     def lnL(self, n_per_point):

@@ -228,6 +228,27 @@ def mode_waveforms(modes, n_q, srate_hz, seed, *, sigma_t=0.03, f0=40.0, fdot=15
 CONFIG4_SEEDS = (4001, 4002)   # (data and injection, samples)
 
 
+def combined_point(p):
+    """Point p of the combined workload: the batched mix (3 detectors,
+    n_lm in {5, 9, 13, 21}, n_t = 2h+1 with h ~ U{100..800}, 16384 points
+    at 16384 Hz, all by the point's seed) with a zero-noise injection at
+    network SNR 20 of the stand-in waveforms at seeded parameters, as for
+    the learned-proposal workload.  Returns the pieces (see config4_parts)."""
+    seed = 500_000 + p
+    rng = np.random.default_rng(seed)
+    n_lm = int(rng.choice([5, 9, 13, 21]))
+    n_t = 2 * int(rng.integers(100, 801)) + 1
+    names = ["D1", "D2", "D3"]
+    modes = MODE_ORDER[:n_lm]
+    n_q, srate = 16384, 16384.0
+    theta = np.array([rng.uniform(0, 2 * np.pi), math.asin(rng.uniform(-1, 1)),
+                      rng.uniform(0, np.pi), rng.uniform(0, 2 * np.pi),
+                      rng.uniform(-1, 1), 400.0, rng.uniform(-0.5, 0.5) * T_REF_MAX_S])
+    h = mode_waveforms(modes, n_q, srate, seed + 1, amp=20.0)
+    return dict(det_names=names, dets=[DETECTORS[d] for d in names], modes=modes,
+                n_q=n_q, srate_hz=srate, n_t=n_t, h_lm=h, theta_inj=theta, snr=20.0)
+
+
 def config4_parts(seed=None):
     """Learned-proposal workload: 3 detectors, 9 modes (l = 2, 3), 16384
     points at 16384 Hz, 1601 bins; a zero-noise injection at network SNR 20

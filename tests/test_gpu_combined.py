@@ -1,0 +1,112 @@
+"""The combined form: per-point learned proposals (with plain fallback)
+feeding one batched persistent evaluation of caller-supplied draws
+(ile_batch_run_dev).  Each point's ln L_marg from the batched run equals
+the FP64 oracle's on the same draws and weights (1e-3, the north-star
+tolerance; the FP32 bulk contraction is good to ~1e-6 relative per
+sample); the batched run of caller draws agrees with the single-point path
+on the same draws; invalid draws are rejected."""
+import numpy as np
+import pytest
+
+from paper_1902_04934_amd import combined, ile, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available()
+    return T
+
+
+@pytest.fixture(scope="module")
+def run4(torch):
+    points = [synth.combined_point(p) for p in range(4)]
+    n = 20_000
+    res, info, X, lp, lq, batch, t = combined.run(points, n)
+    yield points, n, res, info, X, lp, lq, batch, t
+    batch.close()
+
+
+def test_combined_matches_oracle(run4):
+    from oracle import oracle as O
+    points, n, res, info, X, lp, lq, batch, t = run4
+    print("timings", t)
+    for p, parts in enumerate(points):
+        inst = info[p]["inst"]
+        want_inst, _, _ = O.injection_instance(
+            synth.Instance(dets=inst.dets, modes=inst.modes, srate_hz=inst.srate_hz, n_t=inst.n_t,
+                           Q=np.zeros_like(inst.Q), U=np.zeros_like(inst.U),
+                           V=np.zeros_like(inst.V)),
+            parts["h_lm"], parts["theta_inj"], snr=parts["snr"])
+        x = X[p].cpu().numpy()
+        lnL = O.Ctx(want_inst).eval(x)
+        ref = O.integrate(lnL, lp[p].cpu().numpy(), lq[p].cpu().numpy())
+        got = res[p]
+        print(p, info[p]["n_lm"], info[p]["n_t"], "fell_back", info[p]["fell_back"],
+              got["ln_L_marg"], ref["ln_L_marg"], got["n_eff"], ref["n_eff"])
+        assert got["n_samples"] == n
+        assert abs(got["ln_L_marg"] - ref["ln_L_marg"]) <= 1e-3
+        assert abs(got["n_eff"] - ref["n_eff"]) <= 1e-3 * ref["n_eff"]
+        assert abs(got["max_ln_L"] - np.max(lnL)) <= 1e-4 * max(1.0, abs(np.max(lnL)))
+    # the per-sample outputs of the batched run
+    L = batch.lnL(n)
+    assert L.shape == (len(points), n) and np.all(np.isfinite(L))
+
+
+def test_combined_matches_single_point_path(run4, torch):
+    """Same draws through one context per point (ile_integrate_dev)."""
+    points, n, res, info, X, lp, lq, batch, t = run4
+    for p in (0, 2):
+        with ile.Context(info[p]["inst"], precision="fp32") as ctx:
+            out = torch.zeros(6, dtype=torch.float64, device="cuda")
+            ctx.integrate_dev(X[p], lp[p], lq[p], n, out)
+            ctx.sync()
+            r = out.cpu().numpy()
+        assert abs(r[0] - res[p]["ln_L_marg"]) <= 1e-6 * max(1.0, abs(r[0]))
+        assert abs(r[1] - res[p]["n_eff"]) <= 1e-6 * r[1]
+
+
+def test_prior_draws_through_run_dev_equal_run(torch):
+    """Prior draws given as caller draws (ln p = ln q) reproduce the batch's
+    own prior run bit for bit (same graph apart from the draw)."""
+    pts = [synth.batched_point(p, n_q=8192, srate_hz=8192.0) for p in range(3)]
+    n, seed = 4000, 9
+    with ile.Batch("fp32") as b:
+        for inst in pts:
+            b.add_point(inst)
+        want = b.run(seed, n)
+        X = torch.empty((3, 7, n), dtype=torch.float64, device="cuda")
+        for p, inst in enumerate(pts):
+            with ile.Context(inst, precision="fp32") as c:
+                c.draw_prior_dev(seed + p, 0, n, X[p], n)
+                c.sync()
+        got = b.run_dev(n, X)
+    for a, w in zip(got, want):
+        assert a["ln_L_marg"] == w["ln_L_marg"] and a["n_eff"] == w["n_eff"]
+        assert a["max_ln_L"] == w["max_ln_L"]
+
+
+def test_run_dev_rejects_invalid_draws(torch):
+    pts = [synth.batched_point(p, n_q=8192, srate_hz=8192.0) for p in range(2)]
+    n = 1000
+    with ile.Batch("fp32") as b:
+        for inst in pts:
+            b.add_point(inst)
+        X = torch.empty((2, 7, n), dtype=torch.float64, device="cuda")
+        for p, inst in enumerate(pts):
+            with ile.Context(inst, precision="fp32") as c:
+                c.draw_prior_dev(3 + p, 0, n, X[p], n)
+                c.sync()
+        lq = torch.zeros((2, n), dtype=torch.float64, device="cuda")
+        lq[1, 17] = -float("inf")
+        with pytest.raises(ile.IleError):
+            b.run_dev(n, X, None, lq)
+        lq[1, 17] = 0.0
+        X[0, 4, 5] = 1.5   # cos iota outside [-1, 1]
+        with pytest.raises(ile.IleError):
+            b.run_dev(n, X, None, lq)
+        X[0, 4, 5] = 0.5
+        ok = b.run_dev(n, X, None, lq)   # usable again afterwards
+        assert all(np.isfinite(r["ln_L_marg"]) for r in ok)

@@ -107,7 +107,7 @@ def test_learned_beats_plain_to_neff_1e4(torch):
         for seed in (41, 42, 43, 44):
             with ile.Proposal(ctx, seed=3) as p:
                 t0 = time.perf_counter()
-                # the run's defaults: 300 + 150-step refits of 16384, lr 2e-3, kappa 1.25
+                # the run's defaults: 300 + 150-step refits of 16384, lr 2e-3, kappa 1.2
                 lrn = ctx.run(sampler="learned", seed=seed, chunk=100_000,
                               max_samples=20_000_000, n_eff_target=target, adapt_chunks=3,
                               prop=p, eps=0.1)
