@@ -424,7 +424,8 @@ const char *ile_prop_last_error(const ile_prop *p);
  * Tuning (threads per workgroup, persistent workgroups per CU, queue order)
  * is set by hand or by ile_batch_autotune, which times the candidates and
  * caches the winner in a text file keyed by device, precision and the
- * points' shapes. */
+ * points' shapes.  Defaults: matrix cores, 2 workgroups per CU, queue by
+ * cost; 512 positions for FP32, 128 for BF16, 256 for FP64. */
 typedef struct ile_batch ile_batch;
 
 typedef struct {

@@ -360,6 +360,10 @@ ile_status ile_batch_create(const ile_batch_config *cfg, ile_batch **out)
     b->lds_max = (int)prop.sharedMemPerBlock;
     b->dev_name = prop.gcnArchName;
     b->tune.engine = 1;
+    // measured on 32 points of the 5-21-mode, 201-1601-bin mix at 1e6 draws
+    // each: FP32 fastest at 512 positions, BF16 at 128
+    if (cfg->precision == ILE_FP32) b->tune.threads = 512;
+    if (cfg->precision == ILE_BF16) b->tune.threads = 128;
     if (cfg->stream) {
         b->stream = (hipStream_t)cfg->stream;
     } else if (hipStreamCreate(&b->stream) != hipSuccess) {
