@@ -802,23 +802,34 @@ __global__ __launch_bounds__(256) void k_mdn_cast(ile_mdn_dev M)
     if (j < NPARAM) write_copies(M, j, M.theta[j]);
 }
 
-// Sum the partial rows in order, mask, normalize by the weight sum; then
-// one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 weights and
-// refresh the BF16 copies.
+// Sum the partial rows in a fixed order, mask, normalize by the weight sum;
+// then one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 weights
+// and refresh the BF16 copies.  A workgroup serves 64 parameters with four
+// row slices each (rows s, s+4, s+8, ...), so the read of all rows runs at
+// four times the occupancy; the slices combine in slice order.
+constexpr int UPD_P = 64;   // parameters per workgroup
 __global__ __launch_bounds__(256) void k_mdn_update(ile_mdn_dev M, const float *__restrict__ part,
                                                     int np, float *grad, double *loss, int adam,
                                                     float bc1, float bc2, float lr)
 {
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= NPARAM) return;
-    // sums in row order; the loads are independent, so unrolling lets many
-    // be in flight at once
+    __shared__ float red_g[4][UPD_P], red_w[4][UPD_P];
+    const int jj = threadIdx.x & (UPD_P - 1), sl = threadIdx.x / UPD_P;
+    const int j = blockIdx.x * UPD_P + jj;
     float ws = 0.f, gs = 0.f;
-#pragma unroll 16
-    for (int t = 0; t < np; t++) {
-        ws += part[(size_t)t * NPART + NPARAM + 1];
-        gs += part[(size_t)t * NPART + j];
+    if (j < NPARAM) {
+        // the loads are independent, so unrolling lets many be in flight
+#pragma unroll 8
+        for (int t = sl; t < np; t += 4) {
+            ws += part[(size_t)t * NPART + NPARAM + 1];
+            gs += part[(size_t)t * NPART + j];
+        }
     }
+    red_g[sl][jj] = gs;
+    red_w[sl][jj] = ws;
+    __syncthreads();
+    if (sl != 0 || j >= NPARAM) return;
+    gs = ((red_g[0][jj] + red_g[1][jj]) + red_g[2][jj]) + red_g[3][jj];
+    ws = ((red_w[0][jj] + red_w[1][jj]) + red_w[2][jj]) + red_w[3][jj];
     const float gj = (ws > 0.f && ile_mdn_trainable(j)) ? gs / ws : 0.f;
     if (j == 0 && loss) {
         float ls = 0.f;
@@ -1262,7 +1273,7 @@ hipError_t ile_launch_mdn_update(const ile_mdn_dev &M, const float *part, int n_
 {
     const double s = (double)std::max<int64_t>(step, 1);
     const float bc1 = (float)(1.0 - pow(0.9, s)), bc2 = (float)(1.0 - pow(0.999, s));
-    hipLaunchKernelGGL(k_mdn_update, dim3((NPARAM + 255) / 256), dim3(256), 0, st, M, part,
+    hipLaunchKernelGGL(k_mdn_update, dim3((NPARAM + UPD_P - 1) / UPD_P), dim3(256), 0, st, M, part,
                        n_part, grad, loss, adam ? 1 : 0, bc1, bc2, (float)lr);
     return hipGetLastError();
 }
