@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_prep_multi(const ile_geom *geoms,
     for (int k = 0; k < g.n_det; k++) shp[(int64_t)k * n + t] = ok ? sh[k] : -1;
     key += (uint32_t)p * B;
     keys[i] = key;
-    atomicAdd(&hist[key], 1u);
+    (void)wave_count_slot(hist, key);
 }
 
 // sorted position -> local sample index of the point
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void k_scatter_multi(const uint32_t *keys, con
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_total) return;
     const int p = point_of(offs, n_points, i);
-    const uint32_t at = atomicAdd(&pos[keys[i]], 1u);
+    const uint32_t at = wave_count_slot(pos, keys[i]);
     perm[at] = (int32_t)(i - offs[p]);
 }
 

@@ -47,6 +47,30 @@ struct ile_point_dev {
     double *out;              // lnLmargT [N]
 };
 
+// Increment table[key] by one for every active lane, aggregated over the
+// lanes of the wave that share a key: one atomic per distinct key (the
+// ordering keys of concentrated draws fall into few buckets, where one
+// atomic per lane serializes).  Returns the lane's slot: the table value
+// before the wave's increment plus the lane's rank among the lanes with its
+// key.  Every active lane of the wave must call it.
+__device__ inline uint32_t wave_count_slot(uint32_t *table, uint32_t key)
+{
+    uint64_t todo = __ballot(1);
+    const int lane = __lane_id();
+    uint32_t slot = 0;
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const uint32_t k0 = __shfl(key, leader);
+        const uint64_t same = __ballot(key == k0);
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&table[k0], (uint32_t)__popcll(same));
+        base = __shfl(base, leader);
+        if (key == k0) slot = base + (uint32_t)__popcll(same & ((1ull << lane) - 1));
+        todo &= ~same;
+    }
+    return slot;
+}
+
 // K steps of the matrix-core contraction (4 real rows = 2 modes each); the
 // device Q holds 4 * ksp_of(n_lm) rows per detector (rows 2a and 2a+1 = Re,
 // Im of mode a, the rest zero).

@@ -262,7 +262,7 @@ __global__ __launch_bounds__(256) void k_prep(ile_geom g,
     }
     for (int k = 0; k < g.n_det; k++) shifts[(int64_t)k * N + i] = ok ? s[k] : -1;
     keys[i] = key;
-    atomicAdd(&hist[key], 1u);
+    (void)wave_count_slot(hist, key);
 }
 
 // Exclusive scan of n uint32 in place: blocks of 1024 threads x 4 values.
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(256) void k_scatter(const uint32_t *__restrict__ ke
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    uint32_t pos = atomicAdd(&offs[keys[i]], 1u);
+    const uint32_t pos = wave_count_slot(offs, keys[i]);
     perm[pos] = (int32_t)i;
 }
 
