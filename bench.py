@@ -197,6 +197,45 @@ def combined_leg(n_points=32, n=1_000_000, m_oracle=2000):
             "max_abs_d_ln_L_marg_vs_oracle": max(errs), "oracle_s": t_orc}
 
 
+def precision_forms(inst, n, seed, steps, m_oracle=2000):
+    """The bulk contraction in FP64, FP32 and BF16 hi/lo (time marginalization
+    and reduction in FP64 in all three) on the same workload: kernel time,
+    evaluation rate and fraction of the precision's peak, and the largest
+    per-sample |d lnL| / max(1, |lnL|) against the FP64 oracle on the first
+    m_oracle prior draws of the run's stream."""
+    import numpy as np
+    import torch
+    from oracle import oracle as O
+    from paper_1902_04934_amd import ile
+    peak = {"fp64": FP64_PEAK_TFLOPS, "fp32": FP32_PEAK_TFLOPS, "bf16": BF16_PEAK_TFLOPS}
+    fl = flops_per_sample(inst.n_det, inst.n_lm, inst.n_t) * n
+    out = {}
+    x = None
+    for prec in ("fp64", "fp32", "bf16"):
+        with ile.Context(inst, precision=prec) as ctx:
+            ctx.run_prior(seed, n)
+            kms = []
+            for _ in range(steps):
+                ctx.run_prior(seed, n)
+                kms.append(ctx.last_kernel_ms())
+            kernel_ms = sum(kms) / len(kms)
+            xd = torch.empty((7, m_oracle), dtype=torch.float64, device="cuda")
+            ctx.draw_prior_dev(seed, 0, m_oracle, xd, m_oracle)
+            lnd = torch.empty(m_oracle, dtype=torch.float64, device="cuda")
+            ctx.eval_dev(xd, m_oracle, lnd)
+            ctx.sync()
+            got = lnd.cpu().numpy()
+            if x is None:
+                x = xd.cpu().numpy()
+                want = O.Ctx(inst).eval(x)
+        err = float(np.max(np.abs(got - want) / np.maximum(1.0, np.abs(want))))
+        out[prec] = {"kernel_ms": kernel_ms, "evals_per_s": n * inst.n_t / (kernel_ms * 1e-3),
+                     "frac_of_peak": fl / (kernel_ms * 1e-3) / 1e12 / peak[prec],
+                     "max_rel_err_lnL_vs_oracle": err}
+    out["oracle_samples"] = m_oracle
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +249,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-plain sampler comparison")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the FP64/FP32/BF16 comparison on the same workload")
     ap.add_argument("--no-combined", action="store_true",
                     help="skip the combined-form leg (per-point learned proposals, batched)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -277,6 +318,7 @@ def main():
                    "sigma_ln_L": res["sigma_ln_L"]},
     }
     ctx.close()
+    out["precision_forms"] = None if args.no_forms else precision_forms(inst, n, seed, 3)
     out["learned"] = None if args.no_learned else learned_leg()
     out["combined"] = None if args.no_combined else combined_leg()
     if not args.no_cpu:

@@ -251,7 +251,7 @@ typedef struct {
     double fallback_neff;    /* (< 0: 1000; 0: never fall back)               */
     int32_t train_steps, train_batch;
     double lr;
-    int32_t refine_rounds;   /* refits after the first training (< 0: 16)     */
+    int32_t refine_rounds;   /* refits after the first training (< 0: 24)     */
     int32_t refine_steps;    /* (<= 0: 150)                                   */
     double refine_eff;       /* (<= 0: 0.05)                                  */
     double train_ess;        /* tempering target of the training weights, as

@@ -902,7 +902,7 @@ static ile_status run_learned(ile_ctx *c, const ile_run_opts *o, ile_result *out
     const double temper = o->temper > 0 ? o->temper : 10.0;
     const double eps = o->eps >= 0 ? o->eps : 0.1;
     const double fb = o->fallback_neff >= 0 ? o->fallback_neff : 1000.0;
-    const int refine_rounds = o->refine_rounds >= 0 ? o->refine_rounds : 16;
+    const int refine_rounds = o->refine_rounds >= 0 ? o->refine_rounds : 24;
     const int refine_steps = o->refine_steps > 0 ? o->refine_steps : 150;
     const double refine_eff = o->refine_eff > 0 ? o->refine_eff : 0.05;
     const double kappa = o->sigma_scale > 0 ? o->sigma_scale : 1.2;
