@@ -70,13 +70,14 @@ def flops_per_sample(n_det, n_lm, n_t):
     return 4 * n_det * n_lm * n_t + 16 * n_det * n_lm * n_lm
 
 
-def cpu_baseline(inst, n_total, seed, target_s=12.0):
+def cpu_baseline(inst, n_total, seed, target_s=15.0):
     """Time the FP64 oracle on the host on the first M samples of the same
-    workload, M sized for about target_s seconds of CPU work."""
+    workload, M sized for about target_s seconds of CPU work (capped at the
+    whole workload), from a first timing of 20000 samples."""
     from oracle import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
     octx = O.Ctx(inst)
-    m0 = 2000
+    m0 = 20000
     s0, _ = O.prior_draw(seed, 0, m0)
     t = time.perf_counter()
     octx.eval(s0, n_threads=threads)
