@@ -158,6 +158,62 @@ def integrate(lnLmargT, ln_p, ln_q):
                 sigma=r.sigma, max_lnL=r.max_lnL, n_samples=r.n_samples)
 
 
+# ------------------------------------------------ extrinsic harvest
+def inverse_cdf(c, target):
+    """Inverse-CDF pick on inclusive cumulative weights c: the first index
+    i with c[i] > target; when rounding leaves target at or above the total,
+    the first index whose cumulative weight reaches the total (so an index
+    of zero weight is never returned)."""
+    i = int(np.searchsorted(c, target, side="right"))
+    if i >= c.size:
+        i = int(np.searchsorted(c, c[-1], side="left"))
+    return i
+
+
+def harvest(ctx, samples, ln_p, ln_q, u):
+    """Joint extrinsic posterior draws from one final Monte Carlo iteration
+    (Sec. V: joint intrinsic and extrinsic information harvested from a
+    single final iteration; Eq. (3) at fixed intrinsic parameters).
+
+    The draws theta_alpha with log prior ln_p and log proposal ln_q, and the
+    bin grid t_j of Eq. (9), carry the joint weight
+        P(alpha, j)  proportional to  exp(ln p_alpha - ln q_alpha + L_alpha,j),
+    which factors into a sample draw with weight exp(lnLmargT + ln p - ln q)
+    (Eq. (4)'s weight) and a bin draw with weight exp(L_alpha,j) given the
+    sample.  Draw k takes the sample by inverse CDF of uniform u[0][k] on
+    the cumulative sample weights (index order), then the bin by inverse CDF
+    of u[1][k] on that sample's cumulative bin weights.  Bin j means the
+    geocentre time t_ref + (j - (n_t-1)/2)/srate.
+
+    Returns (idx [n_out] int64, bin [n_out] int32, theta [7][n_out]) with
+    theta the chosen sample with row 6 replaced by the bin time."""
+    inst = ctx.inst
+    s = np.ascontiguousarray(samples, np.float64)
+    u = np.asarray(u, np.float64).reshape(2, -1)
+    lnL = ctx.eval(s)
+    if not np.all(np.isfinite(lnL)):
+        raise ValueError("invalid sample")
+    lw = lnL + np.asarray(ln_p, np.float64) - np.asarray(ln_q, np.float64)
+    lw = np.where(np.isfinite(lw), lw, -np.inf)
+    if not np.any(np.isfinite(lw)):
+        raise ValueError("no sample with positive weight")
+    c = np.cumsum(np.exp(lw - lw.max()))
+    n_out = u.shape[1]
+    idx = np.zeros(n_out, np.int64)
+    bins = np.zeros(n_out, np.int32)
+    theta = np.zeros((7, n_out))
+    h = (inst.n_t - 1) // 2
+    for k in range(n_out):
+        a = inverse_cdf(c, u[0, k] * c[-1])
+        L = ctx.lnL_series(s[:, a])
+        cj = np.cumsum(np.exp(L - L.max()))
+        j = inverse_cdf(cj, u[1, k] * cj[-1])
+        idx[k], bins[k] = a, j
+        theta[:, k] = s[:, a]
+        theta[6, k] = s[6, a] + (j - h) / inst.srate_hz
+    return idx, bins, theta
+
+
 # ------------------------------------------------------------ sampling
 def philox4x32_10(ctr, key):
     c = (C.c_uint32 * 4)(*ctr)
