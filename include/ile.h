@@ -193,6 +193,39 @@ ile_status ile_run_prior(ile_ctx *ctx, uint64_t seed, int64_t N,
                          int64_t chunk, double d_min, double d_max,
                          ile_result *out);
 
+/* ------------------------------------------------- extrinsic harvest
+ * Joint extrinsic posterior draws from one final Monte Carlo iteration
+ * (Sec. V: joint intrinsic and extrinsic information harvested from a
+ * single final iteration; Eq. (3) at fixed intrinsic parameters).  The N
+ * device samples samples_dev[7][N] with log prior ln_p_dev[N] and log
+ * proposal density ln_q_dev[N] (either may be NULL: 0) and the bin grid of
+ * Eq. (9) carry the joint weight exp(ln p_alpha - ln q_alpha + L_alpha,j).
+ * Draw k (0 <= k < n_out) takes
+ *   alpha_k = the first alpha whose cumulative weight (index order) exceeds
+ *             u[0][k] times the total, the weight being
+ *             exp(lnLmargT_alpha + ln p_alpha - ln q_alpha), Eq. (4);
+ *   j_k     = the first bin whose cumulative exp(L_alpha_k,j) exceeds
+ *             u[1][k] times that sample's total,
+ * and when rounding leaves the target at the total, the first index that
+ * reaches it (an index of zero weight is never drawn).  u_dev is device
+ * double [2][n_out] of uniforms in [0, 1), the caller's random numbers.
+ * Writes device idx_dev[n_out] (alpha_k), bin_dev[n_out] (j_k) and, if
+ * theta_dev is not NULL, theta_dev[7][n_out]: sample alpha_k with row 6
+ * replaced by the bin's geocentre time t_ref + (j_k - (n_t-1)/2)/srate.
+ * ln p = -inf is a zero weight.  Blocking (returns when the outputs are
+ * written).  Errors: ILE_E_ARG for N <= 0, n_out < 0 or a NULL pointer
+ * that is needed; ILE_E_RANGE for a sample out of range (as ile_eval), a
+ * NaN ln p or ln q, ln p = +inf, ln q = -inf, or a uniform outside
+ * [0, 1); ILE_E_NUMERIC if no sample has a finite positive weight.  On
+ * error the outputs are unspecified.  Device work: one evaluation of the N
+ * samples, then the per-bin series of the drawn samples in chunks of at
+ * most 256 MiB (n_out = 0 is a no-op). */
+ile_status ile_harvest_dev(ile_ctx *ctx, const double *samples_dev,
+                           const double *ln_p_dev, const double *ln_q_dev,
+                           int64_t N, const double *u_dev, int64_t n_out,
+                           int64_t *idx_dev, int32_t *bin_dev,
+                           double *theta_dev);
+
 /* ----------------------------------------------------------- samplers
  * The Monte Carlo over extrinsic parameters (Sec. II.A: direct Monte Carlo
  * with an adaptive sampling prior; Sec. III.B: the sampling prior is

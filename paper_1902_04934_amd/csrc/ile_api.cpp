@@ -53,6 +53,7 @@ struct ile_ctx {
     DevBuf hP, hC, bins, hist_tmp;  // adaptive proposal state and scratch
     int hist_nb = 0;
     DevBuf trx, trw;                // training set of the learned sampler
+    DevBuf hv_w, hv_cdf, hv_ws, hv_part, hv_flag, hv_sel;   // harvest
     ile_learned_info learned{};
     std::vector<hipEvent_t> ev;   // pairs around contraction launches
     int n_ev_used = 0;
@@ -745,6 +746,56 @@ ile_status ile_draw_prior_dev(ile_ctx *c, uint64_t seed, int64_t first, int64_t 
     return ILE_OK;
 }
 
+// Extrinsic posterior harvest (Sec. V; Eq. (3) at fixed intrinsic
+// parameters): sample weights and their prefix sums, one inverse-CDF pick per
+// draw, then the per-bin series of the picked samples in chunks of at most
+// 256 MiB and one bin pick per draw.
+ile_status ile_harvest_dev(ile_ctx *c, const double *smp, const double *lp, const double *lq,
+                           int64_t N, const double *u, int64_t n_out, int64_t *idx,
+                           int32_t *bins, double *theta)
+{
+    ile_status s = check_ready(c);
+    if (s) return s;
+    if (N <= 0 || n_out < 0 || !smp || (n_out > 0 && (!u || !idx || !bins)))
+        return fail(c, ILE_E_ARG, "bad N, n_out or pointer");
+    if (N > 0x7fffffff) return fail(c, ILE_E_ARG, "N = %lld exceeds 2^31-1", (long long)N);
+    if (n_out == 0) return ILE_OK;
+    const int n_t = c->cfg.n_t, nb = ile_hv_parts();
+    const int64_t m_max = std::max<int64_t>(1, ((int64_t)1 << 28) / ((int64_t)n_t * 8));
+    const int64_t m_cap = std::min<int64_t>(m_max, n_out);
+    hipStream_t st = c->stream;
+    if ((s = ensure(c, c->out, (size_t)std::max<int64_t>(N, m_cap) * sizeof(double)))) return s;
+    if ((s = ensure(c, c->hv_w, (size_t)N * sizeof(double)))) return s;
+    if ((s = ensure(c, c->hv_cdf, (size_t)N * sizeof(double)))) return s;
+    if ((s = ensure(c, c->hv_ws, ile_mdn_fit_ws_doubles() * sizeof(double)))) return s;
+    if ((s = ensure(c, c->hv_part, (size_t)nb * sizeof(double)))) return s;
+    if ((s = ensure(c, c->hv_flag, 16))) return s;
+    if ((s = ensure(c, c->hv_sel, (size_t)m_cap * 7 * sizeof(double)))) return s;
+    if ((s = ensure(c, c->series, (size_t)m_cap * n_t * sizeof(double)))) return s;
+    int32_t *flag = (int32_t *)c->hv_flag.p;
+    double *lnL = (double *)c->out.p, *w = (double *)c->hv_w.p, *cdf = (double *)c->hv_cdf.p;
+    HIP_TRY(c, hipMemsetAsync(flag, 0, sizeof(int32_t), st));
+    if ((s = run_eval(c, smp, N, lnL, nullptr))) return s;
+    HIP_TRY(c, ile_launch_hv_weights(lnL, lp, lq, N, w, (double *)c->hv_part.p, flag, st));
+    HIP_TRY(c, ile_launch_mdn_cdf(w, N, cdf, (double *)c->hv_ws.p, st));
+    HIP_TRY(c, ile_launch_hv_pick(cdf, N, u, n_out, idx, flag, st));
+    if ((s = finish_call(c))) return s;
+    int32_t f = 0;
+    HIP_TRY(c, hipMemcpy(&f, flag, sizeof(f), hipMemcpyDeviceToHost));
+    if (f & 1) return fail(c, ILE_E_RANGE, "ln_p/ln_q invalid (NaN, ln p = +inf or ln q = -inf)");
+    if (f & 4) return fail(c, ILE_E_RANGE, "a uniform of u lies outside [0, 1)");
+    if (f & 2) return fail(c, ILE_E_NUMERIC, "no sample has a finite positive weight");
+    double *sel = (double *)c->hv_sel.p, *ser = (double *)c->series.p;
+    for (int64_t k0 = 0; k0 < n_out; k0 += m_cap) {
+        const int64_t m = std::min<int64_t>(m_cap, n_out - k0);
+        HIP_TRY(c, ile_launch_hv_gather(smp, N, idx + k0, m, sel, st));
+        if ((s = run_eval(c, sel, m, lnL, ser))) return s;
+        HIP_TRY(c, ile_launch_hv_bin(ser, m, n_t, u + n_out + k0, sel, c->cfg.srate_hz,
+                                     bins + k0, theta ? theta + k0 : nullptr, n_out, st));
+    }
+    return finish_call(c);
+}
+
 ile_status ile_run_prior(ile_ctx *c, uint64_t seed, int64_t N, int64_t chunk,
                          double d_min, double d_max, ile_result *out)
 {
@@ -1196,7 +1247,8 @@ void ile_destroy(ile_ctx *c)
     for (DevBuf *b : {&c->Q, &c->U, &c->V, &c->smp, &c->out, &c->lnp, &c->lnq,
                       &c->shifts, &c->keys, &c->perm, &c->hist, &c->scan_tmp,
                       &c->errflag, &c->red_tmp, &c->parts, &c->res, &c->series,
-                      &c->hP, &c->hC, &c->bins, &c->hist_tmp, &c->trx, &c->trw})
+                      &c->hP, &c->hC, &c->bins, &c->hist_tmp, &c->trx, &c->trw,
+                      &c->hv_w, &c->hv_cdf, &c->hv_ws, &c->hv_part, &c->hv_flag, &c->hv_sel})
         release(*b);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);

@@ -154,6 +154,24 @@ hipError_t ile_launch_batch_lw(const double *lp, const double *lq, int64_t n_tot
 hipError_t ile_launch_to_bf16_split(const double *Q, int64_t n, void *dst,
                                     hipStream_t st);
 
+// ------------------------------------------------ extrinsic harvest
+// weights: w = exp(ln w - max ln w), ln w = lnL + ln p - ln q (NULL: 0),
+// part: ile_hv_parts() doubles; err bit 0: an invalid ln p / ln q, bit 1:
+// no finite positive weight.  pick (u is [2][n_out]): err bit 2 for a uniform
+// outside [0, 1) in either row.
+int ile_hv_parts();
+hipError_t ile_launch_hv_weights(const double *lnL, const double *ln_p, const double *ln_q,
+                                 int64_t n, double *w, double *part, int32_t *err,
+                                 hipStream_t st);
+hipError_t ile_launch_hv_pick(const double *cdf, int64_t n, const double *u, int64_t n_out,
+                              int64_t *idx, int32_t *err, hipStream_t st);
+hipError_t ile_launch_hv_gather(const double *smp, int64_t ld, const int64_t *idx, int64_t m,
+                                double *sel, hipStream_t st);
+// one wave per row of series[m][n_t]; theta [7][ld_out] may be NULL
+hipError_t ile_launch_hv_bin(const double *series, int64_t m, int n_t, const double *v,
+                             const double *sel, double srate, int32_t *bins, double *theta,
+                             int64_t ld_out, hipStream_t st);
+
 // ------------------------------------------------ learned proposal (MDN)
 // Network sizes and the flat parameter layout (W1 | b1 | W2 | b2 | W3 | b3,
 // row-major, masked entries held at zero) documented in ile.h.

@@ -139,6 +139,8 @@ def lib():
         L.ile_integrate.argtypes = [_vp, _dp, _dp, _dp, C.c_int64, C.POINTER(Result)]
         L.ile_eval_dev.argtypes = [_vp, _vp, C.c_int64, _vp]
         L.ile_integrate_dev.argtypes = [_vp, _vp, _vp, _vp, C.c_int64, _vp]
+        L.ile_harvest_dev.argtypes = [_vp, _vp, _vp, _vp, C.c_int64, _vp, C.c_int64, _vp,
+                                      _vp, _vp]
         L.ile_draw_prior_dev.argtypes = [_vp, C.c_uint64, C.c_int64, C.c_int64,
                                          C.c_double, C.c_double, _vp, C.c_int64, _vp]
         L.ile_run_prior.argtypes = [_vp, C.c_uint64, C.c_int64, C.c_int64,
@@ -285,6 +287,13 @@ def ile_eval_dev(h, samples_dev, n, out_dev):
 def ile_integrate_dev(h, samples_dev, ln_p_dev, ln_q_dev, n, result_dev):
     _check(lib().ile_integrate_dev(h, _dev(samples_dev), _dev(ln_p_dev),
                                    _dev(ln_q_dev), int(n), _dev(result_dev)), h)
+
+
+def ile_harvest_dev(h, samples_dev, ln_p_dev, ln_q_dev, n, u_dev, n_out, idx_dev,
+                    bin_dev, theta_dev=None):
+    _check(lib().ile_harvest_dev(h, _dev(samples_dev), _dev(ln_p_dev), _dev(ln_q_dev),
+                                 int(n), _dev(u_dev), int(n_out), _dev(idx_dev),
+                                 _dev(bin_dev), _dev(theta_dev)), h)
 
 
 def ile_draw_prior_dev(h, seed, first, n, d_min, d_max, samples_dev, ld,
@@ -440,6 +449,11 @@ class Context:
 
     def integrate_dev(self, samples_dev, ln_p_dev, ln_q_dev, n, result_dev):
         ile_integrate_dev(self.h, samples_dev, ln_p_dev, ln_q_dev, n, result_dev)
+
+    def harvest_dev(self, samples_dev, ln_p_dev, ln_q_dev, n, u_dev, n_out, idx_dev,
+                    bin_dev, theta_dev=None):
+        ile_harvest_dev(self.h, samples_dev, ln_p_dev, ln_q_dev, n, u_dev, n_out, idx_dev,
+                        bin_dev, theta_dev)
 
     def draw_prior_dev(self, seed, first, n, samples_dev, ld, ln_p_dev=None,
                        d_min=10.0, d_max=1000.0):
