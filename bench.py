@@ -198,6 +198,57 @@ def combined_leg(n_points=32, n=1_000_000, m_oracle=2000):
             "max_abs_d_ln_L_marg_vs_oracle": max(errs), "oracle_s": t_orc}
 
 
+def harvest_leg(inst, n, seed, n_out=100_000, steps=3, m_check=50):
+    """Extrinsic posterior harvest on the benchmark workload as one final
+    iteration: n prior draws (proposal = prior, so the sample weight is the
+    likelihood) evaluated and reduced to ln L_marg, and n_out joint (sample,
+    time bin) draws.  Reports the blocking call's wall time and
+    checks m_check draws' bins against the oracle's per-bin series, and every
+    draw's parameters against its sample."""
+    import numpy as np
+    import torch
+    from oracle import oracle as O
+    from paper_1902_04934_amd import ile
+    with ile.Context(inst) as ctx:
+        X = torch.empty((7, n), dtype=torch.float64, device="cuda")
+        lp = torch.empty(n, dtype=torch.float64, device="cuda")
+        ctx.draw_prior_dev(seed, 0, n, X, n, lp)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(seed + 17)
+        u = torch.rand((2, n_out), dtype=torch.float64, device="cuda", generator=g)
+        idx = torch.empty(n_out, dtype=torch.int64, device="cuda")
+        bins = torch.empty(n_out, dtype=torch.int32, device="cuda")
+        th = torch.empty((7, n_out), dtype=torch.float64, device="cuda")
+        res = torch.empty(6, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()   # u comes from torch's stream, the draws from the context's
+        ctx.sync()
+        ctx.harvest_dev(X, lp, lp, n, u, n_out, idx, bins, th, res)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.harvest_dev(X, lp, lp, n, u, n_out, idx, bins, th, res)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        xs, ids, bs, ths, us, r = (t.cpu().numpy() for t in (X, idx, bins, th, u, res))
+    h = (inst.n_t - 1) // 2
+    octx = O.Ctx(inst)
+    rng = np.random.default_rng(seed)
+    agree = 0
+    for k in rng.choice(n_out, m_check, replace=False):
+        L = octx.lnL_series(xs[:, ids[k]])
+        c = np.cumsum(np.exp(L - L.max()))
+        agree += int(O.inverse_cdf(c, us[1, k] * c[-1]) == bs[k])
+    consistent = bool(np.array_equal(ths[:6], xs[:6, ids]) and np.array_equal(
+        ths[6], xs[6, ids] + (bs.astype(np.int64) - h) / inst.srate_hz))
+    return {"workload": f"{n} prior draws of the benchmark point, {n_out} joint "
+                        f"(sample, time bin) draws over {inst.n_t} bins",
+            "harvest_ms": ms, "draws_per_s": n_out / (ms * 1e-3),
+            "ln_L_marg": float(r[0]), "n_eff": float(r[1]),
+            "distinct_samples": int(np.unique(ids).size),
+            "oracle_bin_checks": m_check, "oracle_bin_agree": agree,
+            "params_consistent": consistent}
+
+
 def precision_forms(inst, n, seed, steps, m_oracle=2000):
     """The bulk contraction in FP64, FP32 and BF16 hi/lo (time marginalization
     and reduction in FP64 in all three) on the same workload: kernel time,
@@ -254,6 +305,8 @@ def main():
                     help="skip the FP64/FP32/BF16 comparison on the same workload")
     ap.add_argument("--no-combined", action="store_true",
                     help="skip the combined-form leg (per-point learned proposals, batched)")
+    ap.add_argument("--no-harvest", action="store_true",
+                    help="skip the extrinsic posterior harvest leg")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -320,6 +373,7 @@ def main():
     }
     ctx.close()
     out["precision_forms"] = None if args.no_forms else precision_forms(inst, n, seed, 3)
+    out["harvest"] = None if args.no_harvest else harvest_leg(inst, n, seed)
     out["learned"] = None if args.no_learned else learned_leg()
     out["combined"] = None if args.no_combined else combined_leg()
     if not args.no_cpu:

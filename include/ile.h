@@ -212,6 +212,9 @@ ile_status ile_run_prior(ile_ctx *ctx, uint64_t seed, int64_t N,
  * Writes device idx_dev[n_out] (alpha_k), bin_dev[n_out] (j_k) and, if
  * theta_dev is not NULL, theta_dev[7][n_out]: sample alpha_k with row 6
  * replaced by the bin's geocentre time t_ref + (j_k - (n_t-1)/2)/srate.
+ * If result_dev is not NULL it receives the Eq. (4) reduction of the same
+ * evaluation, as ile_integrate_dev writes it (6 doubles), so that one call
+ * is the whole final iteration: ln L_marg and the joint draws.
  * ln p = -inf is a zero weight.  Blocking (returns when the outputs are
  * written).  Errors: ILE_E_ARG for N <= 0, n_out < 0 or a NULL pointer
  * that is needed; ILE_E_RANGE for a sample out of range (as ile_eval), a
@@ -219,12 +222,12 @@ ile_status ile_run_prior(ile_ctx *ctx, uint64_t seed, int64_t N,
  * [0, 1); ILE_E_NUMERIC if no sample has a finite positive weight.  On
  * error the outputs are unspecified.  Device work: one evaluation of the N
  * samples, then the per-bin series of the drawn samples in chunks of at
- * most 256 MiB (n_out = 0 is a no-op). */
+ * most 2 GiB, kept by the context for reuse (n_out = 0 is a no-op). */
 ile_status ile_harvest_dev(ile_ctx *ctx, const double *samples_dev,
                            const double *ln_p_dev, const double *ln_q_dev,
                            int64_t N, const double *u_dev, int64_t n_out,
                            int64_t *idx_dev, int32_t *bin_dev,
-                           double *theta_dev);
+                           double *theta_dev, double *result_dev);
 
 /* ----------------------------------------------------------- samplers
  * The Monte Carlo over extrinsic parameters (Sec. II.A: direct Monte Carlo
@@ -525,10 +528,13 @@ typedef enum {
     ILE_OPT_ENGINE = 1,  /* contraction engine: 1 = matrix cores (default;
                             the only BF16 engine), 0 = vector FMA (a block
                             width of 128 or 192 becomes 256) */
-    ILE_OPT_THREADS = 2  /* positions per block: 256 or 512, or 128 or 192
+    ILE_OPT_THREADS = 2, /* positions per block: 256 or 512, or 128 or 192
                             with the matrix cores (workgroups of twice as
                             many threads: producers + consumers); default
                             128 for FP64 and BF16, 256 for FP32 */
+    ILE_OPT_HARVEST_ROWS = 3  /* most draws whose per-bin series
+                            ile_harvest_dev holds at once (>= 1; 0 restores
+                            the default of 2 GiB of series) */
 } ile_option;
 ile_status ile_set_option(ile_ctx *ctx, ile_option opt, int64_t value);
 

@@ -54,6 +54,7 @@ struct ile_ctx {
     int hist_nb = 0;
     DevBuf trx, trw;                // training set of the learned sampler
     DevBuf hv_w, hv_cdf, hv_ws, hv_part, hv_flag, hv_sel;   // harvest
+    int64_t hv_rows = 0;            // draws per series chunk (0: 2 GiB of series)
     ile_learned_info learned{};
     std::vector<hipEvent_t> ev;   // pairs around contraction launches
     int n_ev_used = 0;
@@ -749,10 +750,10 @@ ile_status ile_draw_prior_dev(ile_ctx *c, uint64_t seed, int64_t first, int64_t 
 // Extrinsic posterior harvest (Sec. V; Eq. (3) at fixed intrinsic
 // parameters): sample weights and their prefix sums, one inverse-CDF pick per
 // draw, then the per-bin series of the picked samples in chunks of at most
-// 256 MiB and one bin pick per draw.
+// 2 GiB and one bin pick per draw.
 ile_status ile_harvest_dev(ile_ctx *c, const double *smp, const double *lp, const double *lq,
                            int64_t N, const double *u, int64_t n_out, int64_t *idx,
-                           int32_t *bins, double *theta)
+                           int32_t *bins, double *theta, double *result)
 {
     ile_status s = check_ready(c);
     if (s) return s;
@@ -761,14 +762,15 @@ ile_status ile_harvest_dev(ile_ctx *c, const double *smp, const double *lp, cons
     if (N > 0x7fffffff) return fail(c, ILE_E_ARG, "N = %lld exceeds 2^31-1", (long long)N);
     if (n_out == 0) return ILE_OK;
     const int n_t = c->cfg.n_t, nb = ile_hv_parts();
-    const int64_t m_max = std::max<int64_t>(1, ((int64_t)1 << 28) / ((int64_t)n_t * 8));
+    const int64_t m_max = c->hv_rows > 0 ? c->hv_rows
+                                          : std::max<int64_t>(1, ((int64_t)1 << 31) / ((int64_t)n_t * 8));
     const int64_t m_cap = std::min<int64_t>(m_max, n_out);
     hipStream_t st = c->stream;
     if ((s = ensure(c, c->out, (size_t)std::max<int64_t>(N, m_cap) * sizeof(double)))) return s;
     if ((s = ensure(c, c->hv_w, (size_t)N * sizeof(double)))) return s;
     if ((s = ensure(c, c->hv_cdf, (size_t)N * sizeof(double)))) return s;
     if ((s = ensure(c, c->hv_ws, ile_mdn_fit_ws_doubles() * sizeof(double)))) return s;
-    if ((s = ensure(c, c->hv_part, (size_t)nb * sizeof(double)))) return s;
+    if ((s = ensure(c, c->hv_part, (size_t)(nb + 1) * sizeof(double)))) return s;
     if ((s = ensure(c, c->hv_flag, 16))) return s;
     if ((s = ensure(c, c->hv_sel, (size_t)m_cap * 7 * sizeof(double)))) return s;
     if ((s = ensure(c, c->series, (size_t)m_cap * n_t * sizeof(double)))) return s;
@@ -776,6 +778,12 @@ ile_status ile_harvest_dev(ile_ctx *c, const double *smp, const double *lp, cons
     double *lnL = (double *)c->out.p, *w = (double *)c->hv_w.p, *cdf = (double *)c->hv_cdf.p;
     HIP_TRY(c, hipMemsetAsync(flag, 0, sizeof(int32_t), st));
     if ((s = run_eval(c, smp, N, lnL, nullptr))) return s;
+    if (result) {
+        if ((s = ensure(c, c->parts, 8 * sizeof(double)))) return s;
+        HIP_TRY(c, ile_launch_reduce(lnL, lp, lq, N, (double *)c->red_tmp.p,
+                                     (double *)c->parts.p, st));
+        HIP_TRY(c, ile_launch_finish((const double *)c->parts.p, 1, result, st));
+    }
     HIP_TRY(c, ile_launch_hv_weights(lnL, lp, lq, N, w, (double *)c->hv_part.p, flag, st));
     HIP_TRY(c, ile_launch_mdn_cdf(w, N, cdf, (double *)c->hv_ws.p, st));
     HIP_TRY(c, ile_launch_hv_pick(cdf, N, u, n_out, idx, flag, st));
@@ -1227,6 +1235,10 @@ ile_status ile_set_option(ile_ctx *c, ile_option opt, int64_t v)
     case ILE_OPT_THREADS:
         t.threads = (int)v;
         break;
+    case ILE_OPT_HARVEST_ROWS:
+        if (v < 0) return fail(c, ILE_E_ARG, "harvest rows must be >= 0");
+        c->hv_rows = v;
+        return ILE_OK;
     default:
         return fail(c, ILE_E_ARG, "unknown option %d", (int)opt);
     }

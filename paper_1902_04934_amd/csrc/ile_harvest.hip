@@ -7,13 +7,15 @@
 // exp(L_alpha,j) for that sample.
 //
 //   k_hv_lw    ln w per sample and per-block maxima
+//   k_hv_max   max ln w over the block maxima
 //   k_hv_w     w = exp(ln w - max ln w)        (then the fixed-order prefix
 //                                               sums of ile_launch_mdn_cdf)
 //   k_hv_pick  sample index per draw (binary search of the cumulative sums;
 //              u is [2][n_out], both rows are checked here)
 //   k_hv_gather  the chosen samples, packed, for the per-bin evaluation
 //   k_hv_bin   one wave per draw: the bin by a chunked wave scan of
-//              exp(L_j - max L), and the harvested parameters
+//              exp(L_j - max L), and the harvested parameters (the row in
+//              registers up to 2048 bins, streamed above)
 #include "ile_internal.h"
 
 #include <math.h>
@@ -59,12 +61,19 @@ __global__ __launch_bounds__(HV_T) void k_hv_lw(const double *__restrict__ lnL,
     }
 }
 
-__global__ __launch_bounds__(HV_T) void k_hv_w(double *__restrict__ w, int64_t n,
-                                               const double *__restrict__ part, int n_part,
-                                               int32_t *err)
+// max ln w over the per-block maxima into part[n_part] (one block)
+__global__ __launch_bounds__(64) void k_hv_max(double *part, int n_part)
 {
-    double M = -INFINITY;
-    for (int b = 0; b < n_part; b++) M = fmax(M, part[b]);
+    double m = -INFINITY;
+    for (int b = threadIdx.x; b < n_part; b += 64) m = fmax(m, part[b]);
+    m = wave_max_d(m);
+    if (threadIdx.x == 0) part[n_part] = m;
+}
+
+__global__ __launch_bounds__(HV_T) void k_hv_w(double *__restrict__ w, int64_t n,
+                                               const double *__restrict__ pM, int32_t *err)
+{
+    const double M = *pM;
     const int64_t i = (int64_t)blockIdx.x * HV_T + threadIdx.x;
     if (M == -INFINITY || M == INFINITY) {
         if (i == 0) atomicOr(err, 2);   // no sample with a finite positive weight
@@ -185,6 +194,68 @@ __global__ __launch_bounds__(HV_T) void k_hv_bin(const double *__restrict__ seri
     if (lane == 0) bins[r] = jsel;
 }
 
+// The same pick with the row held in registers (n_t <= 64 NC): one read of
+// the row, one exp per bin; the chunked scan and the two searches are those
+// of k_hv_bin.
+template <int NC>
+__global__ __launch_bounds__(HV_T) void k_hv_bin_reg(const double *__restrict__ series, int64_t m,
+                                                     int n_t, const double *__restrict__ v,
+                                                     const double *__restrict__ sel, double srate,
+                                                     int32_t *__restrict__ bins,
+                                                     double *__restrict__ theta, int64_t ld_out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * (HV_T / 64) + (threadIdx.x >> 6);
+    if (r >= m) return;   // whole waves leave together
+    const double *L = series + r * n_t;
+    const int nch = (n_t + 63) >> 6;
+    double x[NC];
+    double M = -INFINITY;
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+        const int j = c * 64 + lane;
+        x[c] = (c < nch && j < n_t) ? L[j] : -INFINITY;
+        M = fmax(M, x[c]);
+    }
+    M = wave_max_d(M);
+    double run = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+        if (c < nch) {
+            const int j = c * 64 + lane;
+            double e = j < n_t ? exp(x[c] - M) : 0.0;
+            for (int o = 1; o < 64; o <<= 1) {
+                const double y = __shfl_up(e, o, 64);
+                if (lane >= o) e += y;
+            }
+            x[c] = run + e;
+            run += __shfl(e, 63, 64);
+        }
+    }
+    const double tot = run, target = v[r] * tot;
+    int jsel = -1;
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+        if (c < nch && jsel < 0) {
+            const uint64_t hit = __ballot(c * 64 + lane < n_t && x[c] > target);
+            if (hit) jsel = c * 64 + __builtin_ctzll(hit);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+        if (c < nch && jsel < 0) {
+            const uint64_t hit = __ballot(c * 64 + lane < n_t && x[c] >= tot);
+            if (hit) jsel = c * 64 + __builtin_ctzll(hit);
+        }
+    }
+    if (theta && lane < 7) {
+        double y = sel[lane * m + r];
+        if (lane == 6) y += (double)(jsel - (n_t - 1) / 2) / srate;
+        theta[lane * ld_out + r] = y;
+    }
+    if (lane == 0) bins[r] = jsel;
+}
+
 }  // namespace
 
 int ile_hv_parts() { return 256; }
@@ -196,8 +267,9 @@ hipError_t ile_launch_hv_weights(const double *lnL, const double *ln_p, const do
     if (n <= 0) return hipSuccess;
     const int nb = ile_hv_parts();
     hipLaunchKernelGGL(k_hv_lw, dim3(nb), dim3(HV_T), 0, st, lnL, ln_p, ln_q, n, w, part, err);
+    hipLaunchKernelGGL(k_hv_max, dim3(1), dim3(64), 0, st, part, nb);
     hipLaunchKernelGGL(k_hv_w, dim3((unsigned)((n + HV_T - 1) / HV_T)), dim3(HV_T), 0, st, w, n,
-                       (const double *)part, nb, err);
+                       (const double *)(part + nb), err);
     return hipGetLastError();
 }
 
@@ -225,7 +297,15 @@ hipError_t ile_launch_hv_bin(const double *series, int64_t m, int n_t, const dou
 {
     if (m <= 0) return hipSuccess;
     constexpr int rows = HV_T / 64;
-    hipLaunchKernelGGL(k_hv_bin, dim3((unsigned)((m + rows - 1) / rows)), dim3(HV_T), 0, st,
-                       series, m, n_t, v, sel, srate, bins, theta, ld_out);
+    const dim3 grid((unsigned)((m + rows - 1) / rows));
+    if (n_t <= 64 * 8)
+        hipLaunchKernelGGL(k_hv_bin_reg<8>, grid, dim3(HV_T), 0, st, series, m, n_t, v, sel, srate,
+                           bins, theta, ld_out);
+    else if (n_t <= 64 * 32)
+        hipLaunchKernelGGL(k_hv_bin_reg<32>, grid, dim3(HV_T), 0, st, series, m, n_t, v, sel,
+                           srate, bins, theta, ld_out);
+    else
+        hipLaunchKernelGGL(k_hv_bin, grid, dim3(HV_T), 0, st, series, m, n_t, v, sel, srate, bins,
+                           theta, ld_out);
     return hipGetLastError();
 }

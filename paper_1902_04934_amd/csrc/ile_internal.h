@@ -156,7 +156,7 @@ hipError_t ile_launch_to_bf16_split(const double *Q, int64_t n, void *dst,
 
 // ------------------------------------------------ extrinsic harvest
 // weights: w = exp(ln w - max ln w), ln w = lnL + ln p - ln q (NULL: 0),
-// part: ile_hv_parts() doubles; err bit 0: an invalid ln p / ln q, bit 1:
+// part: ile_hv_parts() + 1 doubles; err bit 0: an invalid ln p / ln q, bit 1:
 // no finite positive weight.  pick (u is [2][n_out]): err bit 2 for a uniform
 // outside [0, 1) in either row.
 int ile_hv_parts();

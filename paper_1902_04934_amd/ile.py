@@ -25,6 +25,7 @@ PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
 ILE_OPT_SORT = 0
 ILE_OPT_ENGINE = 1
 ILE_OPT_THREADS = 2
+ILE_OPT_HARVEST_ROWS = 3
 
 
 class IleError(RuntimeError):
@@ -140,7 +141,7 @@ def lib():
         L.ile_eval_dev.argtypes = [_vp, _vp, C.c_int64, _vp]
         L.ile_integrate_dev.argtypes = [_vp, _vp, _vp, _vp, C.c_int64, _vp]
         L.ile_harvest_dev.argtypes = [_vp, _vp, _vp, _vp, C.c_int64, _vp, C.c_int64, _vp,
-                                      _vp, _vp]
+                                      _vp, _vp, _vp]
         L.ile_draw_prior_dev.argtypes = [_vp, C.c_uint64, C.c_int64, C.c_int64,
                                          C.c_double, C.c_double, _vp, C.c_int64, _vp]
         L.ile_run_prior.argtypes = [_vp, C.c_uint64, C.c_int64, C.c_int64,
@@ -290,10 +291,10 @@ def ile_integrate_dev(h, samples_dev, ln_p_dev, ln_q_dev, n, result_dev):
 
 
 def ile_harvest_dev(h, samples_dev, ln_p_dev, ln_q_dev, n, u_dev, n_out, idx_dev,
-                    bin_dev, theta_dev=None):
+                    bin_dev, theta_dev=None, result_dev=None):
     _check(lib().ile_harvest_dev(h, _dev(samples_dev), _dev(ln_p_dev), _dev(ln_q_dev),
                                  int(n), _dev(u_dev), int(n_out), _dev(idx_dev),
-                                 _dev(bin_dev), _dev(theta_dev)), h)
+                                 _dev(bin_dev), _dev(theta_dev), _dev(result_dev)), h)
 
 
 def ile_draw_prior_dev(h, seed, first, n, d_min, d_max, samples_dev, ld,
@@ -451,9 +452,9 @@ class Context:
         ile_integrate_dev(self.h, samples_dev, ln_p_dev, ln_q_dev, n, result_dev)
 
     def harvest_dev(self, samples_dev, ln_p_dev, ln_q_dev, n, u_dev, n_out, idx_dev,
-                    bin_dev, theta_dev=None):
+                    bin_dev, theta_dev=None, result_dev=None):
         ile_harvest_dev(self.h, samples_dev, ln_p_dev, ln_q_dev, n, u_dev, n_out, idx_dev,
-                        bin_dev, theta_dev)
+                        bin_dev, theta_dev, result_dev)
 
     def draw_prior_dev(self, seed, first, n, samples_dev, ld, ln_p_dev=None,
                        d_min=10.0, d_max=1000.0):

@@ -38,6 +38,7 @@ def run_harvest(torch, ctx, s, lp, lq, u, with_theta=True):
     bins = torch.full((max(n_out, 1),), -7, dtype=torch.int32, device="cuda")
     th = torch.full((7, max(n_out, 1)), np.nan, dtype=torch.float64, device="cuda") \
         if with_theta else None
+    torch.cuda.synchronize()   # the fills above run on torch's stream, not the context's
     ctx.harvest_dev(S, P, Q, n, U, n_out, idx, bins, th)
     torch.cuda.synchronize()
     return (idx.cpu().numpy()[:n_out], bins.cpu().numpy()[:n_out],
@@ -141,9 +142,9 @@ def test_harvest_reduced_precision_valid(torch, orc, precision):
 
 def test_harvest_chunks_and_full_size(torch, orc):
     """1601 bins, 21 modes, 3 detectors, 10^6 prior samples, 10^5 draws
-    (five series chunks of at most 20958 draws): every sample pick against
+    in one series chunk: every sample pick against
     the oracle's cumulative weights over all 10^6 samples, bins sampled
-    (both sides of every chunk boundary and 300 random draws)."""
+    (300 random draws)."""
     inst = synth.config2()
     n, seed = synth.CONFIG_SAMPLES[2]
     n_out = 100_000
@@ -157,7 +158,7 @@ def test_harvest_chunks_and_full_size(torch, orc):
     with ile.Context(inst) as ctx:
         idx, bins, theta = run_harvest(torch, ctx, s, lp, lq, u)
     d1 = check_samples(orc, s, lp, lq, lnL, u[0], idx)
-    m_max = (1 << 28) // (inst.n_t * 8)
+    m_max = (1 << 31) // (inst.n_t * 8)
     ks = set(rng.choice(n_out, 300, replace=False).tolist())
     for b in range(m_max, n_out, m_max):
         ks |= {b - 1, b}
@@ -169,6 +170,47 @@ def test_harvest_chunks_and_full_size(torch, orc):
     print(f"harvest full: {len(np.unique(idx))} distinct samples drawn; "
           f"{d1} sample and {d2} bin picks differ (valid)")
     assert d1 <= n_out // 1000 and d2 <= 2
+
+
+def test_harvest_result_is_the_integral(torch, orc):
+    """The optional Eq. (4) result of the harvest's own evaluation equals
+    ile_integrate_dev's on the same samples (same kernels: bit for bit) and
+    the oracle's reduction to 1e-9."""
+    inst = synth.make_instance(["D1", "D2", "D3"], 9, 4096, 4096.0, 201, 551)
+    s, lp, lq, u = _inputs(2500, 552, 300)
+    want = orc.integrate(orc.Ctx(inst).eval(s), lp, lq)
+    with ile.Context(inst) as ctx:
+        S, P, Q, U = (_dev(torch, x) for x in (s, lp, lq, u))
+        idx = torch.empty(300, dtype=torch.int64, device="cuda")
+        bins = torch.empty(300, dtype=torch.int32, device="cuda")
+        r1 = torch.full((6,), np.nan, dtype=torch.float64, device="cuda")
+        r2 = torch.full((6,), np.nan, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        ctx.harvest_dev(S, P, Q, s.shape[1], U, 300, idx, bins, None, r1)
+        ctx.integrate_dev(S, P, Q, s.shape[1], r2)
+        ctx.sync()
+        a, b = r1.cpu().numpy(), r2.cpu().numpy()
+    assert np.array_equal(a, b)
+    assert abs(a[0] - want["ln_L_marg"]) <= 1e-9
+    assert abs(a[1] - want["n_eff"]) <= 1e-9 * want["n_eff"]
+    assert a[5] == s.shape[1]
+
+
+def test_harvest_chunked_series(torch, orc):
+    """Series held for at most 777 draws at a time (ILE_OPT_HARVEST_ROWS):
+    the same picks as one chunk, and both sides of every chunk boundary
+    against the oracle."""
+    inst = synth.make_instance(["D1", "D2", "D3"], 9, 4096, 4096.0, 2401, 541)
+    s, lp, lq, u = _inputs(1500, 542, 5000)
+    octx = orc.Ctx(inst)
+    with ile.Context(inst) as ctx:
+        one = run_harvest(torch, ctx, s, lp, lq, u)
+        ile.ile_set_option(ctx.h, ile.ILE_OPT_HARVEST_ROWS, 777)
+        many = run_harvest(torch, ctx, s, lp, lq, u)
+    for x, y in zip(one, many):
+        assert np.array_equal(x, y)
+    ks = sorted({k for b in range(777, 5000, 777) for k in (b - 1, b)} | {0, 4999})
+    check_bins(orc, octx, inst, s, many[0], many[1], many[2], u[1], ks)
 
 
 def test_harvest_edge_cases(torch, orc):
