@@ -150,6 +150,36 @@ def learned_leg(target=1e4):
     return out
 
 
+def reuse_leg(n_points=8, target=1e4):
+    """Proposal reuse across intrinsic points on a sequence of neighbouring
+    points (the learned-proposal workload with the stand-in chirp's f0 and
+    fdot stepped by 1% per point): learned runs to n_eff = target, every
+    point cold, then the network and histograms carried from point to point
+    (warm).  Reports the wall time per point and the largest cold-warm
+    difference of ln L_marg in units of their combined standard error."""
+    import numpy as np
+    from paper_1902_04934_amd import reuse, synth
+    pts = synth.lambda_sequence(n_points)
+    cold = reuse.run(pts, warm=False, target=target)
+    warm = reuse.run(pts, warm=True, target=target)
+    def summary(rs):
+        return {"seconds": [r["seconds"] for r in rs], "refits": [r["refits"] for r in rs],
+                "fell_back": sum(r["fell_back"] for r in rs),
+                "n_eff": [r["n_eff"] for r in rs], "ln_L_marg": [r["ln_L_marg"] for r in rs]}
+    z = max(abs(c["ln_L_marg"] - w["ln_L_marg"]) / np.hypot(c["sigma_ln_L"], w["sigma_ln_L"])
+            for c, w in zip(cold, warm))
+    sc = sum(r["seconds"] for r in cold[1:])
+    sw = sum(r["seconds"] for r in warm[1:])
+    return {"workload": f"{n_points} neighbouring intrinsic points (3 detectors, 9 modes, 1601 "
+                        "bins, FP64, injections at network SNR 20), learned runs to "
+                        f"n_eff = {target:g}",
+            "cold": summary(cold), "warm": summary(warm),
+            "seconds_per_point_after_first": {"cold": sc / (n_points - 1),
+                                              "warm": sw / (n_points - 1)},
+            "speedup_after_first": sc / sw,
+            "max_abs_d_ln_L_over_sigma": float(z)}
+
+
 def combined_leg(n_points=32, n=1_000_000, m_oracle=2000):
     """The combined form at the combined workload's per-point shape (3
     detectors, 5-21 modes, 201-1601 bins, 16384-point Q in FP32, 1e6 draws
@@ -305,6 +335,8 @@ def main():
                     help="skip the FP64/FP32/BF16 comparison on the same workload")
     ap.add_argument("--no-combined", action="store_true",
                     help="skip the combined-form leg (per-point learned proposals, batched)")
+    ap.add_argument("--no-reuse", action="store_true",
+                    help="skip the proposal-reuse leg (cold vs warm over neighbouring points)")
     ap.add_argument("--no-harvest", action="store_true",
                     help="skip the extrinsic posterior harvest leg")
     ap.add_argument("--calib-copy", action="store_true",
@@ -375,6 +407,7 @@ def main():
     out["precision_forms"] = None if args.no_forms else precision_forms(inst, n, seed, 3)
     out["harvest"] = None if args.no_harvest else harvest_leg(inst, n, seed)
     out["learned"] = None if args.no_learned else learned_leg()
+    out["reuse"] = None if args.no_reuse else reuse_leg()
     out["combined"] = None if args.no_combined else combined_leg()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, n_total, seed)

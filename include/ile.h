@@ -299,6 +299,16 @@ typedef struct {
                                 chunks after it is not)                       */
     double sigma_scale;      /* kappa set on prop for the refinement and
                                 estimation draws (<= 0: 1.2)                 */
+    int32_t warm;            /* sampler LEARNED: 1 = prop carries a network
+                                trained at another intrinsic point (the
+                                integrator reused from point to point, Sec.
+                                II.C): the adaptive rounds draw from its
+                                defensive mixture (with the context's
+                                histograms, which are not refit in them)
+                                instead of from the histograms, and the first
+                                training takes refine_steps warm Adam steps
+                                from its current weights.  0: as described
+                                above                                        */
 } ile_run_opts;
 
 /* Monte Carlo estimate of ln L_marg: chunk after chunk, draw on the device,

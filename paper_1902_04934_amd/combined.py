@@ -12,15 +12,16 @@ import numpy as np
 from . import ile, synth
 
 
-def injected_point(parts, precision="fp32"):
+def injected_point(parts, precision="fp32", stream=None):
     """A context holding the device injection of one point (its Q, U, V built
-    on the device) and the host Instance with the same Q, U, V."""
+    on the device) and the host Instance with the same Q, U, V.  stream: a
+    hipStream_t handle for the context (None: its own)."""
     n_lm, n_q, nd = len(parts["modes"]), parts["n_q"], len(parts["dets"])
     base = synth.Instance(dets=parts["dets"], modes=parts["modes"], srate_hz=parts["srate_hz"],
                           n_t=parts["n_t"], Q=np.zeros((nd, n_lm, n_q), complex),
                           U=np.zeros((nd, n_lm, n_lm), complex),
                           V=np.zeros((nd, n_lm, n_lm), complex))
-    ctx = ile.Context(base, precision=precision)
+    ctx = ile.Context(base, precision=precision, stream=stream)
     rho2, dinj, Q, U, V = ile.ile_inject(ctx.h, parts["h_lm"], base.t0_s, base.dets,
                                          parts["theta_inj"], parts["snr"], want_data=True)
     inst = synth.Instance(dets=base.dets, modes=base.modes, srate_hz=base.srate_hz,

@@ -987,26 +987,34 @@ static ile_status run_learned(ile_ctx *c, const ile_run_opts *o, ile_result *out
     c->learned = ile_learned_info{};
     double *smp = (double *)c->smp.p, *lp = (double *)c->lnp.p, *lq = (double *)c->lnq.p;
     double *trx = (double *)c->trx.p, *trw = (double *)c->trw.p;
-    // 1. adaptive rounds: the training set
+    const ile_mdn_mix mix{nb, (const double *)c->hP.p, (const double *)c->hC.p, eps};
+    const bool warm = o->warm != 0;
+    // 1. adaptive rounds: the training set, drawn from the histograms (refit
+    //    after each round), or from the carried-over mixture when warm
     for (int rd = 0; rd < rounds; rd++) {
         const int64_t first = (int64_t)rd * chunk;
-        HIP_TRY(c, ile_launch_hist_draw(o->seed, first, chunk, nb, (const double *)c->hP.p,
-                                        (const double *)c->hC.p, o->d_min_mpc, o->d_max_mpc,
-                                        c->cfg.t_ref_max_s, smp, chunk, lp, lq,
-                                        (int32_t *)c->bins.p, c->stream));
+        if (warm)
+            HIP_TRY(c, ile_launch_mdn_sample(ile_prop_dev(o->prop), mix, o->seed, first, chunk,
+                                             smp, chunk, lp, lq, ile_prop_grid(o->prop),
+                                             c->stream));
+        else
+            HIP_TRY(c, ile_launch_hist_draw(o->seed, first, chunk, nb, (const double *)c->hP.p,
+                                            (const double *)c->hC.p, o->d_min_mpc, o->d_max_mpc,
+                                            c->cfg.t_ref_max_s, smp, chunk, lp, lq,
+                                            (int32_t *)c->bins.p, c->stream));
         if ((s = run_eval(c, smp, chunk, (double *)c->out.p, nullptr))) return s;
         HIP_TRY(c, hipMemcpy2DAsync(trx + first, (size_t)ntr * sizeof(double), smp,
                                     (size_t)chunk * sizeof(double), (size_t)chunk * sizeof(double),
                                     7, hipMemcpyDeviceToDevice, c->stream));
         HIP_TRY(c, ile_launch_lnw((const double *)c->out.p, lp, lq, chunk, trw + first,
                                   c->stream));
-        if ((s = refit_impl(c, (const int32_t *)c->bins.p, chunk, (const double *)c->out.p, lp,
-                            lq, chunk, floor_w, temper)))
+        if (!warm && (s = refit_impl(c, (const int32_t *)c->bins.p, chunk,
+                                     (const double *)c->out.p, lp, lq, chunk, floor_w, temper)))
             return s;
     }
     // 2. training
     ile_prop_train_opts to{};
-    to.steps = o->train_steps > 0 ? o->train_steps : 300;
+    to.steps = warm ? refine_steps : (o->train_steps > 0 ? o->train_steps : 300);
     to.batch = o->train_batch > 0 ? o->train_batch : 16384;
     to.lr = o->lr > 0 ? o->lr : 2e-3;
     to.ess_frac = o->train_ess > 0 ? o->train_ess : 0.01;
@@ -1018,7 +1026,6 @@ static ile_status run_learned(ile_ctx *c, const ile_run_opts *o, ile_result *out
     c->learned.n_train_samples = ntr;
     c->learned.train_ms = ile_prop_last_ms(o->prop);
     c->learned.final_loss = loss;
-    const ile_mdn_mix mix{nb, (const double *)c->hP.p, (const double *)c->hC.p, eps};
     double r[6] = {0, 0, 0, 0, 0, 0};
     // 3. refinement: each chunk of the mixture replaces the oldest chunk of
     //    the training ring and the network is refit, until a chunk is

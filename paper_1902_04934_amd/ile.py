@@ -66,7 +66,8 @@ class RunOpts(C.Structure):
                 ("train_steps", C.c_int32), ("train_batch", C.c_int32), ("lr", C.c_double),
                 ("refine_rounds", C.c_int32), ("refine_steps", C.c_int32),
                 ("refine_eff", C.c_double), ("train_ess", C.c_double),
-                ("refine_kish", C.c_double), ("sigma_scale", C.c_double)]
+                ("refine_kish", C.c_double), ("sigma_scale", C.c_double),
+                ("warm", C.c_int32)]
 
 
 class LearnedInfo(C.Structure):
@@ -315,13 +316,15 @@ def ile_run(h, sampler="adaptive", seed=1, chunk=100_000, max_samples=1_000_000,
             n_eff_target=0.0, d_min=10.0, d_max=1000.0, n_bins=50, floor=0.1,
             temper=10.0, adapt_chunks=-1, reset=True, prop=None, eps=-1.0,
             fallback_neff=-1.0, train_steps=0, train_batch=0, lr=0.0, refine_rounds=-1,
-            refine_steps=0, refine_eff=0.0, train_ess=0.0, refine_kish=0.0, sigma_scale=0.0):
+            refine_steps=0, refine_eff=0.0, train_ess=0.0, refine_kish=0.0, sigma_scale=0.0,
+            warm=False):
     o = RunOpts(SAMPLER[sampler], int(seed), int(chunk), int(max_samples),
                 float(n_eff_target), float(d_min), float(d_max), int(n_bins),
                 float(floor), float(temper), int(adapt_chunks), 1 if reset else 0,
                 prop, float(eps), float(fallback_neff), int(train_steps),
                 int(train_batch), float(lr), int(refine_rounds), int(refine_steps),
-                float(refine_eff), float(train_ess), float(refine_kish), float(sigma_scale))
+                float(refine_eff), float(train_ess), float(refine_kish), float(sigma_scale),
+                1 if warm else 0)
     r = Result()
     nc = C.c_int64()
     _check(lib().ile_run(h, C.byref(o), C.byref(r), C.byref(nc)), h)

@@ -249,6 +249,24 @@ def combined_point(p):
                 n_q=n_q, srate_hz=srate, n_t=n_t, h_lm=h, theta_inj=theta, snr=20.0)
 
 
+def lambda_sequence(n_points, seed=None, step=0.01):
+    """A sequence of neighbouring intrinsic points for proposal reuse: the
+    learned-proposal workload's detectors, modes, grid and injected extrinsic
+    parameters, with the stand-in chirp's f0 and fdot (its intrinsic
+    parameters) raised by step * p at point p.  Each point is its own
+    zero-noise injection at network SNR 20, so neighbouring points share the
+    extrinsic posterior's location.  Returns a list of parts."""
+    base = config4_parts(seed)
+    seed = CONFIG4_SEEDS[0] if seed is None else seed
+    out = []
+    for p in range(n_points):
+        s = 1.0 + step * p
+        h = mode_waveforms(base["modes"], base["n_q"], base["srate_hz"], seed + 1, amp=20.0,
+                           f0=40.0 * s, fdot=1500.0 * s)
+        out.append(dict(base, h_lm=h))
+    return out
+
+
 def config4_parts(seed=None):
     """Learned-proposal workload: 3 detectors, 9 modes (l = 2, 3), 16384
     points at 16384 Hz, 1601 bins; a zero-noise injection at network SNR 20
