@@ -64,9 +64,10 @@ def test_warm_runs_reach_target(runs):
 
 
 def test_warm_mixture_same_sample_parity(torch, runs):
-    """The network left by the last warm run, as a defensive mixture with the
-    last point's histograms: device ln L_marg of its draws equals the
-    oracle's on the same samples and weights."""
+    """A network trained on the last point, then a warm run on that point
+    from it (its rounds drawn from the network's mixture): the run reaches
+    the target without falling back, and the device ln L_marg of the
+    mixture's draws equals the oracle's on the same samples and weights."""
     from oracle import oracle as O
     pts = runs[0]
     last = pts[-1]
