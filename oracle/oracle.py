@@ -158,6 +158,51 @@ def integrate(lnLmargT, ln_p, ln_q):
                 sigma=r.sigma, max_lnL=r.max_lnL, n_samples=r.n_samples)
 
 
+# ------------------------------------------ Q, U, V from the frequency domain
+def fft_freqs(n_q, df):
+    """Frequencies of the n_q-point FFT grid: i df for i < n_q/2, else
+    (i - n_q) df."""
+    i = np.arange(n_q)
+    return np.where(i < n_q // 2, i, i - n_q) * df
+
+
+def qvu_fd(h_f, d_f, psd, df, f_min, f_max, t0, s_idx=None):
+    """Q, U, V of Eq. (8) from frequency-domain series, each inner product
+    the band-limited noise-weighted integral of Eq. (2) taken as a sum over
+    the FFT grid f_i with spacing df:
+        <a|b>_k = 2 df sum_{f_min < |f_i| < f_max} conj(a_i) b_i / S_k,i,
+        Q_k,lm(t) = 2 df sum_i exp(2 pi i f_i t) conj(h_lm,i) d_k,i / S_k,i,
+        U_k = <h_lm|h_l'm'>_k,  V_k = <h*_lm|h_l'm'>_k,
+    where the transform of conj(h) at f is conj(h(-f)), so V's summand is
+    h_lm(-f_i) h_l'm'(f_i) / S_k,i.  h_f [n_lm][n], d_f [n_det][n] complex,
+    psd [n_det][n] the spectrum at |f_i|.  Q at the times t0 + s/(n df) for
+    s in s_idx (default all n), as the direct sum (no FFT)."""
+    h_f = np.asarray(h_f, np.complex128)
+    d_f = np.asarray(d_f, np.complex128)
+    psd = np.asarray(psd, np.float64)
+    n = h_f.shape[1]
+    f = fft_freqs(n, df)
+    band = (np.abs(f) > f_min) & (np.abs(f) < f_max)
+    w = np.where(band[None, :], 2.0 * df / np.where(band[None, :], psd, 1.0), 0.0)
+    s_idx = np.arange(n) if s_idx is None else np.asarray(s_idx)
+    t = t0 + s_idx / (n * df)
+    E = np.exp(2j * np.pi * np.outer(f, t))            # [n][len(s)]
+    n_det, n_lm = d_f.shape[0], h_f.shape[0]
+    Q = np.zeros((n_det, n_lm, s_idx.size), np.complex128)
+    for k in range(n_det):
+        for a in range(n_lm):
+            Q[k, a] = (w[k] * np.conj(h_f[a]) * d_f[k]) @ E
+    neg = (-np.arange(n)) % n                           # index of -f_i
+    U = np.zeros((n_det, n_lm, n_lm), np.complex128)
+    V = np.zeros((n_det, n_lm, n_lm), np.complex128)
+    for k in range(n_det):
+        for a in range(n_lm):
+            for b in range(n_lm):
+                U[k, a, b] = np.sum(w[k] * np.conj(h_f[a]) * h_f[b])
+                V[k, a, b] = np.sum(w[k] * h_f[a][neg] * h_f[b])
+    return Q, U, V
+
+
 # ------------------------------------------------ extrinsic harvest
 def inverse_cdf(c, target):
     """Inverse-CDF pick on inclusive cumulative weights c: the first index
