@@ -150,6 +150,42 @@ def learned_leg(target=1e4):
     return out
 
 
+def qvu_leg(steps=10):
+    """Q, U, V built on the device from frequency-domain series at the
+    benchmark point's shape (3 detectors, 21 modes, 16384-point grid at
+    16384 Hz, band 20-4000 Hz): wall time of the blocking build, the inverse
+    FFT's device time, and the build's compulsory HBM bytes (read h, d, S;
+    write Q, U, V) over its wall time against the 8 TB/s peak."""
+    import numpy as np
+    import torch
+    from paper_1902_04934_amd import ile, synth
+    c = synth.fd_inputs(["D1", "D2", "D3"], 21, 16384, 16384.0, 611)
+    nd, nl, n = 3, 21, c["n_q"]
+    H = torch.tensor(np.ascontiguousarray(c["h_f"]).view(np.float64), device="cuda")
+    D = torch.tensor(np.ascontiguousarray(c["d_f"]).view(np.float64), device="cuda")
+    P = torch.tensor(np.ascontiguousarray(c["psd"]), device="cuda")
+    Q = torch.empty((nd, nl, 2 * n), dtype=torch.float64, device="cuda")
+    U = torch.empty((nd, nl, 2 * nl), dtype=torch.float64, device="cuda")
+    V = torch.empty((nd, nl, 2 * nl), dtype=torch.float64, device="cuda")
+    h = ile.ile_create(c["dets"], c["modes"], c["srate_hz"], 1601)
+    try:
+        torch.cuda.synchronize()
+        ile.ile_qvu_fd_dev(h, H, D, P, n, c["df"], 20.0, 4000.0, -0.5, Q, U, V)
+        t0 = time.perf_counter()
+        ffts = []
+        for _ in range(steps):
+            ile.ile_qvu_fd_dev(h, H, D, P, n, c["df"], 20.0, 4000.0, -0.5, Q, U, V)
+            ffts.append(ile.lib().ile_last_kernel_ms(h))
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+    finally:
+        ile.ile_destroy(h)
+    nbytes = 16 * n * (nl + nd) + 8 * n * nd + 16 * n * nd * nl + 2 * 16 * nd * nl * nl
+    return {"workload": "Q, U, V of 3 detectors x 21 modes on a 16384-point grid "
+                        "(16384 Hz), band 20-4000 Hz, FP64",
+            "build_ms": ms, "ifft_ms": sum(ffts) / len(ffts), "compulsory_bytes": nbytes,
+            "hbm_frac_of_build": nbytes / (ms * 1e-3) / 8e12}
+
+
 def reuse_leg(n_points=8, target=1e4):
     """Proposal reuse across intrinsic points on a sequence of neighbouring
     points (the learned-proposal workload with the stand-in chirp's f0 and
@@ -335,6 +371,8 @@ def main():
                     help="skip the FP64/FP32/BF16 comparison on the same workload")
     ap.add_argument("--no-combined", action="store_true",
                     help="skip the combined-form leg (per-point learned proposals, batched)")
+    ap.add_argument("--no-qvu", action="store_true",
+                    help="skip the frequency-domain Q, U, V construction leg")
     ap.add_argument("--no-reuse", action="store_true",
                     help="skip the proposal-reuse leg (cold vs warm over neighbouring points)")
     ap.add_argument("--no-harvest", action="store_true",
@@ -407,6 +445,7 @@ def main():
     out["precision_forms"] = None if args.no_forms else precision_forms(inst, n, seed, 3)
     out["harvest"] = None if args.no_harvest else harvest_leg(inst, n, seed)
     out["learned"] = None if args.no_learned else learned_leg()
+    out["qvu"] = None if args.no_qvu else qvu_leg()
     out["reuse"] = None if args.no_reuse else reuse_leg()
     out["combined"] = None if args.no_combined else combined_leg()
     if not args.no_cpu:

@@ -129,6 +129,41 @@ ile_status ile_set_data(ile_ctx *ctx, const double *Q, int64_t n_q,
                         double t0_s, const double *U, const double *V,
                         const ile_detector *dets);
 
+/* Q, U, V of Eq. (8) built on the device from frequency-domain series and
+ * installed as by ile_set_data.  Each inner product is Eq. (2) as a sum over
+ * the n_q-point FFT grid f_i = i df for i < n_q/2, else (i - n_q) df:
+ *   <a|b>_k   = 2 df sum_{f_min < |f_i| < f_max} conj(a_i) b_i / S_k,i,
+ *   Q_k,lm[s] = 2 df sum_i exp(2 pi i f_i t_s) conj(h_lm,i) d_k,i / S_k,i
+ *               over the same band, t_s = t0_s + s / (n_q df),
+ *   U_k = <h_lm|h_l'm'>_k,   V_k = <h*_lm|h_l'm'>_k, whose summand is
+ *               h_lm,-i h_l'm',i / S_k,i (the transform of conj(h) at f is
+ *               conj(h(-f))).
+ * h_f: host double [n_lm][n_q][2], the modes' transforms (time origin at
+ * the geocentre event time); d_f: host double [n_det][n_q][2], the data's
+ * transforms on the same clock; psd: host double [n_det][n_q], S_k at
+ * |f_i|, positive and finite inside the band.  The band is open; f_min < 0
+ * includes f = 0.  Q takes one inverse FFT per (detector, mode) row on the
+ * device (FP64, radix-4 self-sorting passes).  n_q must be a power of two in
+ * [2, 2^24] (ILE_E_UNSUPPORTED otherwise).  Q_out, U_out, V_out (may be
+ * NULL) receive host copies in ile_set_data's layouts.  Errors:
+ * ILE_E_ARG for NULL inputs, df <= 0, f_max <= f_min or a non-finite t0_s;
+ * ILE_E_NUMERIC for a non-finite input or a bad spectrum in the band; then
+ * ile_set_data's checks. */
+ile_status ile_set_data_fd(ile_ctx *ctx, const double *h_f, const double *d_f,
+                           const double *psd, int64_t n_q, double df, double f_min,
+                           double f_max, double t0_s, const ile_detector *dets,
+                           double *Q_out, double *U_out, double *V_out);
+
+/* The same construction on device buffers, without installing: h_f_dev
+ * [n_lm][n_q][2], d_f_dev [n_det][n_q][2], psd_dev [n_det][n_q] in; Q_dev
+ * [n_det][n_lm][n_q][2], U_dev and V_dev [n_det][n_lm][n_lm][2] out (every
+ * buffer the caller's).  Blocking; ile_last_kernel_ms then gives the inverse
+ * FFT's device time.  Errors as ile_set_data_fd. */
+ile_status ile_qvu_fd_dev(ile_ctx *ctx, const double *h_f_dev, const double *d_f_dev,
+                          const double *psd_dev, int64_t n_q, double df, double f_min,
+                          double f_max, double t0_s, double *Q_dev, double *U_dev,
+                          double *V_dev);
+
 /* A zero-noise injection built on the device and installed as by
  * ile_set_data: a physically consistent instance for tests of recovery.
  * White unit-variance noise, so Eq. (2) is <a|b> = sum_i conj(a_i) b_i with

@@ -55,6 +55,7 @@ struct ile_ctx {
     DevBuf trx, trw;                // training set of the learned sampler
     DevBuf hv_w, hv_cdf, hv_ws, hv_part, hv_flag, hv_sel;   // harvest
     int64_t hv_rows = 0;            // draws per series chunk (0: 2 GiB of series)
+    DevBuf fd_tmp, fd_flag, fd_in, fd_out;   // frequency-domain construction
     ile_learned_info learned{};
     std::vector<hipEvent_t> ev;   // pairs around contraction launches
     int n_ev_used = 0;
@@ -617,6 +618,87 @@ ile_status ile_inject(ile_ctx *c, const double *h_lm, int64_t n_q, double t0_s,
     if (Q_out) memcpy(Q_out, Q.data(), 8 * Q.size());
     if (U_out) memcpy(U_out, U.data(), 8 * U.size());
     if (V_out) memcpy(V_out, V.data(), 8 * V.size());
+    return ILE_OK;
+}
+
+// Q, U, V of Eq. (8) from frequency-domain series (Eq. (2) on the FFT grid):
+// the band-weighted products, an inverse FFT per (detector, mode) row and the
+// U, V sums, all on the device.  Blocking.
+ile_status ile_qvu_fd_dev(ile_ctx *c, const double *h_f, const double *d_f, const double *psd,
+                          int64_t n_q, double df, double f_min, double f_max, double t0_s,
+                          double *Q, double *U, double *V)
+{
+    if (!c) return ILE_E_ARG;
+    HIP_TRY(c, hipSetDevice(c->cfg.device));
+    begin_call(c);
+    if (!h_f || !d_f || !psd || !Q || !U || !V) return fail(c, ILE_E_ARG, "null pointer");
+    if (n_q < 2 || n_q > ((int64_t)1 << 24) || (n_q & (n_q - 1)))
+        return fail(c, ILE_E_UNSUPPORTED, "n_q = %lld is not a power of two in [2, 2^24]",
+                    (long long)n_q);
+    if (!(df > 0) || !std::isfinite(df) || !std::isfinite(t0_s) || std::isnan(f_min) ||
+        std::isnan(f_max) || !(f_max > f_min))
+        return fail(c, ILE_E_ARG, "bad df, band or t0");
+    const int nd = c->cfg.n_det, nl = c->cfg.n_lm, rows = nd * nl;
+    ile_status s;
+    if ((s = ensure(c, c->fd_tmp, (size_t)rows * n_q * 16))) return s;
+    if ((s = ensure(c, c->fd_flag, 16))) return s;
+    hipStream_t st = c->stream;
+    int32_t *flag = (int32_t *)c->fd_flag.p;
+    // the inverse FFT ends in Q: start in the scratch buffer when the number
+    // of passes (radix-4, plus one radix-2 for odd log2 n_q) is odd
+    const bool odd = ile_fft_passes(n_q) & 1;
+    double *a = odd ? (double *)c->fd_tmp.p : Q, *b = odd ? Q : (double *)c->fd_tmp.p, *res = nullptr;
+    HIP_TRY(c, hipMemsetAsync(flag, 0, sizeof(int32_t), st));
+    HIP_TRY(c, ile_launch_fd_prod(h_f, d_f, psd, n_q, nd, nl, df, f_min, f_max, t0_s, a, flag, st));
+    hipEvent_t e0 = next_event(c), e1 = next_event(c);
+    if (!e0 || !e1) return fail(c, ILE_E_DEVICE, "hipEventCreate failed");
+    HIP_TRY(c, hipEventRecord(e0, st));
+    HIP_TRY(c, ile_launch_ifft_rows(a, b, n_q, rows, &res, st));
+    HIP_TRY(c, hipEventRecord(e1, st));
+    if (res != Q) return fail(c, ILE_E_DEVICE, "internal: FFT result buffer");
+    HIP_TRY(c, ile_launch_uv_fd(h_f, psd, n_q, nd, nl, df, f_min, f_max, U, V, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) c->last_ms = ms;
+    c->n_ev_used = 0;
+    int32_t f = 0;
+    HIP_TRY(c, hipMemcpy(&f, flag, sizeof(f), hipMemcpyDeviceToHost));
+    if (f) return fail(c, ILE_E_NUMERIC, "non-finite input or non-positive spectrum in the band");
+    return ILE_OK;
+}
+
+ile_status ile_set_data_fd(ile_ctx *c, const double *h_f, const double *d_f, const double *psd,
+                           int64_t n_q, double df, double f_min, double f_max, double t0_s,
+                           const ile_detector *dets, double *Q_out, double *U_out,
+                           double *V_out)
+{
+    if (!c) return ILE_E_ARG;
+    HIP_TRY(c, hipSetDevice(c->cfg.device));
+    begin_call(c);
+    if (!h_f || !d_f || !psd || !dets) return fail(c, ILE_E_ARG, "null pointer");
+    if (n_q < 2 || n_q > ((int64_t)1 << 24) || (n_q & (n_q - 1)))
+        return fail(c, ILE_E_UNSUPPORTED, "n_q = %lld is not a power of two in [2, 2^24]",
+                    (long long)n_q);
+    const int nd = c->cfg.n_det, nl = c->cfg.n_lm;
+    const size_t nh = (size_t)2 * nl * n_q, ndd = (size_t)2 * nd * n_q, np_ = (size_t)nd * n_q;
+    const size_t nQ = (size_t)2 * nd * nl * n_q, nUV = (size_t)2 * nd * nl * nl;
+    ile_status s;
+    if ((s = ensure(c, c->fd_in, (nh + ndd + np_) * sizeof(double)))) return s;
+    if ((s = ensure(c, c->fd_out, (nQ + 2 * nUV) * sizeof(double)))) return s;
+    double *dh = (double *)c->fd_in.p, *dd = dh + nh, *dp = dd + ndd;
+    double *dQ = (double *)c->fd_out.p, *dU = dQ + nQ, *dV = dU + nUV;
+    HIP_TRY(c, hipMemcpy(dh, h_f, nh * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(dd, d_f, ndd * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(dp, psd, np_ * sizeof(double), hipMemcpyHostToDevice));
+    if ((s = ile_qvu_fd_dev(c, dh, dd, dp, n_q, df, f_min, f_max, t0_s, dQ, dU, dV))) return s;
+    std::vector<double> Q(nQ), U(nUV), V(nUV);
+    HIP_TRY(c, hipMemcpy(Q.data(), dQ, nQ * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(U.data(), dU, nUV * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(V.data(), dV, nUV * sizeof(double), hipMemcpyDeviceToHost));
+    if ((s = ile_set_data(c, Q.data(), n_q, t0_s, U.data(), V.data(), dets))) return s;
+    if (Q_out) memcpy(Q_out, Q.data(), nQ * sizeof(double));
+    if (U_out) memcpy(U_out, U.data(), nUV * sizeof(double));
+    if (V_out) memcpy(V_out, V.data(), nUV * sizeof(double));
     return ILE_OK;
 }
 
@@ -1267,7 +1349,8 @@ void ile_destroy(ile_ctx *c)
                       &c->shifts, &c->keys, &c->perm, &c->hist, &c->scan_tmp,
                       &c->errflag, &c->red_tmp, &c->parts, &c->res, &c->series,
                       &c->hP, &c->hC, &c->bins, &c->hist_tmp, &c->trx, &c->trw,
-                      &c->hv_w, &c->hv_cdf, &c->hv_ws, &c->hv_part, &c->hv_flag, &c->hv_sel})
+                      &c->hv_w, &c->hv_cdf, &c->hv_ws, &c->hv_part, &c->hv_flag, &c->hv_sel,
+                      &c->fd_tmp, &c->fd_flag, &c->fd_in, &c->fd_out})
         release(*b);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);

@@ -154,6 +154,21 @@ hipError_t ile_launch_batch_lw(const double *lp, const double *lq, int64_t n_tot
 hipError_t ile_launch_to_bf16_split(const double *Q, int64_t n, void *dst,
                                     hipStream_t st);
 
+// ------------------------------------ Q, U, V from the frequency domain
+// prod: X [n_det][n_lm][n] complex; err bit 0 for a non-finite input or a
+// non-positive spectrum in the band.  ifft_rows: inverse FFT of `rows`
+// complex rows of n (power of two) ping-ponging between a (input) and b;
+// *result is the buffer holding the output.
+hipError_t ile_launch_fd_prod(const double *h, const double *d, const double *psd, int64_t n,
+                              int n_det, int n_lm, double df, double f_min, double f_max,
+                              double t0, double *X, int32_t *err, hipStream_t st);
+int ile_fft_passes(int64_t n);
+hipError_t ile_launch_ifft_rows(double *a, double *b, int64_t n, int rows, double **result,
+                                hipStream_t st);
+hipError_t ile_launch_uv_fd(const double *h, const double *psd, int64_t n, int n_det, int n_lm,
+                            double df, double f_min, double f_max, double *U, double *V,
+                            hipStream_t st);
+
 // ------------------------------------------------ extrinsic harvest
 // weights: w = exp(ln w - max ln w), ln w = lnL + ln p - ln q (NULL: 0),
 // part: ile_hv_parts() + 1 doubles; err bit 0: an invalid ln p / ln q, bit 1:

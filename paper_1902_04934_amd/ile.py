@@ -141,6 +141,10 @@ def lib():
         L.ile_integrate.argtypes = [_vp, _dp, _dp, _dp, C.c_int64, C.POINTER(Result)]
         L.ile_eval_dev.argtypes = [_vp, _vp, C.c_int64, _vp]
         L.ile_integrate_dev.argtypes = [_vp, _vp, _vp, _vp, C.c_int64, _vp]
+        L.ile_set_data_fd.argtypes = [_vp, _dp, _dp, _dp, C.c_int64, C.c_double, C.c_double,
+                                      C.c_double, C.c_double, C.POINTER(Detector), _dp, _dp, _dp]
+        L.ile_qvu_fd_dev.argtypes = [_vp, _vp, _vp, _vp, C.c_int64, C.c_double, C.c_double,
+                                     C.c_double, C.c_double, _vp, _vp, _vp]
         L.ile_harvest_dev.argtypes = [_vp, _vp, _vp, _vp, C.c_int64, _vp, C.c_int64, _vp,
                                       _vp, _vp, _vp]
         L.ile_draw_prior_dev.argtypes = [_vp, C.c_uint64, C.c_int64, C.c_int64,
@@ -289,6 +293,33 @@ def ile_eval_dev(h, samples_dev, n, out_dev):
 def ile_integrate_dev(h, samples_dev, ln_p_dev, ln_q_dev, n, result_dev):
     _check(lib().ile_integrate_dev(h, _dev(samples_dev), _dev(ln_p_dev),
                                    _dev(ln_q_dev), int(n), _dev(result_dev)), h)
+
+
+def ile_set_data_fd(h, h_f, d_f, psd, df, f_min, f_max, t0_s, dets, want_data=False):
+    """Q, U, V from frequency-domain series (see ile.h); with want_data,
+    returns the host Q, U, V it installed."""
+    hf = np.ascontiguousarray(h_f, np.complex128)
+    dfa = np.ascontiguousarray(d_f, np.complex128)
+    ps = np.ascontiguousarray(psd, np.float64)
+    n_lm, n_q = hf.shape
+    n_det = dfa.shape[0]
+    det_arr = (Detector * n_det)(*[Detector(*d) for d in dets])
+    Q = np.zeros((n_det, n_lm, n_q), np.complex128) if want_data else None
+    U = np.zeros((n_det, n_lm, n_lm), np.complex128) if want_data else None
+    V = np.zeros((n_det, n_lm, n_lm), np.complex128) if want_data else None
+    vp = (lambda a: a.view(np.float64).ctypes.data_as(_dp)) if want_data else (lambda a: None)
+    _check(lib().ile_set_data_fd(h, hf.view(np.float64).ctypes.data_as(_dp),
+                                 dfa.view(np.float64).ctypes.data_as(_dp), ps.ctypes.data_as(_dp),
+                                 int(n_q), float(df), float(f_min), float(f_max), float(t0_s),
+                                 det_arr, vp(Q), vp(U), vp(V)), h)
+    return (Q, U, V) if want_data else None
+
+
+def ile_qvu_fd_dev(h, h_f_dev, d_f_dev, psd_dev, n_q, df, f_min, f_max, t0_s, Q_dev, U_dev,
+                   V_dev):
+    _check(lib().ile_qvu_fd_dev(h, _dev(h_f_dev), _dev(d_f_dev), _dev(psd_dev), int(n_q),
+                                float(df), float(f_min), float(f_max), float(t0_s),
+                                _dev(Q_dev), _dev(U_dev), _dev(V_dev)), h)
 
 
 def ile_harvest_dev(h, samples_dev, ln_p_dev, ln_q_dev, n, u_dev, n_out, idx_dev,

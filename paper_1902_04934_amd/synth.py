@@ -225,6 +225,38 @@ def mode_waveforms(modes, n_q, srate_hz, seed, *, sigma_t=0.03, f0=40.0, fdot=15
     return h
 
 
+def fd_inputs(det_names, n_lm, n_q, srate_hz, seed, *, f_knee=40.0):
+    """Frequency-domain stand-ins for building Q, U, V: the stand-in mode
+    series' transforms h_f [n_lm][n_q] (dt times the FFT; time origin at
+    sample 0), per-detector data transforms d_f [n_det][n_q] (coloured
+    Gaussian noise plus the first mode delayed by a seeded few ms and
+    scaled), and a smooth coloured spectrum psd [n_det][n_q] at |f_i|
+    (seismic wall below f_knee, flat bucket, shot-noise rise), each
+    detector's scaled by a seeded factor.  Data only."""
+    rng = np.random.default_rng(seed)
+    modes = MODE_ORDER[:n_lm]
+    dt = 1.0 / srate_hz
+    h = mode_waveforms(modes, n_q, srate_hz, seed + 1, amp=20.0)
+    h_f = dt * np.fft.fft(h, axis=1)
+    df = srate_hz / n_q
+    i = np.arange(n_q)
+    f = np.abs(np.where(i < n_q // 2, i, i - n_q) * df)
+    fs = np.maximum(f, df)
+    shape = (f_knee / fs) ** 4 + 1.0 + (fs / (8 * f_knee)) ** 2
+    n_det = len(det_names)
+    psd = np.empty((n_det, n_q))
+    d_f = np.empty((n_det, n_q), np.complex128)
+    sf = np.where(i < n_q // 2, i, i - n_q) * df
+    for k in range(n_det):
+        psd[k] = 1e-3 * shape * rng.uniform(0.5, 2.0)
+        noise = (rng.standard_normal(n_q) + 1j * rng.standard_normal(n_q)) \
+            * np.sqrt(psd[k] / (4 * df))
+        lag = rng.uniform(-0.01, 0.01)
+        d_f[k] = noise + rng.uniform(0.5, 1.5) * h_f[0] * np.exp(-2j * np.pi * sf * lag)
+    return dict(det_names=list(det_names), dets=[DETECTORS[d] for d in det_names],
+                modes=modes, n_q=n_q, srate_hz=srate_hz, df=df, h_f=h_f, d_f=d_f, psd=psd)
+
+
 CONFIG4_SEEDS = (4001, 4002)   # (data and injection, samples)
 
 
