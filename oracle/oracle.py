@@ -203,6 +203,44 @@ def qvu_fd(h_f, d_f, psd, df, f_min, f_max, t0, s_idx=None):
     return Q, U, V
 
 
+# ------------------------------------------- surrogate (reduced-order) form
+def rom_coeffs(A, lam):
+    """Surrogate coefficients c_lm,b(lambda) = sum_p A[lm][b][p] lambda^p of
+    the linear representation h_lm(lambda; t) = sum_b c_lm,b(lambda) e_b(t)
+    (Sec. V: a linear basis for h_lm enabling likelihoods as a function of
+    both extrinsic and intrinsic parameters).  A complex [n_lm][n_b][P]."""
+    A = np.asarray(A, np.complex128)
+    return np.tensordot(A, lam ** np.arange(A.shape[2]), axes=([2], [0]))
+
+
+def rom_instance(basis, modes, A, lam):
+    """The Eq. (8) quantities at lambda from the basis overlaps held in
+    `basis` (Q^B_k,b(t) = <e_b(t)|d>_k, G_k = <e_b|e_b'>_k, H_k =
+    <e_b*|e_b'>_k as its Q, U, V), by linearity of Eq. (2):
+        Q_k,lm(t) = sum_b conj(c_lm,b) Q^B_k,b(t),
+        U_k = conj(C) G_k C^T,   V_k = C H_k C^T   (C = [c_lm,b])."""
+    import copy
+    C = rom_coeffs(A, lam)
+    inst = copy.copy(basis)
+    inst.modes = list(modes)
+    inst.Q = np.einsum("ab,kbs->kas", np.conj(C), basis.Q)
+    inst.U = np.stack([np.conj(C) @ basis.U[k] @ C.T for k in range(basis.n_det)])
+    inst.V = np.stack([C @ basis.V[k] @ C.T for k in range(basis.n_det)])
+    return inst
+
+
+def rom_eval(basis, modes, A, samples8):
+    """ln L_margT of joint samples [8][N] (7 extrinsic rows, then lambda) by
+    the definition: the surrogate's Q, U, V at each sample's lambda, then
+    Eq. (7) and Eq. (9) as in Ctx.eval."""
+    s = np.asarray(samples8, np.float64)
+    out = np.empty(s.shape[1])
+    for i in range(s.shape[1]):
+        inst = rom_instance(basis, modes, A, s[7, i])
+        out[i] = Ctx(inst).eval(s[:7, i:i + 1])[0]
+    return out
+
+
 # ------------------------------------------------ extrinsic harvest
 def inverse_cdf(c, target):
     """Inverse-CDF pick on inclusive cumulative weights c: the first index
