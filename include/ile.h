@@ -228,6 +228,40 @@ ile_status ile_run_prior(ile_ctx *ctx, uint64_t seed, int64_t N,
                          int64_t chunk, double d_min, double d_max,
                          ile_result *out);
 
+/* ------------------------------------------- surrogate (linear-basis) form
+ * One Monte Carlo over intrinsic and extrinsic parameters at once (Sec. V:
+ * a linear representation of h_lm through basis functions gives the
+ * likelihood as a function of both).  The templates are
+ *   h_lm(lambda; t) = sum_b c_lm,b(lambda) e_b(t),
+ *   c_lm,b(lambda)  = sum_p A[lm][b][p] lambda^p,   lambda in [-1, 1],
+ * so by linearity of Eq. (2), with C = [c_lm,b]:
+ *   Q_k,lm(t) = sum_b conj(c_lm,b) Q^B_k,b(t),  U_k = conj(C) G_k C^T,
+ *   V_k = C H_k C^T,
+ * where Q^B_k,b(t) = <e_b(t)|d>_k, G_k = <e_b|e_b'>_k, H_k = <e_b*|e_b'>_k.
+ * Usage: create the context with n_lm = the basis size (its mode list is not
+ * used for harmonics in this form; any valid list), install Q^B, G, H as Q,
+ * U, V (ile_set_data or ile_set_data_fd), then ile_rom_set.  Eq. (7) then
+ * holds with -2Y_lm replaced by z_b = sum_lm c_lm,b(lambda) -2Y_lm(iota, phi)
+ * of the physical modes, computed per sample on the device.
+ *
+ * ile_rom_set: modes [n_lm] the physical modes (as in ile_config, n_lm <=
+ * ILE_MAX_LM), n_pow in [1, 8] powers of lambda, A host double
+ * [n_lm][n_b][n_pow][2] (n_b = the context's n_lm), copied.  ILE_E_ARG for a
+ * bad mode or size, ILE_E_NUMERIC for a non-finite A.
+ * ile_rom_eval_dev / ile_rom_integrate_dev: as ile_eval_dev and
+ * ile_integrate_dev for joint samples samples_dev[8][N]: rows 0..6 as
+ * everywhere, row 7 lambda.  A lambda outside [-1, 1] gives a NaN output
+ * and the sticky ILE_E_RANGE of ile_sync; ILE_E_STATE before ile_rom_set.
+ * Plain evaluation (ile_eval and the rest) of the same context keeps using
+ * its own mode list's harmonics. */
+ile_status ile_rom_set(ile_ctx *ctx, const ile_mode *modes, int32_t n_lm, int32_t n_pow,
+                       const double *A);
+ile_status ile_rom_eval_dev(ile_ctx *ctx, const double *samples_dev, int64_t N,
+                            double *lnL_margT_dev);
+ile_status ile_rom_integrate_dev(ile_ctx *ctx, const double *samples_dev,
+                                 const double *ln_p_dev, const double *ln_q_dev,
+                                 int64_t N, double *result_dev);
+
 /* ------------------------------------------------- extrinsic harvest
  * Joint extrinsic posterior draws from one final Monte Carlo iteration
  * (Sec. V: joint intrinsic and extrinsic information harvested from a

@@ -56,6 +56,9 @@ struct ile_ctx {
     DevBuf hv_w, hv_cdf, hv_ws, hv_part, hv_flag, hv_sel;   // harvest
     int64_t hv_rows = 0;            // draws per series chunk (0: 2 GiB of series)
     DevBuf fd_tmp, fd_flag, fd_in, fd_out;   // frequency-domain construction
+    ile_geom rom_g{};               // surrogate form: physical modes' Y tables
+    int rom_pow = 0;                // powers of lambda in the coefficients (0: not set)
+    DevBuf rom_A, rom_Z;
     ile_learned_info learned{};
     std::vector<hipEvent_t> ev;   // pairs around contraction launches
     int n_ev_used = 0;
@@ -699,6 +702,78 @@ ile_status ile_set_data_fd(ile_ctx *c, const double *h_f, const double *d_f, con
     if (Q_out) memcpy(Q_out, Q.data(), nQ * sizeof(double));
     if (U_out) memcpy(U_out, U.data(), nUV * sizeof(double));
     if (V_out) memcpy(V_out, V.data(), nUV * sizeof(double));
+    return ILE_OK;
+}
+
+// Surrogate (linear-basis) form, Sec. V: the context's n_lm "modes" are
+// basis functions e_b with Q, U, V their overlaps; each joint sample carries
+// lambda in row 7, and z = C(lambda) Y takes the place of the harmonics.
+ile_status ile_rom_set(ile_ctx *c, const ile_mode *modes, int32_t n_lm, int32_t n_pow,
+                       const double *A)
+{
+    if (!c) return ILE_E_ARG;
+    HIP_TRY(c, hipSetDevice(c->cfg.device));
+    begin_call(c);
+    if (!modes || !A) return fail(c, ILE_E_ARG, "null pointer");
+    if (n_lm < 1 || n_lm > ILE_MAX_LM || n_pow < 1 || n_pow > 8)
+        return fail(c, ILE_E_ARG, "n_lm = %d or n_pow = %d out of range", n_lm, n_pow);
+    for (int a = 0; a < n_lm; a++)
+        if (modes[a].l < 2 || modes[a].l > 6 || std::abs(modes[a].m) > modes[a].l)
+            return fail(c, ILE_E_ARG, "mode %d invalid", a);
+    ile_geom gp{};
+    gp.n_lm = n_lm;
+    if (!build_ylm_table(gp, std::vector<ile_mode>(modes, modes + n_lm)))
+        return fail(c, ILE_E_ARG, "mode list too long");
+    const size_t na = (size_t)2 * n_lm * c->cfg.n_lm * n_pow;
+    for (size_t i = 0; i < na; i++)
+        if (!std::isfinite(A[i])) return fail(c, ILE_E_NUMERIC, "A[%zu] not finite", i / 2);
+    ile_status s;
+    if ((s = ensure(c, c->rom_A, na * sizeof(double)))) return s;
+    HIP_TRY(c, hipMemcpy(c->rom_A.p, A, na * sizeof(double), hipMemcpyHostToDevice));
+    c->rom_g = gp;
+    c->rom_pow = n_pow;
+    return ILE_OK;
+}
+
+static ile_status rom_eval_impl(ile_ctx *c, const double *smp, int64_t N, double *out)
+{
+    ile_status s;
+    const int nb = c->cfg.n_lm;
+    if ((s = ensure(c, c->rom_Z, (size_t)std::max<int64_t>(N, 1) * nb * 2 * sizeof(double))))
+        return s;
+    if ((s = ensure_work(c, N))) return s;
+    HIP_TRY(c, ile_launch_rom_z(c->rom_g, smp, N, (const double *)c->rom_A.p, nb, c->rom_pow,
+                                (double *)c->rom_Z.p, (int32_t *)c->errflag.p, c->stream));
+    c->g.ext_y = (const double2 *)c->rom_Z.p;
+    s = run_eval(c, smp, N, out, nullptr);
+    c->g.ext_y = nullptr;
+    return s;
+}
+
+ile_status ile_rom_eval_dev(ile_ctx *c, const double *smp, int64_t N, double *out)
+{
+    ile_status s = check_ready(c);
+    if (s) return s;
+    if (!c->rom_pow) return fail(c, ILE_E_STATE, "ile_rom_set has not been called");
+    if (N < 0 || (N > 0 && (!smp || !out))) return fail(c, ILE_E_ARG, "bad N or pointer");
+    if (N == 0) return ILE_OK;
+    return rom_eval_impl(c, smp, N, out);
+}
+
+ile_status ile_rom_integrate_dev(ile_ctx *c, const double *smp, const double *lp,
+                                 const double *lq, int64_t N, double *res)
+{
+    ile_status s = check_ready(c);
+    if (s) return s;
+    if (!c->rom_pow) return fail(c, ILE_E_STATE, "ile_rom_set has not been called");
+    if (N < 0 || !res || (N > 0 && !smp)) return fail(c, ILE_E_ARG, "bad N or pointer");
+    if ((s = ensure(c, c->out, (size_t)std::max<int64_t>(N, 1) * sizeof(double)))) return s;
+    if ((s = ensure(c, c->parts, 8 * sizeof(double)))) return s;
+    if ((s = ensure_work(c, N))) return s;
+    if (N > 0 && (s = rom_eval_impl(c, smp, N, (double *)c->out.p))) return s;
+    HIP_TRY(c, ile_launch_reduce((const double *)c->out.p, lp, lq, N, (double *)c->red_tmp.p,
+                                 (double *)c->parts.p, c->stream));
+    HIP_TRY(c, ile_launch_finish((const double *)c->parts.p, 1, res, c->stream));
     return ILE_OK;
 }
 
@@ -1350,7 +1425,7 @@ void ile_destroy(ile_ctx *c)
                       &c->errflag, &c->red_tmp, &c->parts, &c->res, &c->series,
                       &c->hP, &c->hC, &c->bins, &c->hist_tmp, &c->trx, &c->trw,
                       &c->hv_w, &c->hv_cdf, &c->hv_ws, &c->hv_part, &c->hv_flag, &c->hv_sel,
-                      &c->fd_tmp, &c->fd_flag, &c->fd_in, &c->fd_out})
+                      &c->fd_tmp, &c->fd_flag, &c->fd_in, &c->fd_out, &c->rom_A, &c->rom_Z})
         release(*b);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);

@@ -34,6 +34,9 @@ struct ile_geom {
     double term_a[ILE_MAX_TERMS];
     signed char term_pc[ILE_MAX_TERMS];
     signed char term_ps[ILE_MAX_TERMS];
+    // surrogate form: per-sample vectors z [N][n_lm] used in place of -2Y_lm
+    // (the n_lm "modes" are then basis functions), or null
+    const double2 *ext_y;
 };
 
 // Device pointers of one intrinsic point of a batch.
@@ -153,6 +156,14 @@ hipError_t ile_launch_batch_lw(const double *lp, const double *lq, int64_t n_tot
                                int32_t *err, hipStream_t st);
 hipError_t ile_launch_to_bf16_split(const double *Q, int64_t n, void *dst,
                                     hipStream_t st);
+
+// ------------------------------------ surrogate (linear-basis) form
+// z_b = sum_lm c_lm,b(lambda) -2Y_lm(iota, phi) per joint sample (rows 0..6
+// extrinsic, row 7 lambda of smp [8][N]); gp holds the physical modes' Y
+// tables; A [n_lm][n_b][n_pow] complex; err bit 0 for lambda outside [-1, 1]
+// (z = NaN).
+hipError_t ile_launch_rom_z(const ile_geom &gp, const double *smp, int64_t N, const double *A,
+                            int n_b, int n_pow, double *Z, int32_t *err, hipStream_t st);
 
 // ------------------------------------ Q, U, V from the frequency domain
 // prod: X [n_det][n_lm][n] complex; err bit 0 for a non-finite input or a

@@ -145,6 +145,9 @@ def lib():
                                       C.c_double, C.c_double, C.POINTER(Detector), _dp, _dp, _dp]
         L.ile_qvu_fd_dev.argtypes = [_vp, _vp, _vp, _vp, C.c_int64, C.c_double, C.c_double,
                                      C.c_double, C.c_double, _vp, _vp, _vp]
+        L.ile_rom_set.argtypes = [_vp, C.POINTER(Mode), C.c_int32, C.c_int32, _dp]
+        L.ile_rom_eval_dev.argtypes = [_vp, _vp, C.c_int64, _vp]
+        L.ile_rom_integrate_dev.argtypes = [_vp, _vp, _vp, _vp, C.c_int64, _vp]
         L.ile_harvest_dev.argtypes = [_vp, _vp, _vp, _vp, C.c_int64, _vp, C.c_int64, _vp,
                                       _vp, _vp, _vp]
         L.ile_draw_prior_dev.argtypes = [_vp, C.c_uint64, C.c_int64, C.c_int64,
@@ -320,6 +323,24 @@ def ile_qvu_fd_dev(h, h_f_dev, d_f_dev, psd_dev, n_q, df, f_min, f_max, t0_s, Q_
     _check(lib().ile_qvu_fd_dev(h, _dev(h_f_dev), _dev(d_f_dev), _dev(psd_dev), int(n_q),
                                 float(df), float(f_min), float(f_max), float(t0_s),
                                 _dev(Q_dev), _dev(U_dev), _dev(V_dev)), h)
+
+
+def ile_rom_set(h, modes, A):
+    """Surrogate form (see ile.h): physical modes [(l, m)] and the complex
+    coefficient table A [n_lm][n_b][n_pow]."""
+    a = np.ascontiguousarray(A, np.complex128)
+    marr = (Mode * len(modes))(*[Mode(int(l), int(m)) for (l, m) in modes])
+    _check(lib().ile_rom_set(h, marr, len(modes), int(a.shape[2]),
+                             a.view(np.float64).ctypes.data_as(_dp)), h)
+
+
+def ile_rom_eval_dev(h, samples_dev, n, out_dev):
+    _check(lib().ile_rom_eval_dev(h, _dev(samples_dev), int(n), _dev(out_dev)), h)
+
+
+def ile_rom_integrate_dev(h, samples_dev, ln_p_dev, ln_q_dev, n, result_dev):
+    _check(lib().ile_rom_integrate_dev(h, _dev(samples_dev), _dev(ln_p_dev), _dev(ln_q_dev),
+                                       int(n), _dev(result_dev)), h)
 
 
 def ile_harvest_dev(h, samples_dev, ln_p_dev, ln_q_dev, n, u_dev, n_out, idx_dev,
