@@ -150,6 +150,47 @@ def learned_leg(target=1e4):
     return out
 
 
+def rom_leg(n=1_000_000, steps=5):
+    """Surrogate (linear-basis) form at the benchmark point's shape: its Q,
+    U, V as the overlaps of 21 basis functions, 21 physical modes, a seeded
+    cubic-in-lambda coefficient table; n joint samples (prior extrinsic draws
+    on the device, lambda uniform on [-1, 1]) evaluated and reduced in one
+    Monte Carlo over intrinsic and extrinsic parameters.  Reports the wall
+    time per step and the contraction's device time."""
+    import numpy as np
+    import torch
+    from paper_1902_04934_amd import ile, synth
+    basis = synth.config2()
+    rng = np.random.default_rng(91)
+    A = (rng.normal(size=(21, 21, 4)) + 1j * rng.normal(size=(21, 21, 4))) / 21
+    with ile.Context(basis) as ctx:
+        ile.ile_rom_set(ctx.h, synth.MODE_ORDER[:21], A)
+        X = torch.empty((8, n), dtype=torch.float64, device="cuda")
+        lp = torch.empty(n, dtype=torch.float64, device="cuda")
+        g = torch.Generator(device="cuda")
+        g.manual_seed(92)
+        X[7] = torch.rand(n, dtype=torch.float64, device="cuda", generator=g) * 2 - 1
+        torch.cuda.synchronize()
+        ctx.draw_prior_dev(93, 0, n, X, n, lp)
+        r = torch.empty(6, dtype=torch.float64, device="cuda")
+        ile.ile_rom_integrate_dev(ctx.h, X, lp, lp, n, r)
+        ctx.sync()
+        t0 = time.perf_counter()
+        kms = []
+        for _ in range(steps):
+            ile.ile_rom_integrate_dev(ctx.h, X, lp, lp, n, r)
+            ctx.sync()
+            kms.append(ctx.last_kernel_ms())
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        res = r.cpu().numpy()
+    return {"workload": f"surrogate form: 21 basis functions (Q 16384 points at 16384 Hz, 3 "
+                        f"detectors, {basis.n_t} bins), 21 physical modes, 4 powers of lambda, "
+                        f"{n} joint (lambda, theta) samples",
+            "ms_per_step": ms, "kernel_ms": sum(kms) / len(kms),
+            "evals_per_s": n * basis.n_t / (ms * 1e-3),
+            "ln_L_marg": float(res[0]), "n_eff": float(res[1])}
+
+
 def qvu_leg(steps=10):
     """Q, U, V built on the device from frequency-domain series at the
     benchmark point's shape (3 detectors, 21 modes, 16384-point grid at
@@ -371,6 +412,8 @@ def main():
                     help="skip the FP64/FP32/BF16 comparison on the same workload")
     ap.add_argument("--no-combined", action="store_true",
                     help="skip the combined-form leg (per-point learned proposals, batched)")
+    ap.add_argument("--no-rom", action="store_true",
+                    help="skip the surrogate (linear-basis) joint Monte Carlo leg")
     ap.add_argument("--no-qvu", action="store_true",
                     help="skip the frequency-domain Q, U, V construction leg")
     ap.add_argument("--no-reuse", action="store_true",
@@ -446,6 +489,7 @@ def main():
     out["harvest"] = None if args.no_harvest else harvest_leg(inst, n, seed)
     out["learned"] = None if args.no_learned else learned_leg()
     out["qvu"] = None if args.no_qvu else qvu_leg()
+    out["rom"] = None if args.no_rom else rom_leg()
     out["reuse"] = None if args.no_reuse else reuse_leg()
     out["combined"] = None if args.no_combined else combined_leg()
     if not args.no_cpu:

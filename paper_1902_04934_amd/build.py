@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libile.so")
 SOURCES = ["csrc/ile_kernels.hip", "csrc/ile_sampler.hip", "csrc/ile_batch.hip",
-           "csrc/ile_mdn.hip", "csrc/ile_harvest.hip", "csrc/ile_qvu.hip",
+           "csrc/ile_mdn.hip", "csrc/ile_harvest.hip", "csrc/ile_qvu.hip", "csrc/ile_rom.hip",
            "csrc/ile_api.cpp", "csrc/ile_batch_api.cpp", "csrc/ile_prop_api.cpp"]
 
 HIP_FLAGS = [

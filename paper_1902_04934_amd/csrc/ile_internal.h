@@ -77,6 +77,28 @@ __device__ inline uint32_t wave_count_slot(uint32_t *table, uint32_t key)
 // K steps of the matrix-core contraction (4 real rows = 2 modes each); the
 // device Q holds 4 * ksp_of(n_lm) rows per detector (rows 2a and 2a+1 = Re,
 // Im of mode a, the rest zero).
+__device__ inline double ipow(double x, int n)
+{
+    double r = 1.0;
+    for (int i = 0; i < n; i++) r *= x;
+    return r;
+}
+
+// -2Y_lm(iota, phi) of mode a from the per-mode Wigner-d term table.
+__device__ inline double2 sylm_dev(const ile_geom &g, int a, double cos_iota,
+                                   double phi)
+{
+    double c = sqrt(0.5 * (1.0 + cos_iota));   // cos(iota/2)
+    double s = sqrt(0.5 * (1.0 - cos_iota));   // sin(iota/2)
+    double sum = 0.0;
+    const int t0 = g.mode_first[a], nt = g.mode_nterm[a];
+    for (int t = t0; t < t0 + nt; t++)
+        sum += g.term_a[t] * ipow(c, g.term_pc[t]) * ipow(s, g.term_ps[t]);
+    double sm, cm;
+    sincos((double)g.mode_m[a] * phi, &sm, &cm);
+    return make_double2(sum * cm, sum * sm);
+}
+
 __host__ __device__ inline int ksp_of(int n_lm) { return (2 * n_lm + 3) / 4; }
 
 // K steps (32 rows each) of the BF16 hi/lo contraction: the rows are

@@ -77,28 +77,6 @@ __device__ inline void antenna_dev(const ile_geom &g, int k, double ra,
          (Y[0] * DX[0] + Y[1] * DX[1] + Y[2] * DX[2]);
 }
 
-__device__ inline double ipow(double x, int n)
-{
-    double r = 1.0;
-    for (int i = 0; i < n; i++) r *= x;
-    return r;
-}
-
-// -2Y_lm(iota, phi) of mode a from the per-mode Wigner-d term table.
-__device__ inline double2 sylm_dev(const ile_geom &g, int a, double cos_iota,
-                                   double phi)
-{
-    double c = sqrt(0.5 * (1.0 + cos_iota));   // cos(iota/2)
-    double s = sqrt(0.5 * (1.0 - cos_iota));   // sin(iota/2)
-    double sum = 0.0;
-    const int t0 = g.mode_first[a], nt = g.mode_nterm[a];
-    for (int t = t0; t < t0 + nt; t++)
-        sum += g.term_a[t] * ipow(c, g.term_pc[t]) * ipow(s, g.term_ps[t]);
-    double sm, cm;
-    sincos((double)g.mode_m[a] * phi, &sm, &cm);
-    return make_double2(sum * cm, sum * sm);
-}
-
 __host__ __device__ inline size_t prologue_scratch_bytes(int ts, int nd, int nl)
 {
     // s_th[7][ts], s_Y[ts][nl], s_F[ts][nd] (complex), s_qp[ts][nd*nl]
@@ -1488,50 +1466,6 @@ hipError_t ile_launch_contract_batched(ile_precision prec, const ile_tune &tu,
     if (tu.threads == 512) ILE_BATCHED(float, 512, ENG_VALU);
     ILE_BATCHED(float, 256, ENG_VALU);
 #undef ILE_BATCHED
-}
-
-namespace {
-// One thread per joint sample: Y_lm of the physical modes, the surrogate
-// coefficients c_lm,b(lambda) by Horner's rule, z_b = sum_lm c_lm,b Y_lm.
-__global__ __launch_bounds__(256) void k_rom_z(const ile_geom gp, const double *__restrict__ smp,
-                                               int64_t N, const double2 *__restrict__ A, int n_b,
-                                               int n_pow, double2 *__restrict__ Z, int32_t *err)
-{
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= N) return;
-    const double lam = smp[7 * N + i], ci = smp[4 * N + i], phi = smp[3 * N + i];
-    const int nl = gp.n_lm;
-    if (!(lam >= -1.0 && lam <= 1.0) || !(ci >= -1.0 && ci <= 1.0) || !isfinite(phi)) {
-        atomicOr(err, 1);
-        for (int b = 0; b < n_b; b++) Z[i * n_b + b] = make_double2(NAN, NAN);
-        return;
-    }
-    double2 Y[ILE_MAX_LM];
-    for (int a = 0; a < nl; a++) Y[a] = sylm_dev(gp, a, ci, phi);
-    for (int b = 0; b < n_b; b++) {
-        double zx = 0.0, zy = 0.0;
-        for (int a = 0; a < nl; a++) {
-            const double2 *Ab = A + ((int64_t)a * n_b + b) * n_pow;
-            double cx = Ab[n_pow - 1].x, cy = Ab[n_pow - 1].y;
-            for (int p = n_pow - 2; p >= 0; p--) {
-                cx = cx * lam + Ab[p].x;
-                cy = cy * lam + Ab[p].y;
-            }
-            zx += cx * Y[a].x - cy * Y[a].y;
-            zy += cx * Y[a].y + cy * Y[a].x;
-        }
-        Z[i * n_b + b] = make_double2(zx, zy);
-    }
-}
-}  // namespace
-
-hipError_t ile_launch_rom_z(const ile_geom &gp, const double *smp, int64_t N, const double *A,
-                            int n_b, int n_pow, double *Z, int32_t *err, hipStream_t st)
-{
-    if (N <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rom_z, dim3(nblk(N, 256)), dim3(256), 0, st, gp, smp, N,
-                       (const double2 *)A, n_b, n_pow, (double2 *)Z, err);
-    return hipGetLastError();
 }
 
 hipError_t ile_launch_prior(uint64_t seed, int64_t first, int64_t N,
