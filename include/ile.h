@@ -9,6 +9,13 @@
  * block of extrinsic samples theta_alpha the library evaluates Eq. (7) on a
  * grid of n_t time bins, marginalizes over time (Eq. (9)) and reduces the
  * importance-weighted samples to ln L_marg (Eq. (4)) and n_eff (Sec. II.C).
+ * Around that path: Q, U, V built on the device from frequency-domain
+ * series (ile_set_data_fd, Eq. (2) and Eq. (8)); the adaptive and learned
+ * samplers (ile_run) with reuse from one intrinsic point to the next; the
+ * batched form for many points (ile_batch_*); joint extrinsic posterior
+ * draws from a final iteration (ile_harvest_dev, Sec. V); and the surrogate
+ * form, one Monte Carlo over intrinsic and extrinsic parameters
+ * (ile_rom_*, Sec. V).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
