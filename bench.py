@@ -11,7 +11,7 @@ Workload (default): 3 detectors, 21 modes (l = 2..4), Q of 16384 complex
 points at 16384 Hz, 1e6 prior samples, 1601 time bins, FP64 -- the plain
 at-scale single-point configuration.  Synthetic data (seeded stand-ins).
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the benchmark runs on one GPU.
 """
 import argparse
 import json
@@ -425,7 +425,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch

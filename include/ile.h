@@ -82,7 +82,7 @@ typedef enum {
     ILE_E_NUMERIC = 4,     /* non-finite Q/U/V, or U not Hermitian            */
     ILE_E_DEVICE = 5,      /* HIP runtime error or no usable GPU              */
     ILE_E_NOMEM = 6,       /* device allocation failed                        */
-    ILE_E_UNSUPPORTED = 7  /* valid request this build does not support       */
+    ILE_E_UNSUPPORTED = 7  /* valid request the library does not support      */
 } ile_status;
 
 typedef enum { ILE_FP64 = 0, ILE_FP32 = 1, ILE_BF16 = 2 } ile_precision;
