@@ -150,8 +150,8 @@ ile_status ile_set_data(ile_ctx *ctx, const double *Q, int64_t n_q,
  * transforms on the same clock; psd: host double [n_det][n_q], S_k at
  * |f_i|, positive and finite inside the band.  The band is open; f_min < 0
  * includes f = 0.  Q takes one inverse FFT per (detector, mode) row on the
- * device (FP64, radix-4 self-sorting passes).  n_q must be a power of two in
- * [2, 2^24] (ILE_E_UNSUPPORTED otherwise).  Q_out, U_out, V_out (may be
+ * device (FP64; in LDS, the four-step form above 1024 points).  n_q must be a power of two in
+ * [2, 2^20] (ILE_E_UNSUPPORTED otherwise).  Q_out, U_out, V_out (may be
  * NULL) receive host copies in ile_set_data's layouts.  Errors:
  * ILE_E_ARG for NULL inputs, df <= 0, f_max <= f_min or a non-finite t0_s;
  * ILE_E_NUMERIC for a non-finite input or a bad spectrum in the band; then

@@ -635,8 +635,8 @@ ile_status ile_qvu_fd_dev(ile_ctx *c, const double *h_f, const double *d_f, cons
     HIP_TRY(c, hipSetDevice(c->cfg.device));
     begin_call(c);
     if (!h_f || !d_f || !psd || !Q || !U || !V) return fail(c, ILE_E_ARG, "null pointer");
-    if (n_q < 2 || n_q > ((int64_t)1 << 24) || (n_q & (n_q - 1)))
-        return fail(c, ILE_E_UNSUPPORTED, "n_q = %lld is not a power of two in [2, 2^24]",
+    if (n_q < 2 || n_q > ((int64_t)1 << 20) || (n_q & (n_q - 1)))
+        return fail(c, ILE_E_UNSUPPORTED, "n_q = %lld is not a power of two in [2, 2^20]",
                     (long long)n_q);
     if (!(df > 0) || !std::isfinite(df) || !std::isfinite(t0_s) || std::isnan(f_min) ||
         std::isnan(f_max) || !(f_max > f_min))
@@ -648,7 +648,7 @@ ile_status ile_qvu_fd_dev(ile_ctx *c, const double *h_f, const double *d_f, cons
     hipStream_t st = c->stream;
     int32_t *flag = (int32_t *)c->fd_flag.p;
     // the inverse FFT ends in Q: start in the scratch buffer when the number
-    // of passes (radix-4, plus one radix-2 for odd log2 n_q) is odd
+    // of its kernels (one for n_q <= 1024, else two) is odd
     const bool odd = ile_fft_passes(n_q) & 1;
     double *a = odd ? (double *)c->fd_tmp.p : Q, *b = odd ? Q : (double *)c->fd_tmp.p, *res = nullptr;
     HIP_TRY(c, hipMemsetAsync(flag, 0, sizeof(int32_t), st));
@@ -679,8 +679,8 @@ ile_status ile_set_data_fd(ile_ctx *c, const double *h_f, const double *d_f, con
     HIP_TRY(c, hipSetDevice(c->cfg.device));
     begin_call(c);
     if (!h_f || !d_f || !psd || !dets) return fail(c, ILE_E_ARG, "null pointer");
-    if (n_q < 2 || n_q > ((int64_t)1 << 24) || (n_q & (n_q - 1)))
-        return fail(c, ILE_E_UNSUPPORTED, "n_q = %lld is not a power of two in [2, 2^24]",
+    if (n_q < 2 || n_q > ((int64_t)1 << 20) || (n_q & (n_q - 1)))
+        return fail(c, ILE_E_UNSUPPORTED, "n_q = %lld is not a power of two in [2, 2^20]",
                     (long long)n_q);
     const int nd = c->cfg.n_det, nl = c->cfg.n_lm;
     const size_t nh = (size_t)2 * nl * n_q, ndd = (size_t)2 * nd * n_q, np_ = (size_t)nd * n_q;

@@ -4,10 +4,11 @@
 //
 //   k_fd_prod   X_k,lm,i = 2 df / S_k,i conj(h_lm,i) d_k,i exp(2 pi i f_i t0)
 //               (0 outside f_min < |f_i| < f_max)
-//   k_fft_pass4 one radix-4 pass of a self-sorting (Stockham) inverse FFT
-//               over all n_det n_lm rows (k_fft_pass: one radix-2 pass
-//               first when log2 n is odd): Q_k,lm[s] = sum_i X_k,lm,i
-//               exp(2 pi i i s / n), i.e. Q at t0 + s / (n df)
+//   k_fft_row   inverse FFT of one row in LDS (n <= 1024), or for larger
+//   k_fft_a/c   n = N1 N2 the four-step form: N1 transforms of length N2 over
+//               strided columns, a twiddle, N2 transforms of length N1; each
+//               transform self-sorting radix-2 passes in LDS:
+//               Q_k,lm[s] = sum_i X_k,lm,i exp(2 pi i i s / n), Q at t0 + s / (n df)
 //   k_uv        U_k[a][b] = sum_i w_k,i conj(h_a,i) h_b,i and
 //               V_k[a][b] = sum_i w_k,i h_a,-i h_b,i (w = 2 df / S in the
 //               band), one workgroup per (k, a, b), fixed-order reduction
@@ -15,7 +16,7 @@
 
 #include <math.h>
 
-#include <utility>
+#include <algorithm>
 
 namespace {
 
@@ -68,54 +69,105 @@ __global__ __launch_bounds__(FD_T) void k_fd_prod(const double2 *__restrict__ h,
     if (bad) atomicOr(err, 1);
 }
 
-// Pass with current sub-transform length len and stride s = n / len: for
-// t = p s + q (p < len/2, q < s), a = x[q + s p], b = x[q + s (p + len/2)],
-// y[q + 2 s p] = a + b, y[q + s (2p + 1)] = (a - b) exp(2 pi i p / len).
-__global__ __launch_bounds__(FD_T) void k_fft_pass(const double2 *__restrict__ x,
-                                                   double2 *__restrict__ y, int64_t n,
-                                                   int64_t len, int64_t s)
+// Inverse DFT (unnormalized, exp(+2 pi i jk/L)) of nb sequences of length L
+// held at a + q L, by self-sorting radix-2 passes ping-ponging between a and
+// b (pass with sub-length len, stride st = L / len: for t = p st + q',
+// u = a[q' + st p], v = a[q' + st (p + len/2)], b[q' + 2 st p] = u + v,
+// b[q' + st (2p + 1)] = (u - v) exp(2 pi i p / len)).  tw[j] = exp(2 pi i j / L)
+// for j < L/2 (exp(2 pi i p / len) = tw[p st], the same value).  Returns the
+// buffer holding the result.  Every thread of the block must call it.
+__device__ inline void lds_twiddles(double2 *tw, int L)
 {
-    const int64_t t = (int64_t)blockIdx.x * FD_T + threadIdx.x;
-    if (t >= n / 2) return;
-    const int64_t row = (int64_t)blockIdx.y * n;
-    const int64_t p = t / s, q = t - p * s, half = len / 2;
-    const double2 a = x[row + q + s * p], b = x[row + q + s * (p + half)];
-    double sn, cs;
-    sincospi(2.0 * (double)p / (double)len, &sn, &cs);
-    const double dx = a.x - b.x, dy = a.y - b.y;
-    y[row + q + s * 2 * p] = make_double2(a.x + b.x, a.y + b.y);
-    y[row + q + s * (2 * p + 1)] = make_double2(dx * cs - dy * sn, dx * sn + dy * cs);
+    for (int j = threadIdx.x; j < L / 2; j += FD_T) {
+        double sn, cs;
+        sincospi(2.0 * (double)j / (double)L, &sn, &cs);
+        tw[j] = make_double2(cs, sn);
+    }
 }
 
-// Radix-4 pass, sub-transform length len, stride s = n / len: for
-// t = p s + q (p < len/4), a_j = x[q + s (p + j len/4)], and with
-// b0 = a0 + a2, b1 = a0 - a2, b2 = a1 + a3, b3 = i (a1 - a3), w = exp(2 pi i p / len):
-// y[q + s 4p] = b0 + b2, y[q + s (4p+1)] = (b1 + b3) w,
-// y[q + s (4p+2)] = (b0 - b2) w^2, y[q + s (4p+3)] = (b1 - b3) w^3.
-__global__ __launch_bounds__(FD_T) void k_fft_pass4(const double2 *__restrict__ x,
-                                                    double2 *__restrict__ y, int64_t n,
-                                                    int64_t len, int64_t s)
+__device__ double2 *lds_ifft(double2 *a, double2 *b, const double2 *tw, int nb, int L)
 {
-    const int64_t t = (int64_t)blockIdx.x * FD_T + threadIdx.x;
-    if (t >= n / 4) return;
+    const int hl = L / 2, tot = nb * hl;
+    for (int len = L, st = 1; len > 1; len >>= 1, st <<= 1) {
+        for (int t = threadIdx.x; t < tot; t += FD_T) {
+            const int sq = t / hl, w = t - sq * hl;
+            const int p = w / st, q = w - p * st;
+            const double2 *x = a + sq * L;
+            double2 *y = b + sq * L;
+            const double2 u = x[q + st * p], v = x[q + st * (p + len / 2)];
+            const double cs = tw[p * st].x, sn = tw[p * st].y;
+            const double dx = u.x - v.x, dy = u.y - v.y;
+            y[q + st * 2 * p] = make_double2(u.x + v.x, u.y + v.y);
+            y[q + st * (2 * p + 1)] = make_double2(dx * cs - dy * sn, dx * sn + dy * cs);
+        }
+        __syncthreads();
+        double2 *tmp = a;
+        a = b;
+        b = tmp;
+    }
+    return a;
+}
+
+// one workgroup per row, the whole row in LDS (n <= 1024)
+__global__ __launch_bounds__(FD_T) void k_fft_row(const double2 *__restrict__ x,
+                                                  double2 *__restrict__ y, int n)
+{
+    extern __shared__ double2 sh[];
+    const int64_t row = (int64_t)blockIdx.x * n;
+    for (int e = threadIdx.x; e < n; e += FD_T) sh[e] = x[row + e];
+    lds_twiddles(sh + 2 * n, n);
+    __syncthreads();
+    const double2 *r = lds_ifft(sh, sh + n, sh + 2 * n, 1, n);
+    for (int e = threadIdx.x; e < n; e += FD_T) y[row + e] = r[e];
+}
+
+// Four-step, first half: columns i1 in [c0, c0 + B) of the N1 x N2 view
+// x[i1 + N1 i2]; transform over i2, twiddle exp(2 pi i i1 s2 / n), store
+// t[s2 N1 + i1] (B consecutive i1: contiguous).
+__global__ __launch_bounds__(FD_T) void k_fft_a(const double2 *__restrict__ x,
+                                                double2 *__restrict__ t, int64_t n, int N1,
+                                                int N2, int B)
+{
+    extern __shared__ double2 sh[];
     const int64_t row = (int64_t)blockIdx.y * n;
-    const int64_t p = t / s, q = t - p * s, m = len / 4;
-    const double2 a0 = x[row + q + s * p], a1 = x[row + q + s * (p + m)],
-                  a2 = x[row + q + s * (p + 2 * m)], a3 = x[row + q + s * (p + 3 * m)];
-    const double b0x = a0.x + a2.x, b0y = a0.y + a2.y, b1x = a0.x - a2.x, b1y = a0.y - a2.y;
-    const double b2x = a1.x + a3.x, b2y = a1.y + a3.y;
-    const double b3x = -(a1.y - a3.y), b3y = a1.x - a3.x;   // i (a1 - a3)
-    const double fp = (double)p / (double)len;
-    double s1, c1, s2, c2, s3, c3;
-    sincospi(2.0 * fp, &s1, &c1);
-    sincospi(4.0 * fp, &s2, &c2);
-    sincospi(6.0 * fp, &s3, &c3);
-    const double u1x = b1x + b3x, u1y = b1y + b3y, u2x = b0x - b2x, u2y = b0y - b2y;
-    const double u3x = b1x - b3x, u3y = b1y - b3y;
-    y[row + q + s * 4 * p] = make_double2(b0x + b2x, b0y + b2y);
-    y[row + q + s * (4 * p + 1)] = make_double2(u1x * c1 - u1y * s1, u1x * s1 + u1y * c1);
-    y[row + q + s * (4 * p + 2)] = make_double2(u2x * c2 - u2y * s2, u2x * s2 + u2y * c2);
-    y[row + q + s * (4 * p + 3)] = make_double2(u3x * c3 - u3y * s3, u3x * s3 + u3y * c3);
+    const int c0 = blockIdx.x * B;
+    for (int e = threadIdx.x; e < B * N2; e += FD_T) {
+        const int b = e % B, i2 = e / B;
+        sh[b * N2 + i2] = x[row + c0 + b + (int64_t)N1 * i2];
+    }
+    lds_twiddles(sh + 2 * B * N2, N2);
+    __syncthreads();
+    const double2 *r = lds_ifft(sh, sh + B * N2, sh + 2 * B * N2, B, N2);
+    for (int e = threadIdx.x; e < B * N2; e += FD_T) {
+        const int b = e % B, s2 = e / B;
+        const int64_t i1 = c0 + b;
+        const double2 z = r[b * N2 + s2];
+        double sn, cs;
+        sincospi(2.0 * (double)((i1 * s2) % n) / (double)n, &sn, &cs);
+        t[row + (int64_t)s2 * N1 + i1] = make_double2(z.x * cs - z.y * sn, z.x * sn + z.y * cs);
+    }
+}
+
+// Four-step, second half: rows s2 in [d0, d0 + B) of t (contiguous over
+// i1); transform over i1 and store y[s2 + N2 s1].
+__global__ __launch_bounds__(FD_T) void k_fft_c(const double2 *__restrict__ t,
+                                                double2 *__restrict__ y, int64_t n, int N1,
+                                                int N2, int B)
+{
+    extern __shared__ double2 sh[];
+    const int64_t row = (int64_t)blockIdx.y * n;
+    const int d0 = blockIdx.x * B;
+    for (int e = threadIdx.x; e < B * N1; e += FD_T) {
+        const int i1 = e % N1, b = e / N1;
+        sh[b * N1 + i1] = t[row + (int64_t)(d0 + b) * N1 + i1];
+    }
+    lds_twiddles(sh + 2 * B * N1, N1);
+    __syncthreads();
+    const double2 *r = lds_ifft(sh, sh + B * N1, sh + 2 * B * N1, B, N1);
+    for (int e = threadIdx.x; e < B * N1; e += FD_T) {
+        const int b = e % B, s1 = e / B;
+        y[row + d0 + b + (int64_t)N2 * s1] = r[b * N1 + s1];
+    }
 }
 
 __global__ __launch_bounds__(FD_T) void k_uv(const double2 *__restrict__ h,
@@ -167,33 +219,37 @@ hipError_t ile_launch_fd_prod(const double *h, const double *d, const double *ps
     return hipGetLastError();
 }
 
+// 1024 complex doubles per transform batch: 2 x 16 KB of LDS (ping-pong)
+// plus the twiddle table (at most 8 KB), within 64 KB per workgroup; the
+// four-step form then reaches n = 1024^2 = 2^20
+constexpr int FFT_LDS = 1024;
+
 int ile_fft_passes(int64_t n)
 {
-    int p = 0;
-    while (((int64_t)1 << p) < n) p++;
-    return (p & 1) + p / 2;   // one radix-2 pass if log2 n is odd, then radix-4
+    return n <= FFT_LDS ? 1 : 2;   // kernels, each reading one buffer and writing the other
 }
 
 hipError_t ile_launch_ifft_rows(double *a, double *b, int64_t n, int rows, double **result,
                                 hipStream_t st)
 {
-    double2 *x = (double2 *)a, *y = (double2 *)b;
-    int64_t len = n, s = 1;
+    const double2 *x = (const double2 *)a;
+    double2 *y = (double2 *)b;
+    if (n <= FFT_LDS) {
+        hipLaunchKernelGGL(k_fft_row, dim3(rows), dim3(FD_T), (2 * n + n / 2) * sizeof(double2), st,
+                           x, y, (int)n);
+        *result = b;
+        return hipGetLastError();
+    }
     int lg = 0;
     while (((int64_t)1 << lg) < n) lg++;
-    if (lg & 1) {
-        hipLaunchKernelGGL(k_fft_pass, dim3((unsigned)((n / 2 + FD_T - 1) / FD_T), rows),
-                           dim3(FD_T), 0, st, (const double2 *)x, y, n, len, s);
-        std::swap(x, y);
-        len >>= 1;
-        s <<= 1;
-    }
-    for (; len > 1; len >>= 2, s <<= 2) {
-        hipLaunchKernelGGL(k_fft_pass4, dim3((unsigned)((n / 4 + FD_T - 1) / FD_T), rows),
-                           dim3(FD_T), 0, st, (const double2 *)x, y, n, len, s);
-        std::swap(x, y);
-    }
-    *result = (double *)x;
+    const int N2 = 1 << (lg / 2), N1 = (int)(n / N2);   // both <= 1024 for n <= 2^20
+    const int BA = std::min(16, FFT_LDS / N2), BC = std::min(16, FFT_LDS / N1);
+    hipLaunchKernelGGL(k_fft_a, dim3(N1 / BA, rows), dim3(FD_T),
+                       (2 * BA * N2 + N2 / 2) * sizeof(double2), st, x, y, n, N1, N2, BA);
+    hipLaunchKernelGGL(k_fft_c, dim3(N2 / BC, rows), dim3(FD_T),
+                       (2 * BC * N1 + N1 / 2) * sizeof(double2), st, (const double2 *)y, (double2 *)a,
+                       n, N1, N2, BC);
+    *result = a;
     return hipGetLastError();
 }
 

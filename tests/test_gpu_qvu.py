@@ -81,6 +81,17 @@ def test_fd_build_matches_oracle(torch, orc, n_q, f_min, f_max, t0):
     print(n_q, _check(orc, c, Q, U, V, f_min, f_max, t0))
 
 
+@pytest.mark.parametrize("n_q", [1024, 2048, 4096, 8192, 32768])
+def test_fd_lds_and_four_step_sizes(torch, orc, n_q):
+    """The single-workgroup transform at its largest size (1024) and the
+    four-step form with square and oblong factorizations, 64 sampled lags."""
+    c = synth.fd_inputs(["D1", "D2"], 3, n_q, float(n_q), 631 + n_q)
+    with _Handle(c) as ctx:
+        Q, U, V, _ = _dev_build(torch, ctx, c, 8.0, 0.4 * n_q, -0.3)
+    s = np.random.default_rng(n_q).choice(n_q, 64, replace=False)
+    print(n_q, _check(orc, c, Q, U, V, 8.0, 0.4 * n_q, -0.3, s))
+
+
 def test_fd_full_size_sampled(torch, orc):
     """21 modes, 3 detectors, 16384 lags at 16384 Hz, band 20-4000 Hz."""
     c = synth.fd_inputs(["D1", "D2", "D3"], 21, 16384, 16384.0, 611)
