@@ -150,6 +150,38 @@ def learned_leg(target=1e4):
     return out
 
 
+def batched_leg(n_points=256, n=200_000, steps=3, seed=11):
+    """The batched form on its workload: 256 intrinsic points with 5, 9, 13 or
+    21 modes and 201-1601 bins (by seed), 3 detectors, Q 16384 points in
+    FP32, 2e5 prior samples per point, one graph-captured persistent run
+    (draw, order, sort, contraction, per-point reduction) at the default
+    tuning.  Reports the graph's device time (HIP events) and wall time per
+    run, and the throughput in sample x bin per second."""
+    from paper_1902_04934_amd import ile, synth
+    t0 = time.perf_counter()
+    pts = [synth.batched_point(p) for p in range(n_points)]
+    t_gen = time.perf_counter() - t0
+    work = n * sum(p.n_t for p in pts)
+    with ile.Batch("fp32") as b:
+        for inst in pts:
+            b.add_point(inst)
+        b.run(seed, n)
+        t0 = time.perf_counter()
+        gms = []
+        for _ in range(steps):
+            res = b.run(seed, n)
+            gms.append(b.last_ms())
+        wall = 1e3 * (time.perf_counter() - t0) / steps
+        tune = b.get_tuning()
+    g = sum(gms) / len(gms)
+    return {"workload": f"{n_points} points (3 detectors, 5-21 modes, 201-1601 bins, Q 16384 "
+                        f"points FP32), {n} prior samples each, one persistent graph",
+            "graph_ms": g, "wall_ms_per_run": wall, "sample_bins_per_s": work / (g * 1e-3),
+            "samples_per_s": n * n_points / (g * 1e-3), "tuning": tune,
+            "input_generation_s": t_gen,
+            "n_eff_min": min(r["n_eff"] for r in res)}
+
+
 def rom_leg(n=1_000_000, steps=5):
     """Surrogate (linear-basis) form at the benchmark point's shape: its Q,
     U, V as the overlaps of 21 basis functions, 21 physical modes, a seeded
@@ -412,6 +444,8 @@ def main():
                     help="skip the FP64/FP32/BF16 comparison on the same workload")
     ap.add_argument("--no-combined", action="store_true",
                     help="skip the combined-form leg (per-point learned proposals, batched)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched form on its 256-point workload")
     ap.add_argument("--no-rom", action="store_true",
                     help="skip the surrogate (linear-basis) joint Monte Carlo leg")
     ap.add_argument("--no-qvu", action="store_true",
@@ -490,6 +524,7 @@ def main():
     out["learned"] = None if args.no_learned else learned_leg()
     out["qvu"] = None if args.no_qvu else qvu_leg()
     out["rom"] = None if args.no_rom else rom_leg()
+    out["batched"] = None if args.no_batched else batched_leg()
     out["reuse"] = None if args.no_reuse else reuse_leg()
     out["combined"] = None if args.no_combined else combined_leg()
     if not args.no_cpu:
