@@ -80,3 +80,33 @@ def test_batch_autotune_and_cache(torch, points, tmp_path):
             b2.add_point(inst)
         assert b2.autotune(1000, cache) == t            # read from the cache
         assert len(open(cache).read().splitlines()) == 1
+
+
+def test_batch_full_size_sampled(torch):
+    """The batched workload at full size in the benchmark's launch
+    configuration (256 points, Q 16384 points in FP32, 2e5 prior samples per
+    point, default tuning): 64 sampled samples of every 16th point against
+    the FP64 oracle (1e-4 relative, the FP32 bar), and ln L_marg of three
+    points against the oracle's reduction of all their samples (1e-3)."""
+    from oracle import oracle as O
+    pts = [synth.batched_point(p) for p in range(256)]
+    n, seed = 200_000, 11
+    with ile.Batch("fp32") as b:
+        for inst in pts:
+            b.add_point(inst)
+        res = b.run(seed, n)
+        lnl = b.lnL(n)
+    rng = np.random.default_rng(5)
+    worst = 0.0
+    for p in range(0, 256, 16):
+        s, lp = O.prior_draw(seed + p, 0, n)
+        idx = rng.choice(n, 64, replace=False)
+        want = O.Ctx(pts[p]).eval(s[:, idx])
+        err = np.abs(lnl[p][idx] - want) / np.maximum(1.0, np.abs(want))
+        worst = max(worst, float(err.max()))
+        assert err.max() <= 1e-4, (p, pts[p].n_lm, pts[p].n_t, err.max())
+    for p in (0, 100, 255):
+        s, lp = O.prior_draw(seed + p, 0, n)
+        ref = O.integrate(O.Ctx(pts[p]).eval(s), lp, lp)
+        assert abs(res[p]["ln_L_marg"] - ref["ln_L_marg"]) <= 1e-3
+    print(f"batched full size: sampled max rel err {worst:.2e}")
