@@ -128,3 +128,23 @@ def test_rom_errors(torch, case):
         # the context recovers
         got = _run(torch, ctx, s8[:, :10])
         assert np.all(np.isfinite(got))
+
+
+def test_rom_table_beyond_lds(torch, orc):
+    """32 physical modes (l = 2..5), 21 basis functions and 8 powers of
+    lambda: the coefficient table (86 KB) does not fit the 64 KB staging
+    limit, so k_rom_z reads it from global memory."""
+    basis = synth.make_instance(["D1", "D2", "D3"], 21, 4096, 4096.0, 201, 86)
+    modes = [(l, m) for l in range(2, 6) for m in range(-l, l + 1)]
+    assert len(modes) == 32
+    rng = np.random.default_rng(87)
+    A = (rng.normal(size=(32, 21, 8)) + 1j * rng.normal(size=(32, 21, 8))) / 32
+    s, _ = synth.prior_samples(300, 88)
+    s8 = np.vstack([s, rng.uniform(-1, 1, (1, 300))])
+    with ile.Context(basis) as ctx:
+        ile.ile_rom_set(ctx.h, modes, A)
+        got = _run(torch, ctx, s8)
+    want = orc.rom_eval(basis, modes, A, s8)
+    err = np.abs(got - want).max()
+    print(f"rom, table in global memory: max err {err:.3e}")
+    assert err <= 1e-9
