@@ -153,3 +153,20 @@ def test_fd_errors(torch):
             ile.ile_set_data_fd(ctx.h, c3["h_f"], c3["d_f"], c3["psd"], c3["df"], 5.0, 30.0,
                                 0.0, c3["dets"])
         assert e.value.status == ile.ILE_E_UNSUPPORTED
+
+
+def test_fd_largest_shapes(torch, orc):
+    """Four detectors and 32 modes (the library's limits) on a 2048-point
+    grid: every lag, U and V against the oracle."""
+    n = 2048
+    rng = np.random.default_rng(641)
+    modes = [(l, m) for l in range(2, 6) for m in range(-l, l + 1)]
+    dets = [synth.DETECTORS[d] for d in ("D1", "D2", "D3")] + [(36.4, 137.3, 15.0)]
+    f = np.abs(np.where(np.arange(n) < n // 2, np.arange(n), np.arange(n) - n)) * 1.0
+    c = dict(dets=dets, modes=modes, srate_hz=float(n), n_q=n, df=1.0,
+             h_f=(rng.normal(size=(32, n)) + 1j * rng.normal(size=(32, n))) / np.sqrt(1 + f / 50),
+             d_f=rng.normal(size=(4, n)) + 1j * rng.normal(size=(4, n)),
+             psd=np.stack([0.5 + 1e-4 * f ** 2 * (k + 1) for k in range(4)]))
+    with _Handle(c) as ctx:
+        Q, U, V, _ = _dev_build(torch, ctx, c, 10.0, 900.0, -0.25)
+    print("4 x 32:", _check(orc, c, Q, U, V, 10.0, 900.0, -0.25))
