@@ -254,3 +254,15 @@ def test_harvest_edge_cases(torch, orc):
             assert np.array_equal(x, y)
         lnL = orc.Ctx(inst).eval(s)
         check_samples(orc, s, lp, lq, lnL, u[0], a[0])
+
+
+def test_harvest_single_bin(torch, orc):
+    """n_t = 1: every draw takes bin 0 and keeps its sample's t_ref; the
+    sample picks still follow the oracle."""
+    inst = synth.make_instance(["D1", "D2"], 3, 1024, 1024.0, 1, 541)
+    s, lp, lq, u = _inputs(90, 542, 40)
+    with ile.Context(inst) as ctx:
+        idx, bins, theta = run_harvest(torch, ctx, s, lp, lq, u)
+    assert np.all(bins == 0)
+    assert np.array_equal(theta, s[:, idx])
+    check_samples(orc, s, lp, lq, orc.Ctx(inst).eval(s), u[0], idx)
