@@ -13,9 +13,10 @@
 //   k_hv_pick  sample index per draw (binary search of the cumulative sums;
 //              u is [2][n_out], both rows are checked here)
 //   k_hv_gather  the chosen samples, packed, for the per-bin evaluation
-//   k_hv_bin   one wave per draw: the bin by a chunked wave scan of
-//              exp(L_j - max L), and the harvested parameters (the row in
-//              registers up to 2048 bins, streamed above)
+//   k_hv_bin   one wave per draw: the bin from the cumulative sums of
+//              exp(L_j - max L), and the harvested parameters (k_hv_bin_seg
+//              up to 2048 bins: row in registers, lane-owned segments in
+//              LDS; above, k_hv_bin streams the row with chunked wave scans)
 #include "ile_internal.h"
 
 #include <math.h>
@@ -194,60 +195,81 @@ __global__ __launch_bounds__(HV_T) void k_hv_bin(const double *__restrict__ seri
     if (lane == 0) bins[r] = jsel;
 }
 
-// The same pick with the row held in registers (n_t <= 64 NC): one read of
-// the row, one exp per bin; the chunked scan and the two searches are those
-// of k_hv_bin.
+// Segment form of the pick (n_t <= 64 NC): the row is read once into
+// registers, its weights exp(L_j - M) go through the wave's own LDS region
+// so that lane l owns the contiguous bins [l S, (l + 1) S), S = ceil(n_t /
+// 64).  Each lane sums its segment in order (T_l); a wave scan gives the
+// offsets E_l; the cumulative weight of bin j = l S + k is E_l + (sum of the
+// segment's first k + 1 weights), which at a segment's end is E_l + T_l, and
+// the total is that of the last lane.  The first lane whose segment end
+// exceeds the target scans its segment for the bin (when rounding leaves no
+// such lane, the first bin reaching the total).  Two dependent passes of S
+// steps and one 6-step scan, where k_hv_bin chains a scan per 64-bin chunk.
+__device__ inline void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int NC>
-__global__ __launch_bounds__(HV_T) void k_hv_bin_reg(const double *__restrict__ series, int64_t m,
+__global__ __launch_bounds__(HV_T) void k_hv_bin_seg(const double *__restrict__ series, int64_t m,
                                                      int n_t, const double *__restrict__ v,
                                                      const double *__restrict__ sel, double srate,
                                                      int32_t *__restrict__ bins,
                                                      double *__restrict__ theta, int64_t ld_out)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.x * (HV_T / 64) + (threadIdx.x >> 6);
-    if (r >= m) return;   // whole waves leave together
+    extern __shared__ double hv_seg[];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t r = (int64_t)blockIdx.x * (HV_T / 64) + wv;
+    if (r >= m) return;   // whole waves; each uses only its own LDS region
+    const int S = (n_t + 63) >> 6;
+    double *e = hv_seg + wv * 64 * S;
     const double *L = series + r * n_t;
-    const int nch = (n_t + 63) >> 6;
     double x[NC];
     double M = -INFINITY;
 #pragma unroll
     for (int c = 0; c < NC; c++) {
         const int j = c * 64 + lane;
-        x[c] = (c < nch && j < n_t) ? L[j] : -INFINITY;
+        x[c] = (c < S && j < n_t) ? L[j] : -INFINITY;
         M = fmax(M, x[c]);
     }
     M = wave_max_d(M);
-    double run = 0.0;
 #pragma unroll
     for (int c = 0; c < NC; c++) {
-        if (c < nch) {
-            const int j = c * 64 + lane;
-            double e = j < n_t ? exp(x[c] - M) : 0.0;
-            for (int o = 1; o < 64; o <<= 1) {
-                const double y = __shfl_up(e, o, 64);
-                if (lane >= o) e += y;
+        const int j = c * 64 + lane;
+        if (c < S) e[j] = j < n_t ? exp(x[c] - M) : 0.0;
+    }
+    wave_sync_lds();
+    const double *mine = e + lane * S;
+    double T = 0.0;
+    for (int k = 0; k < S; k++) T += mine[k];
+    double P = T;   // inclusive scan over lanes
+    for (int o = 1; o < 64; o <<= 1) {
+        const double y = __shfl_up(P, o, 64);
+        if (lane >= o) P += y;
+    }
+    double E = __shfl_up(P, 1, 64);
+    if (lane == 0) E = 0.0;
+    const double end = E + T;
+    const double tot = __shfl(end, 63, 64), target = v[r] * tot;
+    uint64_t hit = __ballot(end > target);
+    const bool reach = hit == 0;   // rounding left the target at the total
+    if (reach) hit = __ballot(end >= tot);
+    const int owner = __builtin_ctzll(hit);
+    int jl = 0;
+    if (lane == owner) {
+        double q = 0.0;
+        for (int k = 0; k < S; k++) {
+            q += mine[k];
+            const double cj = E + q;
+            if (reach ? cj >= tot : cj > target) {
+                jl = lane * S + k;
+                break;
             }
-            x[c] = run + e;
-            run += __shfl(e, 63, 64);
         }
     }
-    const double tot = run, target = v[r] * tot;
-    int jsel = -1;
-#pragma unroll
-    for (int c = 0; c < NC; c++) {
-        if (c < nch && jsel < 0) {
-            const uint64_t hit = __ballot(c * 64 + lane < n_t && x[c] > target);
-            if (hit) jsel = c * 64 + __builtin_ctzll(hit);
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < NC; c++) {
-        if (c < nch && jsel < 0) {
-            const uint64_t hit = __ballot(c * 64 + lane < n_t && x[c] >= tot);
-            if (hit) jsel = c * 64 + __builtin_ctzll(hit);
-        }
-    }
+    const int jsel = __shfl(jl, owner, 64);
     if (theta && lane < 7) {
         double y = sel[lane * m + r];
         if (lane == 6) y += (double)(jsel - (n_t - 1) / 2) / srate;
@@ -298,11 +320,12 @@ hipError_t ile_launch_hv_bin(const double *series, int64_t m, int n_t, const dou
     if (m <= 0) return hipSuccess;
     constexpr int rows = HV_T / 64;
     const dim3 grid((unsigned)((m + rows - 1) / rows));
+    const size_t seg = (size_t)rows * 64 * ((n_t + 63) / 64) * sizeof(double);
     if (n_t <= 64 * 8)
-        hipLaunchKernelGGL(k_hv_bin_reg<8>, grid, dim3(HV_T), 0, st, series, m, n_t, v, sel, srate,
+        hipLaunchKernelGGL(k_hv_bin_seg<8>, grid, dim3(HV_T), seg, st, series, m, n_t, v, sel, srate,
                            bins, theta, ld_out);
     else if (n_t <= 64 * 32)
-        hipLaunchKernelGGL(k_hv_bin_reg<32>, grid, dim3(HV_T), 0, st, series, m, n_t, v, sel,
+        hipLaunchKernelGGL(k_hv_bin_seg<32>, grid, dim3(HV_T), seg, st, series, m, n_t, v, sel,
                            srate, bins, theta, ld_out);
     else
         hipLaunchKernelGGL(k_hv_bin, grid, dim3(HV_T), 0, st, series, m, n_t, v, sel, srate, bins,
