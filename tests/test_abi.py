@@ -98,3 +98,11 @@ def test_binding_raises_when_library_missing(monkeypatch, tmp_path):
     monkeypatch.setattr(ile, "_lib", None)
     with pytest.raises(ImportError):
         ile.lib()
+
+
+def test_binding_types_every_declared_symbol(L):
+    """The ctypes binding gives every declared entry point its argument
+    types (an untyped call would pass Python ints as 32-bit C ints and
+    truncate pointers)."""
+    missing = [n for n in declared_symbols() if getattr(L, n).argtypes is None]
+    assert not missing, missing
