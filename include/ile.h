@@ -611,16 +611,31 @@ ile_status ile_sync(ile_ctx *ctx);
 typedef enum {
     ILE_OPT_SORT = 0,    /* 1: order samples by window position before the
                             contraction (default), 0: keep input order */
-    ILE_OPT_ENGINE = 1,  /* contraction engine: 1 = matrix cores (default;
-                            the only BF16 engine), 0 = vector FMA (a block
-                            width of 128 or 192 becomes 256) */
-    ILE_OPT_THREADS = 2, /* positions per block: 256 or 512, or 128 or 192
-                            with the matrix cores (workgroups of twice as
-                            many threads: producers + consumers); default
-                            128 for FP64 and BF16, 256 for FP32 */
-    ILE_OPT_HARVEST_ROWS = 3  /* most draws whose per-bin series
+    ILE_OPT_ENGINE = 1,  /* contraction engine: 1 = matrix cores (default):
+                            for FP64 and FP32 the phased form, in which
+                            every wave of a tile computes its share of the
+                            windowed products and then time-marginalizes
+                            its share of the samples; for BF16 the
+                            pipelined form.  2 = matrix cores, pipelined:
+                            producer waves compute the products while
+                            consumer waves marginalize the previous block.
+                            0 = vector FMA (a block width of 128 or 192
+                            becomes 256) */
+    ILE_OPT_THREADS = 2, /* pipelined and vector engines: positions per
+                            block, 256 or 512, or 128 or 192 with the
+                            matrix cores (workgroups of twice as many
+                            threads: producers + consumers); default 128
+                            for FP64 and BF16, 256 for FP32 */
+    ILE_OPT_HARVEST_ROWS = 3, /* most draws whose per-bin series
                             ile_harvest_dev holds at once (>= 1; 0 restores
                             the default of 2 GiB of series) */
+    ILE_OPT_LDS_KB = 4   /* phased engine: LDS per workgroup in KiB for its
+                            coefficient and product blocks (0 .. 160; 0
+                            restores the default of 78, two workgroups per
+                            compute unit).  A larger budget gives longer
+                            time chunks and fewer workgroups per unit; a
+                            budget too small for a 32-position block makes
+                            the evaluation fail with ILE_E_UNSUPPORTED */
 } ile_option;
 ile_status ile_set_option(ile_ctx *ctx, ile_option opt, int64_t value);
 

@@ -48,12 +48,15 @@ class OrcResult(C.Structure):
 
 
 def lib():
+    """Load the oracle library: ILE_ORACLE_LIB names another build of it
+    (the sanitizer build), else oracle/libile_oracle.so, built if missing."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+        path = os.environ.get("ILE_ORACLE_LIB") or _LIB_PATH
+        if path == _LIB_PATH and not os.path.exists(_LIB_PATH):
             from . import build as _build
             _build.build()
-        _lib = C.CDLL(_LIB_PATH)
+        _lib = C.CDLL(path)
         _lib.orc_delay.restype = C.c_double
         _lib.orc_logmeanexp.restype = C.c_double
         _lib.orc_eval.restype = C.c_int64

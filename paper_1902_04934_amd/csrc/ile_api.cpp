@@ -359,8 +359,7 @@ ile_status ile_create(const ile_config *cfg, ile_ctx **out)
         cfg->n_t < 1 || cfg->n_t > 65535 || cfg->n_t % 2 == 0 ||
         !(cfg->d_ref_mpc > 0) || !std::isfinite(cfg->gmst_rad) ||
         !(cfg->earth_radius_m > 0) || !(cfg->t_ref_max_s >= 0) ||
-        (cfg->precision != ILE_FP64 && cfg->precision != ILE_FP32 &&
-         cfg->precision != ILE_BF16))
+        enum_raw(cfg->precision) < ILE_FP64 || enum_raw(cfg->precision) > ILE_BF16)
         return ILE_E_ARG;
     for (int a = 0; a < cfg->n_lm; a++) {
         int l = cfg->modes[a].l, m = cfg->modes[a].m;
@@ -383,13 +382,11 @@ ile_status ile_create(const ile_config *cfg, ile_ctx **out)
         delete c;
         return ILE_E_DEVICE;
     }
-    // every precision defaults to the matrix cores (BF16 has no other engine);
-    // block widths measured fastest on the 3-detector, 21-mode, 1601-bin
-    // workload: 192 positions in FP64, 128 in FP32 and BF16
-    c->tune.engine = 1;
-    // measured on 3 detectors x 21 modes, 1e6 x 1601: FP64 and BF16 fastest
-    // at 128 positions (three workgroups per CU), FP32 at 256
-    c->tune.threads = cfg->precision == ILE_FP32 ? 256 : 128;
+    // every precision defaults to the matrix cores: the phased engine for
+    // FP64 and FP32, the producer/consumer pipeline for BF16 (its only
+    // engine), 128 positions per block there (three workgroups per CU)
+    c->tune.engine = cfg->precision == ILE_BF16 ? 1 : 3;
+    c->tune.threads = cfg->precision == ILE_BF16 ? 128 : 512;
     if (cfg->stream) {
         c->stream = (hipStream_t)cfg->stream;
     } else {
@@ -1297,8 +1294,9 @@ ile_status ile_run(ile_ctx *c, const ile_run_opts *o, ile_result *out, int64_t *
     ile_status s = check_ready(c);
     if (s) return s;
     if (!o || !out) return fail(c, ILE_E_ARG, "null pointer");
-    if (o->sampler == ILE_SAMPLER_LEARNED) return run_learned(c, o, out, n_chunks_out);
-    if (o->sampler != ILE_SAMPLER_PRIOR && o->sampler != ILE_SAMPLER_ADAPTIVE)
+    const int32_t sampler = enum_raw(o->sampler);
+    if (sampler == ILE_SAMPLER_LEARNED) return run_learned(c, o, out, n_chunks_out);
+    if (sampler != ILE_SAMPLER_PRIOR && sampler != ILE_SAMPLER_ADAPTIVE)
         return fail(c, ILE_E_ARG, "unknown sampler");
     if (o->max_samples <= 0 || !(o->d_min_mpc > 0) || !(o->d_max_mpc > o->d_min_mpc) ||
         !std::isfinite(o->d_max_mpc))
@@ -1385,19 +1383,29 @@ ile_status ile_set_option(ile_ctx *c, ile_option opt, int64_t v)
     if (!c) return ILE_E_ARG;
     begin_call(c);
     ile_tune t = c->tune;
-    switch (opt) {
+    switch (enum_raw(opt)) {
     case ILE_OPT_SORT:
         if (v != 0 && v != 1) return fail(c, ILE_E_ARG, "sort must be 0 or 1");
         c->sort = (int)v;
         return ILE_OK;
     case ILE_OPT_ENGINE:
-        if (v != 0 && v != 1) return fail(c, ILE_E_ARG, "engine must be 0 or 1");
-        t.engine = (int)v;
-        // the vector engine has no 128/192-position blocks: use 256
+        if (v < 0 || v > 2) return fail(c, ILE_E_ARG, "engine must be 0, 1 or 2");
+        // option 1 is the phased matrix-core engine where the precision has
+        // one (FP64, FP32), else the pipelined one; option 2 the pipelined
+        t.engine = v == 0 ? 0 : (v == 1 && c->cfg.precision != ILE_BF16) ? 3 : 1;
+        // the vector engine has no 128/192-position blocks: use 256; the
+        // phased engine takes 256 or 512 threads (512 by default), the
+        // pipelined one 128 positions by default
         if (t.engine == 0 && (t.threads == 128 || t.threads == 192)) t.threads = 256;
+        if (t.engine == 3 && t.threads != 256) t.threads = 512;
+        if (t.engine == 1 && c->tune.engine == 3) t.threads = 128;
         break;
     case ILE_OPT_THREADS:
         t.threads = (int)v;
+        break;
+    case ILE_OPT_LDS_KB:
+        if (v < 0 || v > 160) return fail(c, ILE_E_ARG, "LDS budget must be 0 .. 160 KB");
+        t.lds_budget = (int)v * 1024;
         break;
     case ILE_OPT_HARVEST_ROWS:
         if (v < 0) return fail(c, ILE_E_ARG, "harvest rows must be >= 0");

@@ -107,14 +107,7 @@ __global__ __launch_bounds__(256) void k_prep_multi(const ile_geom *geoms,
     }
     uint32_t key = B - 1;   // invalid samples last within the point
     if (ok) {
-        key = 0;
-        for (int d = 0; d < g.key_dims; d++) {
-            int c = (sh[d] - g.key_lo[d]) >> g.key_shift;
-            c = c < 0 ? 0 : c;
-            c = c > (1 << g.key_bits) - 1 ? (1 << g.key_bits) - 1 : c;
-            for (int b = 0; b < g.key_bits; b++)
-                key |= (uint32_t)((c >> b) & 1) << (b * g.key_dims + d);
-        }
+        key = cell_key(g, sh);
     } else {
         atomicOr(err, 1);
     }

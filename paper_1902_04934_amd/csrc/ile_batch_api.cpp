@@ -151,6 +151,7 @@ ile_status build(ile_batch *b, int64_t n, double dmin, double dmax, bool ext)
     size_t dyn = 0, lds = 0;
     for (int p = 0; p < P; p++) {
         gs[p] = batched_geom(b->pts[p]);
+        ile_contract_prepare(gs[p], b->cfg.precision, tu);
         offs[p] = (int64_t)p * n;
         dyn = std::max(dyn, ile_contract_dyn_bytes(gs[p], b->cfg.precision, tu));
         lds = std::max(lds, ile_contract_lds_bytes(gs[p], b->cfg.precision, tu));
@@ -341,8 +342,7 @@ ile_status ile_batch_create(const ile_batch_config *cfg, ile_batch **out)
 {
     if (!out) return ILE_E_ARG;
     *out = nullptr;
-    if (!cfg || (cfg->precision != ILE_FP64 && cfg->precision != ILE_FP32 &&
-                 cfg->precision != ILE_BF16))
+    if (!cfg || enum_raw(cfg->precision) < ILE_FP64 || enum_raw(cfg->precision) > ILE_BF16)
         return ILE_E_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return ILE_E_DEVICE;

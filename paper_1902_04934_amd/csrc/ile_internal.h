@@ -4,8 +4,20 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
 
 #include "ile.h"
+
+// Enum fields and arguments arrive from C callers, where any int may sit in
+// them; C++ must not load an out-of-range value as the enum type, so the
+// ABI reads them as 32-bit integers and validates those.
+template <typename E> inline int32_t enum_raw(const E &e)
+{
+    static_assert(sizeof(E) == sizeof(int32_t), "4-byte enum");
+    int32_t v;
+    memcpy(&v, &e, sizeof v);
+    return v;
+}
 
 #define ILE_NPAR 7
 #define ILE_MAX_TERMS 160   // Wigner-d terms over all modes (l <= 6, <= 32 modes)
@@ -17,12 +29,16 @@ struct ile_geom {
     int n_det, n_lm, n_t, half;      // half = (n_t - 1) / 2
     int n_q;                         // length of each Q series
     int s_max;                       // largest valid window start, n_q - n_t
+    // phased matrix-core engine: positions of one detector's G block (the
+    // union of a chunk's windows) and the LDS row stride of that block; set
+    // per launch from the LDS budget
+    int wcap, wrow;
     double t0;                       // time of Q[0]
     double dt;                       // 1 / srate
     double d_ref, gmst, t_ref_max;
     double r[ILE_MAX_DET][3];        // site vectors [m]
     double D[ILE_MAX_DET][9];        // detector tensors
-    // ordering key: Morton code of the window starts of up to 3 detectors
+    // ordering key: Hilbert index of the window starts of up to 3 detectors
     int key_lo[3];
     int key_shift;                   // log2 of the cell width in samples
     int key_bits;                    // bits per axis
@@ -74,6 +90,56 @@ __device__ inline uint32_t wave_count_slot(uint32_t *table, uint32_t key)
     return slot;
 }
 
+// Ordering key of a sample: its cell (window starts of up to three
+// detectors, each in cells of 2^key_shift positions, key_bits bits per axis)
+// numbered along the Hilbert curve, so that runs of consecutive keys stay
+// compact in every axis (tiles of consecutive samples then span narrower
+// windows than along a Morton order).  Skilling's transpose form (J.
+// Skilling, "Programming the Hilbert curve", AIP Conf. Proc. 707, 381, 2004),
+// then the transposed bits interleaved from the most significant.
+__device__ inline uint32_t cell_key(const ile_geom &g, const int *s)
+{
+    const int n = g.key_dims, b = g.key_bits;
+    if (n < 1 || b < 1) return 0;   // a single cell
+    uint32_t x[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+        if (d < n) {
+            int c = (s[d] - g.key_lo[d]) >> g.key_shift;
+            c = c < 0 ? 0 : c;
+            c = c > (1 << b) - 1 ? (1 << b) - 1 : c;
+            x[d] = (uint32_t)c;
+        }
+    const uint32_t top = 1u << (b - 1);
+    for (uint32_t q = top; q > 1; q >>= 1) {
+        const uint32_t p = q - 1;
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+            if (i < n) {
+                if (x[i] & q) {
+                    x[0] ^= p;
+                } else {
+                    const uint32_t t = (x[0] ^ x[i]) & p;
+                    x[0] ^= t;
+                    x[i] ^= t;
+                }
+            }
+    }
+#pragma unroll
+    for (int i = 1; i < 3; i++)
+        if (i < n) x[i] ^= x[i - 1];
+    const uint32_t last = n == 3 ? x[2] : n == 2 ? x[1] : x[0];
+    uint32_t t = 0;
+    for (uint32_t q = top; q > 1; q >>= 1)
+        if (last & q) t ^= q - 1;
+    uint32_t key = 0;
+    for (int bit = b - 1; bit >= 0; bit--)
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+            if (i < n) key = (key << 1) | (((x[i] ^ t) >> bit) & 1u);
+    return key;
+}
+
 // K steps of the matrix-core contraction (4 real rows = 2 modes each); the
 // device Q holds 4 * ksp_of(n_lm) rows per detector (rows 2a and 2a+1 = Re,
 // Im of mode a, the rest zero).
@@ -109,10 +175,15 @@ __host__ __device__ inline int ksb_of(int n_lm) { return (6 * n_lm + 31) / 32; }
 // Tuning of the contraction kernel.
 struct ile_tune {
     int tile_samples;   // samples per workgroup tile (16)
-    int threads;        // threads per workgroup (= positions per G block): 256 or 512
-    int engine;         // 0: FMA on the vector ALUs, 1: FP64 matrix cores
+    int threads;        // positions per G block of the pipelined engines: 128 .. 512
+    int engine;         // 0: FMA on the vector ALUs, 1: matrix cores, producer and
+                        // consumer waves; 3: matrix cores, phased waves
+    int lds_budget;     // phased engine: dynamic LDS per workgroup in bytes (0: default)
 };
 bool ile_tune_supported(ile_precision prec, const ile_tune &tu);
+// Sets the phased engine's block width in g (wcap, wrow) for this tuning;
+// zero for the other engines.
+void ile_contract_prepare(ile_geom &g, ile_precision prec, const ile_tune &tu);
 
 // Launch wrappers (ile_kernels.hip).  All are asynchronous on `st`.
 hipError_t ile_launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);

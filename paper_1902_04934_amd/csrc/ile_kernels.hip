@@ -227,14 +227,7 @@ __global__ __launch_bounds__(256) void k_prep(ile_geom g,
     }
     uint32_t key = n_buckets - 1;   // invalid samples sort last
     if (ok) {
-        key = 0;
-        for (int d = 0; d < g.key_dims; d++) {
-            int c = (s[d] - g.key_lo[d]) >> g.key_shift;
-            c = c < 0 ? 0 : c;
-            c = c > (1 << g.key_bits) - 1 ? (1 << g.key_bits) - 1 : c;
-            for (int b = 0; b < g.key_bits; b++)
-                key |= (uint32_t)((c >> b) & 1) << (b * g.key_dims + d);
-        }
+        key = cell_key(g, s);
     } else {
         atomicOr(err, 1);
     }
@@ -343,7 +336,8 @@ __global__ __launch_bounds__(256) void k_identity(int32_t *perm, int64_t N)
 //             16 positions, A (coefficients) from LDS, B (Q) from memory.
 // Realign: thread j of the chunk adds G[alpha][s_alpha,k - s_min,k + j] for
 // every sample; online FP64 log-sum-exp over the bins each thread owns.
-enum { ENG_VALU = 0, ENG_MFMA = 1, ENG_BF16 = 2 };
+// ENG_PH: the phased matrix-core engine below (FP64 or FP32 operands).
+enum { ENG_VALU = 0, ENG_MFMA = 1, ENG_BF16 = 2, ENG_PH = 3 };
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -651,40 +645,24 @@ __device__ inline double epi_reduce(const double *R, int tid, bool is_max)
     return is_max ? row_max64(v) : row_sum64(v);
 }
 
-// One tile: samples perm[base .. base + TS) of a point (those below N).
-template <typename TQ, int TS, int NT, int ENG, bool DUMP>
-__device__ __forceinline__ void contract_tile(
+// Per-sample part of a tile, shared by the engines: the samples, -2Y_lm,
+// the antenna patterns, the coefficients c = (d_ref/D) F_k Y_lm in the
+// engine's operand layout and the quadratic term q of Eq. (7).  scr is free
+// LDS of scr_cap bytes (at least prologue_scratch_bytes); U_k and V_k are
+// staged there too when they fit.  s_d receives the absolute window starts
+// (0 for invalid samples).  Ends with a barrier.
+template <typename TQ, int TS, int NT, int ENG>
+__device__ __forceinline__ void tile_prologue(
     const ile_geom &g, int64_t base, const double *__restrict__ smp, int64_t N,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ shifts,
-    const TQ *__restrict__ Q, const double2 *__restrict__ U,
-    const double2 *__restrict__ V, double *__restrict__ out,
-    double *__restrict__ series)
+    const double2 *__restrict__ U, const double2 *__restrict__ V, double *scr,
+    size_t scr_cap, TQ *coef, double *s_q, int *s_idx, int *s_ok, int (*s_d)[TS])
 {
-    static_assert(ENG == ENG_VALU || (TS == 16 && NT % 128 == 0), "MFMA tile is 16 samples");
-    static_assert(ENG != ENG_BF16 || sizeof(TQ) == 4, "BF16 engine accumulates in float");
-    constexpr int NW = NT / 64;
-    __shared__ __align__(16) TQ Gs[TS * NT];
-    __shared__ double s_q[TS];
-    __shared__ int s_idx[TS];      // sample index, -1 if the slot is empty
-    __shared__ int s_ok[TS];
-    __shared__ int s_d[ILE_MAX_DET][TS];
-    __shared__ int s_smin[ILE_MAX_DET], s_spread[ILE_MAX_DET];
-    __shared__ double s_red[NW][TS];
-    __shared__ double s_M[TS];
-    extern __shared__ __align__(16) unsigned char dyn_lds[];
-    TQ *coef = reinterpret_cast<TQ *>(dyn_lds);
-
     const int tid = threadIdx.x;
-    const int nd = g.n_det, nl = g.n_lm, nq = g.n_q;
-    const int KSP = ksp_of(nl), RP = 4 * KSP;   // k-steps and Q rows per detector (padded)
-    const int KSB = ksb_of(nl);                 // BF16 k-steps
-    constexpr bool MF = ENG != ENG_VALU;        // matrix-core engines
-
-    // prologue scratch: inside Gs when it fits, else after the coefficients
+    const int nd = g.n_det, nl = g.n_lm;
+    const int KSP = ksp_of(nl);    // k-steps per detector (padded)
+    const int KSB = ksb_of(nl);    // BF16 k-steps
     const size_t scr_bytes = prologue_scratch_bytes(TS, nd, nl);
-    double *scr = scr_bytes <= sizeof(Gs)
-                      ? reinterpret_cast<double *>(Gs)
-                      : reinterpret_cast<double *>(dyn_lds + coef_bytes<ENG>(TS, nd, nl, sizeof(TQ)));
     double *s_th = scr;                                  // [7][TS]
     double2 *s_Y = reinterpret_cast<double2 *>(scr + 7 * TS);   // [TS][nl]
     double2 *s_F = s_Y + TS * nl;                        // [TS][nd]
@@ -751,9 +729,8 @@ __device__ __forceinline__ void contract_tile(
     //    instead of a dependent global load per term)
     const int nlp = ENG == ENG_MFMA ? 2 * KSP : nl;
     const size_t uv_off = (scr_bytes + 15) & ~(size_t)15;
-    const bool stage_uv = scr == reinterpret_cast<double *>(Gs) &&
-                          uv_off + 2 * (size_t)nl * nl * sizeof(double2) <= sizeof(Gs);
-    double2 *s_U = reinterpret_cast<double2 *>(reinterpret_cast<unsigned char *>(Gs) + uv_off);
+    const bool stage_uv = uv_off + 2 * (size_t)nl * nl * sizeof(double2) <= scr_cap;
+    double2 *s_U = reinterpret_cast<double2 *>(reinterpret_cast<unsigned char *>(scr) + uv_off);
     double2 *s_V = s_U + nl * nl;
     for (int k = 0; k < nd; k++) {
       if (stage_uv) {
@@ -823,8 +800,60 @@ __device__ __forceinline__ void contract_tile(
     }
     __syncthreads();
 
-    // 4. per-detector window range of the tile; quadratic term per sample,
-    //    16 lanes per sample, fixed-order butterfly
+    static_assert(NT >= 16 * TS, "16 lanes per sample for the quadratic sum");
+    if (tid < 16 * TS) {
+        const int al = tid >> 4, l16 = tid & 15;
+        double sum = 0.0;
+        for (int r = l16; r < nd * nl; r += 16) sum += s_qp[al * (nd * nl) + r];
+        for (int off = 8; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+        if (l16 == 0) {
+            const double kap = s_ok[al] ? g.d_ref / s_th[5 * TS + al] : 0.0;
+            s_q[al] = 0.25 * kap * kap * sum;
+        }
+    }
+    __syncthreads();
+}
+
+// One tile: samples perm[base .. base + TS) of a point (those below N).
+template <typename TQ, int TS, int NT, int ENG, bool DUMP>
+__device__ __forceinline__ void contract_tile(
+    const ile_geom &g, int64_t base, const double *__restrict__ smp, int64_t N,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ shifts,
+    const TQ *__restrict__ Q, const double2 *__restrict__ U,
+    const double2 *__restrict__ V, double *__restrict__ out,
+    double *__restrict__ series)
+{
+    static_assert(ENG == ENG_VALU || (TS == 16 && NT % 128 == 0), "MFMA tile is 16 samples");
+    static_assert(ENG != ENG_BF16 || sizeof(TQ) == 4, "BF16 engine accumulates in float");
+    constexpr int NW = NT / 64;
+    __shared__ __align__(16) TQ Gs[TS * NT];
+    __shared__ double s_q[TS];
+    __shared__ int s_idx[TS];      // sample index, -1 if the slot is empty
+    __shared__ int s_ok[TS];
+    __shared__ int s_d[ILE_MAX_DET][TS];
+    __shared__ int s_smin[ILE_MAX_DET], s_spread[ILE_MAX_DET];
+    __shared__ double s_red[NW][TS];
+    __shared__ double s_M[TS];
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
+    TQ *coef = reinterpret_cast<TQ *>(dyn_lds);
+
+    const int tid = threadIdx.x;
+    const int nd = g.n_det, nl = g.n_lm, nq = g.n_q;
+    const int KSP = ksp_of(nl), RP = 4 * KSP;   // k-steps and Q rows per detector (padded)
+    const int KSB = ksb_of(nl);                 // BF16 k-steps
+    constexpr bool MF = ENG != ENG_VALU;        // matrix-core engines
+
+    // prologue scratch: inside Gs when it fits, else after the coefficients
+    const size_t scr_bytes = prologue_scratch_bytes(TS, nd, nl);
+    double *scr = scr_bytes <= sizeof(Gs)
+                      ? reinterpret_cast<double *>(Gs)
+                      : reinterpret_cast<double *>(dyn_lds + coef_bytes<ENG>(TS, nd, nl, sizeof(TQ)));
+
+    tile_prologue<TQ, TS, NT, ENG>(g, base, smp, N, perm, shifts, U, V, scr,
+                                   scr == reinterpret_cast<double *>(Gs) ? sizeof(Gs) : 0,
+                                   coef, s_q, s_idx, s_ok, s_d);
+
+    // 4. per-detector window range of the tile
     if (tid < nd) {
         const int k = tid;
         int lo = 0x7fffffff, hi = -1;
@@ -836,17 +865,6 @@ __device__ __forceinline__ void contract_tile(
         if (hi < 0) lo = hi = 0;
         s_smin[k] = lo;
         s_spread[k] = hi - lo;
-    }
-    static_assert(NT >= 16 * TS, "16 lanes per sample for the quadratic sum");
-    if (tid < 16 * TS) {
-        const int al = tid >> 4, l16 = tid & 15;
-        double sum = 0.0;
-        for (int r = l16; r < nd * nl; r += 16) sum += s_qp[al * (nd * nl) + r];
-        for (int off = 8; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
-        if (l16 == 0) {
-            const double kap = s_ok[al] ? g.d_ref / s_th[5 * TS + al] : 0.0;
-            s_q[al] = 0.25 * kap * kap * sum;
-        }
     }
     __syncthreads();
     if (tid < TS)
@@ -1063,23 +1081,429 @@ __device__ __forceinline__ void contract_tile(
     }
 }
 
+// ------------------------------------------------ phased matrix-core engine
+// One workgroup of four waves per tile of 16 samples.  On gfx950 an FP64
+// matrix-core step holds its SIMD's issue for its whole duration, so the
+// vector work and the matrix work of a SIMD add up instead of overlapping.
+// The tile is therefore not split into producer and consumer waves (which
+// leaves the matrix work on some SIMDs and the vector work on others):
+// every wave takes both roles in turn, per chunk of J bins:
+//   G phase: the G blocks of all detectors, G_k[alpha][p] =
+//            sum_r C_k[alpha][r] Qm_k[r][P_k + p] over the union of the
+//            chunk's windows (P_k = smin_k + j0), as 16-wide N-tiles dealt
+//            to the waves in turn (the first wave rotates with the
+//            detector), each written to its LDS block;
+//   L phase: lane (alpha, sub), LPS = 16 or 32 lanes per sample, owns the
+//            bins j = sub (mod LPS); it sums G_k[alpha][s_alpha,k - smin_k + j - j0]
+//            over the detectors (k ascending) and folds each bin into its
+//            log-sum-exp.
+// J = floor16(wcap - spread), spread the widest detector's range of window
+// starts in the tile, so each block fits wcap positions.  A tile whose
+// spread exceeds wcap - 16 is processed in passes over subsets of its
+// samples (greedy in tile order); rows of samples outside a pass are
+// computed but not read.
+//
+// Log-sum-exp with a lagging reference: each lane keeps (m, s) with
+// s = sum exp(x - m) over its bins, and moves m to x only at its first bin
+// or when x > m + kLseSlack, so most bins cost one exp and one add.  The
+// 16 lanes of a sample are merged by a fixed tree at the end.  A sample's
+// bins, their order within each lane and the merge depend neither on the
+// tile it lands in nor on the chunking or the pass, and neither does its
+// result.
+constexpr double kLseSlack = 64.0;
+
+// a * b + c with c a wave-uniform constant held in scalar registers.  The
+// compiler's own selection turns Horner steps into a register copy of the
+// constant plus an accumulating FMA (its tied operand); this form needs no
+// copy.  Arithmetic only.
+__device__ __forceinline__ double fma_sc(double a, double b, double c)
+{
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+    return d;
+}
+
+// e^d for d <= kLseSlack, the log-sum-exp's terms: d = n ln2 + r with
+// n = rint(d / ln2) and r reduced in two parts (Cody and Waite), so
+// |r| <= ln2 / 2; e^r by its Taylor polynomial of degree 13 (truncation
+// below 5e-18 relative); then scaled by 2^n.  Arguments below -1000 are
+// clamped there (the result underflows to 0 either way), so no overflow or
+// NaN test is needed.  Relative error a few ulp.
+__device__ __forceinline__ double exp_lse(double d)
+{
+    // d is never NaN here, so the clamp needs no canonicalization
+    asm("v_max_f64 %0, %1, %2" : "=v"(d) : "v"(d), "s"(-1000.0));
+    const double n = rint(d * 1.4426950408889634074);
+    const double r = fma(-n, 1.9082149292705877000e-10, fma(-n, 6.9314718036912381649e-1, d));
+    double p = fma_sc(r, 1.0 / 6227020800.0, 1.0 / 479001600.0);   // 1/13!, 1/12!
+    p = fma_sc(p, r, 1.0 / 39916800.0);
+    p = fma_sc(p, r, 1.0 / 3628800.0);
+    p = fma_sc(p, r, 1.0 / 362880.0);
+    p = fma_sc(p, r, 1.0 / 40320.0);
+    p = fma_sc(p, r, 1.0 / 5040.0);
+    p = fma_sc(p, r, 1.0 / 720.0);
+    p = fma_sc(p, r, 1.0 / 120.0);
+    p = fma_sc(p, r, 1.0 / 24.0);
+    p = fma_sc(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)n);
+}
+
+template <typename TQ> struct qload;
+template <> struct qload<double> {
+    static __device__ inline double ld(__amdgpu_buffer_rsrc_t r, int vo, int so)
+    {
+        typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+        const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
+        return __builtin_bit_cast(double, v);
+    }
+};
+template <> struct qload<float> {
+    static __device__ inline float ld(__amdgpu_buffer_rsrc_t r, int vo, int so)
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+};
+
+// Buffer resource over one detector's Q rows (raw bytes, gfx9 word 3).
+template <typename TQ>
+__device__ inline __amdgpu_buffer_rsrc_t q_rsrc(const TQ *Qk, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<TQ *>(Qk), (short)0, bytes, 0x00020000);
+}
+
+// Up to four (detector, N-tile) pairs of a wave, computed together so that
+// four accumulations are always in flight.
+struct PhPairs {
+    int k[4], t[4], p0[4];
+};
+
+// NU pairs: lane l supplies A[l%16][l/16] (coefficients of the pair's
+// detector, LDS) and B[l/16][l%16] = Qm_k[4 ks + l/16][P0 + 16 t + l%16] by
+// buffer loads, the lane's offset in a VGPR and the k-step's in an SGPR, so a
+// load costs no vector instruction.  Columns past the end of Q are clamped
+// (their results are never read).  Operands are double-buffered: the loads
+// of k-step ks + 1 are issued before the products of k-step ks.
+template <typename TQ, int NU>
+__device__ inline void ph_pairs(TQ *G, int wrow, const TQ *coef, __amdgpu_buffer_rsrc_t rs,
+                                int nq, int KSP, int RP, const PhPairs &pp, int lane)
+{
+    using M = mfma_acc<TQ>;
+    const int row = lane >> 4, col = lane & 15;
+    typename M::type acc[NU];
+    int vo[NU], ao[NU];
+#pragma unroll
+    for (int u = 0; u < NU; u++) {
+        acc[u] = typename M::type{0, 0, 0, 0};
+        vo[u] = ((pp.k[u] * RP + row) * nq + min(pp.p0[u] + 16 * pp.t[u] + col, nq - 1)) *
+                (int)sizeof(TQ);
+        ao[u] = pp.k[u] * KSP * 64 + lane;
+    }
+    const int kstep = 4 * nq * (int)sizeof(TQ);
+    TQ a0[NU], b0[NU], a1[NU], b1[NU];
+#pragma unroll
+    for (int u = 0; u < NU; u++) {
+        a0[u] = coef[ao[u]];
+        b0[u] = qload<TQ>::ld(rs, vo[u], 0);
+    }
+    // k-steps in pairs with every load and product unconditional (a load
+    // under a branch is sunk next to its use); an odd last step follows
+    int ks = 0;
+    for (; ks + 1 < KSP; ks += 2) {
+        const int k2 = min(ks + 2, KSP - 1);
+#pragma unroll
+        for (int u = 0; u < NU; u++) {
+            a1[u] = coef[ao[u] + (ks + 1) * 64];
+            b1[u] = qload<TQ>::ld(rs, vo[u], (ks + 1) * kstep);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < NU; u++) acc[u] = M::step(a0[u], b0[u], acc[u]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < NU; u++) {
+            a0[u] = coef[ao[u] + k2 * 64];
+            b0[u] = qload<TQ>::ld(rs, vo[u], k2 * kstep);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < NU; u++) acc[u] = M::step(a1[u], b1[u], acc[u]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (ks < KSP) {
+#pragma unroll
+        for (int u = 0; u < NU; u++) acc[u] = M::step(a0[u], b0[u], acc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < NU; u++) {
+        TQ *Gu = G + (pp.k[u] * 16) * wrow + 16 * pp.t[u] + col;
+#pragma unroll
+        for (int v = 0; v < 4; v++) Gu[M::row(row, v) * wrow] = (TQ)acc[u][v];
+    }
+}
+
+// LDS of the phased tile beyond its static arrays: coefficients
+// [nd][KSP][64], then the G blocks [nd][TS][wrow] (the prologue's scratch
+// lives there first).
+__host__ __device__ inline size_t ph_dyn_bytes(int ts, int nd, int nl, int wrow, size_t e)
+{
+    const size_t gb = (size_t)nd * ts * wrow * e;
+    const size_t sb = prologue_scratch_bytes(ts, nd, nl);
+    return coef_bytes<ENG_MFMA>(ts, nd, nl, e) + (gb > sb ? gb : sb);
+}
+
+// L phase of one chunk for one lane of the phased tile: the chunk's bins
+// j0 + i, i = o, o + LPS, o + 2 LPS, ... < Jc, of its sample (o chosen by
+// the caller so that the lane owns the bins j = sub (mod LPS) whatever the
+// chunking), each the sum of the ND detectors' G entries (k ascending),
+// folded into the lane's log-sum-exp (m, s).  srow: the sample's series row
+// at bin j0 when the per-bin values are wanted (minus q), else null.
+template <typename TQ, int ND, int LPS, bool DUMP>
+__device__ __forceinline__ void ph_lphase(const TQ *G, const int (&go)[ILE_MAX_DET], int Jc,
+                                          int o, double &m, double &ssum, double *srow,
+                                          double q)
+{
+    const auto xsum = [&](int i) {
+        TQ xs = G[go[0] + i];
+#pragma unroll
+        for (int k = 1; k < ND; k++) xs += G[go[k] + i];
+        if (DUMP) srow[i] = (double)xs - q;
+        return (double)xs;
+    };
+    const auto fold = [&](double x) {
+        double d = x - m;
+        if (d > kLseSlack) {
+            ssum = m == -INFINITY ? 0.0 : ssum * exp(m - x);
+            m = x;
+            d = 0.0;
+        }
+        ssum += exp_lse(d);
+    };
+    // two bins at a time: when neither moves the reference, their exps are
+    // independent (the sums are still taken in bin order, as fold would)
+    int i = o;
+    for (; i + LPS < Jc; i += 2 * LPS) {
+        const double x0 = xsum(i), x1 = xsum(i + LPS);
+        const double d0 = x0 - m, d1 = x1 - m;
+        if (d0 > kLseSlack || d1 > kLseSlack) {
+            fold(x0);
+            fold(x1);
+        } else {
+            const double e0 = exp_lse(d0), e1 = exp_lse(d1);
+            ssum += e0;
+            ssum += e1;
+        }
+    }
+    if (i < Jc) fold(xsum(i));
+}
+
+template <typename TQ, int TS, int NT, bool DUMP>
+__device__ __forceinline__ void contract_tile_ph(
+    const ile_geom &g, int64_t base, const double *__restrict__ smp, int64_t N,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ shifts,
+    const TQ *__restrict__ Q, const double2 *__restrict__ U,
+    const double2 *__restrict__ V, double *__restrict__ out,
+    double *__restrict__ series)
+{
+    static_assert(TS == 16 && (NT == 256 || NT == 512), "phased tile: 16 samples, 4 or 8 waves");
+    constexpr int NW = NT / 64;    // waves
+    constexpr int LPS = NT / TS;   // lanes per sample in the L phase
+    __shared__ double s_q[TS];
+    __shared__ int s_idx[TS], s_ok[TS], s_pass[TS];
+    __shared__ int s_d[ILE_MAX_DET][TS];
+    __shared__ int s_smin[ILE_MAX_DET], s_spread[ILE_MAX_DET];
+    __shared__ int s_npass;
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nd = g.n_det, nl = g.n_lm, nq = g.n_q, n_t = g.n_t;
+    const int KSP = ksp_of(nl), RP = 4 * KSP;
+    const int wcap = g.wcap, wrow = g.wrow;
+    TQ *coef = reinterpret_cast<TQ *>(dyn_lds);   // [nd][KSP][64]
+    TQ *G = reinterpret_cast<TQ *>(dyn_lds + coef_bytes<ENG_MFMA>(TS, nd, nl, sizeof(TQ)));
+    const size_t gbytes = (size_t)nd * TS * wrow * sizeof(TQ);
+    const size_t sbytes = prologue_scratch_bytes(TS, nd, nl);
+    // one buffer resource over all of Q (the host keeps it below 2 GiB)
+    const __amdgpu_buffer_rsrc_t rs = q_rsrc<TQ>(Q, nd * RP * nq * (int)sizeof(TQ));
+
+    tile_prologue<TQ, TS, NT, ENG_MFMA>(g, base, smp, N, perm, shifts, U, V,
+                                        reinterpret_cast<double *>(G),
+                                        gbytes > sbytes ? gbytes : sbytes, coef, s_q, s_idx,
+                                        s_ok, s_d);
+
+    // passes: greedy in tile order, each adds the samples that keep every
+    // detector's spread within wcap - 16 (one pass for all but rare tiles)
+    if (tid == 0) {
+        const int lim = wcap - 16;
+        int np = 0;
+        for (int al = 0; al < TS; al++) s_pass[al] = -1;
+        for (;;) {
+            int lo[ILE_MAX_DET] = {}, hi[ILE_MAX_DET] = {};
+            bool any = false;
+            for (int al = 0; al < TS; al++) {
+                if (!s_ok[al] || s_pass[al] >= 0) continue;
+                bool fits = true;
+#pragma unroll
+                for (int k = 0; k < ILE_MAX_DET; k++)
+                    if (any && k < nd)
+                        fits = fits && max(hi[k], s_d[k][al]) - min(lo[k], s_d[k][al]) <= lim;
+                if (!fits) continue;
+#pragma unroll
+                for (int k = 0; k < ILE_MAX_DET; k++)
+                    if (k < nd) {
+                        lo[k] = any ? min(lo[k], s_d[k][al]) : s_d[k][al];
+                        hi[k] = any ? max(hi[k], s_d[k][al]) : s_d[k][al];
+                    }
+                any = true;
+                s_pass[al] = np;
+            }
+            if (!any) break;
+            np++;
+        }
+        s_npass = np;
+    }
+    __syncthreads();
+
+    const int al = tid / LPS, sub = tid % LPS;
+    double m = -INFINITY, ssum = 0.0;
+    const int npass = s_npass;
+    for (int p = 0; p < npass; p++) {
+        if (tid < nd) {
+            int lo = 0x7fffffff, hi = -1;
+            for (int b = 0; b < TS; b++)
+                if (s_pass[b] == p) {
+                    lo = min(lo, s_d[tid][b]);
+                    hi = max(hi, s_d[tid][b]);
+                }
+            s_smin[tid] = lo;
+            s_spread[tid] = hi - lo;
+        }
+        __syncthreads();
+        int smax = 0, sx = 0;
+        for (int k = 0; k < nd; k++) {
+            smax = max(smax, s_spread[k]);
+            sx += (s_spread[k] + 15) >> 4;
+        }
+        // chunk length: the blocks fit wcap positions, and where it keeps
+        // at least 16 bins, the chunk has at most 32 pairs (J/16 tiles per
+        // detector plus the spreads' extra tiles): whole groups of four for
+        // eight waves, two for four
+        int J = (wcap - smax) & ~15;   // >= 16
+        const int jp = ((32 - sx) / nd) * 16;
+        if (jp >= 16 && jp < J) J = jp;
+        const bool mem = s_pass[al] == p;
+        // this lane's sample's entry of every G block at the chunk's first bin
+        int go[ILE_MAX_DET];
+#pragma unroll
+        for (int k = 0; k < ILE_MAX_DET; k++)
+            go[k] = k < nd ? (k * TS + al) * wrow + (mem ? s_d[k][al] - s_smin[k] : 0) : 0;
+        for (int j0 = 0; j0 < n_t; j0 += J) {
+            const int Jc = min(J, n_t - j0);
+            // G phase: the chunk's (detector, N-tile) pairs in detector
+            // order, dealt round-robin: wave wv takes pairs wv, wv + NW, ...
+            // (counts differ by at most one), four at a time
+            {
+                int kk = 0, tt = wv;   // pair wv: detector kk, tile tt
+                const auto norm = [&]() {
+                    while (kk < nd) {
+                        const int T = (Jc + s_spread[kk] + 15) >> 4;
+                        if (tt < T) break;
+                        tt -= T;
+                        kk++;
+                    }
+                };
+                norm();
+                while (kk < nd) {
+                    PhPairs pp;
+                    int nu = 0;
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        if (kk < nd) {
+                            pp.k[u] = kk;
+                            pp.t[u] = tt;
+                            pp.p0[u] = s_smin[kk] + j0;
+                            nu++;
+                            tt += NW;
+                            norm();
+                        } else {
+                            pp.k[u] = pp.k[0];
+                            pp.t[u] = pp.t[0];
+                            pp.p0[u] = pp.p0[0];
+                        }
+                    }
+                    switch (__builtin_amdgcn_readfirstlane(nu)) {
+                    case 4: ph_pairs<TQ, 4>(G, wrow, coef, rs, nq, KSP, RP, pp, lane); break;
+                    case 3: ph_pairs<TQ, 3>(G, wrow, coef, rs, nq, KSP, RP, pp, lane); break;
+                    case 2: ph_pairs<TQ, 2>(G, wrow, coef, rs, nq, KSP, RP, pp, lane); break;
+                    default: ph_pairs<TQ, 1>(G, wrow, coef, rs, nq, KSP, RP, pp, lane); break;
+                    }
+                }
+            }
+            __syncthreads();
+            // L phase
+            if (mem) {
+                double *srow = DUMP ? series + (int64_t)s_idx[al] * n_t + j0 : nullptr;
+                const double q = s_q[al];
+                const int o = (sub - j0) & (LPS - 1);   // first bin j = sub (mod LPS)
+                switch (nd) {
+                case 1: ph_lphase<TQ, 1, LPS, DUMP>(G, go, Jc, o, m, ssum, srow, q); break;
+                case 2: ph_lphase<TQ, 2, LPS, DUMP>(G, go, Jc, o, m, ssum, srow, q); break;
+                case 3: ph_lphase<TQ, 3, LPS, DUMP>(G, go, Jc, o, m, ssum, srow, q); break;
+                default: ph_lphase<TQ, 4, LPS, DUMP>(G, go, Jc, o, m, ssum, srow, q); break;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // merge the LPS lanes of each sample (fixed tree: 16-lane rows, then the
+    // row pair), then the result (M - q) + log S - log n_t
+    double M = row_max64(m);
+    if (LPS == 32) M = fmax(M, __shfl_xor(M, 16));
+    double S = row_sum64(m == -INFINITY ? 0.0 : ssum * exp(m - M));
+    if (LPS == 32) S += __shfl_xor(S, 16);
+    if (sub == 0 && s_idx[al] >= 0)
+        out[s_idx[al]] = s_ok[al] ? (M - s_q[al]) + log(S) - log((double)n_t) : NAN;
+}
+
 template <typename TQ, int TS, int NT, int ENG, bool DUMP>
-__global__ __launch_bounds__(NT) void k_contract(
+__device__ __forceinline__ void run_tile(
+    const ile_geom &g, int64_t base, const double *__restrict__ smp, int64_t N,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ shifts,
+    const TQ *__restrict__ Q, const double2 *__restrict__ U,
+    const double2 *__restrict__ V, double *__restrict__ out,
+    double *__restrict__ series)
+{
+    if constexpr (ENG == ENG_PH)
+        contract_tile_ph<TQ, TS, NT, DUMP>(g, base, smp, N, perm, shifts, Q, U, V, out, series);
+    else
+        contract_tile<TQ, TS, NT, ENG, DUMP>(g, base, smp, N, perm, shifts, Q, U, V, out, series);
+}
+
+// Waves per SIMD the register allocation must allow (the second bound of
+// __launch_bounds__): two eight-wave phased workgroups per CU, as many as
+// their LDS admits, are four waves per SIMD.
+template <int NT, int ENG> constexpr int contract_min_waves() { return ENG == ENG_PH && NT == 512 ? 4 : 1; }
+
+template <typename TQ, int TS, int NT, int ENG, bool DUMP>
+__global__ __launch_bounds__(NT, (contract_min_waves<NT, ENG>())) void k_contract(
     ile_geom g, const double *__restrict__ smp, int64_t N,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ shifts,
     const TQ *__restrict__ Q, const double2 *__restrict__ U,
     const double2 *__restrict__ V, double *__restrict__ out,
     double *__restrict__ series)
 {
-    contract_tile<TQ, TS, NT, ENG, DUMP>(g, (int64_t)blockIdx.x * TS, smp, N, perm, shifts,
-                                         Q, U, V, out, series);
+    run_tile<TQ, TS, NT, ENG, DUMP>(g, (int64_t)blockIdx.x * TS, smp, N, perm, shifts,
+                                    Q, U, V, out, series);
 }
 
 // Persistent form over many intrinsic points: every workgroup takes
 // (point, tile) items from a queue in list order (the host sorts the list by
 // decreasing cost) until it is empty; every wave reaches the exit.
 template <typename TQ, int TS, int NT, int ENG>
-__global__ __launch_bounds__(NT) void k_contract_batched(
+__global__ __launch_bounds__(NT, (contract_min_waves<NT, ENG>())) void k_contract_batched(
     const ile_geom *__restrict__ geoms, const ile_point_dev *__restrict__ pts,
     const int2 *__restrict__ items, int n_items, unsigned *counter)
 {
@@ -1088,13 +1512,14 @@ __global__ __launch_bounds__(NT) void k_contract_batched(
         __syncthreads();
         if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
         __syncthreads();
-        const int it = s_item;
+        // uniform, so the point's parameters load through the scalar unit
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
         if (it >= n_items) break;
         const int2 w = items[it];
         const ile_point_dev &P = pts[w.x];
-        contract_tile<TQ, TS, NT, ENG, false>(geoms[w.x], (int64_t)w.y * TS, P.smp, P.N,
-                                              P.perm, P.shifts, (const TQ *)P.Q, P.U, P.V,
-                                              P.out, nullptr);
+        run_tile<TQ, TS, NT, ENG, false>(geoms[w.x], (int64_t)w.y * TS, P.smp, P.N,
+                                         P.perm, P.shifts, (const TQ *)P.Q, P.U, P.V,
+                                         P.out, nullptr);
     }
 }
 
@@ -1298,6 +1723,61 @@ hipError_t launch_contract_t(const ile_geom &g, const double *smp, int64_t N,
     return hipGetLastError();
 }
 
+// Positions per G block of the phased engine (also its LDS row stride): the
+// largest that keeps the workgroup's dynamic LDS within `budget` bytes, an odd
+// multiple of 128 bytes so that the four rows of one store start in
+// alternate halves of the 256-byte bank period.  0 if none fits.
+int ph_wrow(int nd, int nl, size_t e, size_t budget)
+{
+    const size_t fixed = coef_bytes<ENG_MFMA>(16, nd, nl, e);
+    if (budget <= fixed) return 0;
+    const int unit = (int)(128 / e);
+    const int w = (int)((budget - fixed) / ((size_t)nd * 16 * e));
+    const int q = (w / unit - 1) / 2;
+    return q < 0 ? 0 : unit * (2 * q + 1);
+}
+
+constexpr size_t kPhBudget = 78 * 1024;   // two workgroups per CU
+
+template <typename TQ, int NT, bool DUMP>
+hipError_t launch_contract_ph(const ile_geom &g, const double *smp, int64_t N,
+                              const int32_t *perm, const int32_t *shifts, const void *Q,
+                              const double *U, const double *V, double *out, double *series,
+                              size_t dyn, hipStream_t st)
+{
+    // dynamic LDS above the default limit must be allowed per kernel
+    static size_t allowed = 0;
+    if (dyn > allowed) {
+        hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&k_contract<TQ, 16, NT, ENG_PH, DUMP>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+        if (e != hipSuccess) return e;
+        allowed = dyn;
+    }
+    hipLaunchKernelGGL((k_contract<TQ, 16, NT, ENG_PH, DUMP>), dim3(nblk(N, 16)), dim3(NT),
+                       dyn, st, g, smp, N, perm, shifts, (const TQ *)Q, (const double2 *)U,
+                       (const double2 *)V, out, series);
+    return hipGetLastError();
+}
+
+template <typename TQ, int NT>
+hipError_t launch_batched_ph(const ile_geom *geoms, const ile_point_dev *pts, const int2 *items,
+                             int n_items, unsigned *counter, int grid, size_t dyn,
+                             hipStream_t st)
+{
+    static size_t allowed = 0;
+    if (dyn > allowed) {
+        hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&k_contract_batched<TQ, 16, NT, ENG_PH>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+        if (e != hipSuccess) return e;
+        allowed = dyn;
+    }
+    hipLaunchKernelGGL((k_contract_batched<TQ, 16, NT, ENG_PH>), dim3(grid), dim3(NT), dyn, st,
+                       geoms, pts, items, n_items, counter);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ launchers
@@ -1353,6 +1833,21 @@ static int kernel_threads(const ile_tune &tu)
     return tu.engine == ENG_MFMA ? 2 * tu.threads : tu.threads;
 }
 
+static size_t ph_budget(const ile_tune &tu)
+{
+    return tu.lds_budget > 0 ? (size_t)tu.lds_budget : kPhBudget;
+}
+
+void ile_contract_prepare(ile_geom &g, ile_precision prec, const ile_tune &tu)
+{
+    if (tu.engine == ENG_PH && prec != ILE_BF16) {
+        const size_t e = prec == ILE_FP64 ? 8 : 4;
+        g.wrow = g.wcap = ph_wrow(g.n_det, g.n_lm, e, ph_budget(tu));
+    } else {
+        g.wrow = g.wcap = 0;
+    }
+}
+
 static size_t coef_bytes_of(const ile_geom &g, ile_precision prec, const ile_tune &tu, size_t e)
 {
     if (prec == ILE_BF16) return coef_bytes<ENG_BF16>(tu.tile_samples, g.n_det, g.n_lm, e);
@@ -1364,6 +1859,12 @@ size_t ile_contract_lds_bytes(const ile_geom &g, ile_precision prec,
                               const ile_tune &tu)
 {
     const size_t e = prec == ILE_FP64 ? 8 : 4;
+    if (tu.engine == ENG_PH && prec != ILE_BF16) {
+        const int w = ph_wrow(g.n_det, g.n_lm, e, ph_budget(tu));
+        // a block narrower than 32 positions cannot hold a 16-bin chunk
+        if (w < 32) return (size_t)1 << 30;
+        return ph_dyn_bytes(16, g.n_det, g.n_lm, w, e) + 2048;
+    }
     const size_t gs = (size_t)tu.tile_samples * (tu.engine == ENG_MFMA ? 2 : 1) * tu.threads * e;
     const size_t coef = coef_bytes_of(g, prec, tu, e);
     const size_t scr = prologue_scratch_bytes(tu.tile_samples, g.n_det, g.n_lm);
@@ -1373,6 +1874,9 @@ size_t ile_contract_lds_bytes(const ile_geom &g, ile_precision prec,
 bool ile_tune_supported(ile_precision prec, const ile_tune &tu)
 {
     if (tu.tile_samples != 16) return false;
+    // the phased engine takes FP64 and FP32 operands in workgroups of four
+    // or eight waves; its block width follows from the LDS budget
+    if (tu.engine == ENG_PH) return prec != ILE_BF16 && (tu.threads == 256 || tu.threads == 512);
     // positions per block: 256 or 512 for both engines; the matrix-core
     // engines also take 128 and 192 (smaller LDS, more workgroups per CU)
     const bool mf_only = tu.threads == 128 || tu.threads == 192;
@@ -1390,6 +1894,28 @@ hipError_t ile_launch_contract(const ile_geom &g, ile_precision prec,
 {
     if (N <= 0) return hipSuccess;
     if (!ile_tune_supported(prec, tu)) return hipErrorInvalidValue;
+    if (tu.engine == ENG_PH) {
+        ile_geom gp = g;
+        ile_contract_prepare(gp, prec, tu);
+        if (gp.wcap < 32) return hipErrorInvalidValue;
+        const size_t e = prec == ILE_FP64 ? 8 : 4;
+        // one 32-bit buffer range covers the whole series
+        if ((size_t)g.n_det * 4 * ksp_of(g.n_lm) * g.n_q * e > 0x7fffffffu)
+            return hipErrorInvalidValue;
+        const size_t dyn = ph_dyn_bytes(16, g.n_det, g.n_lm, gp.wrow, e);
+#define ILE_PH(TQ, NT)                                                                      \
+    return series ? launch_contract_ph<TQ, NT, true>(gp, smp, N, perm, shifts, Q, U, V, out,  \
+                                                     series, dyn, st)                        \
+                  : launch_contract_ph<TQ, NT, false>(gp, smp, N, perm, shifts, Q, U, V, out, \
+                                                      series, dyn, st)
+        if (prec == ILE_FP64) {
+            if (tu.threads == 256) ILE_PH(double, 256);
+            ILE_PH(double, 512);
+        }
+        if (tu.threads == 256) ILE_PH(float, 256);
+        ILE_PH(float, 512);
+#undef ILE_PH
+    }
 #define ILE_CONTRACT(TQ, NT, ENG) \
     return launch_contract_t<TQ, 16, NT, ENG>(g, smp, N, perm, shifts, Q, U, V, out, series, st)
     if (prec == ILE_FP64) {
@@ -1423,6 +1949,8 @@ hipError_t ile_launch_contract(const ile_geom &g, ile_precision prec,
 size_t ile_contract_dyn_bytes(const ile_geom &g, ile_precision prec, const ile_tune &tu)
 {
     const size_t e = prec == ILE_FP64 ? 8 : 4;
+    if (tu.engine == ENG_PH && prec != ILE_BF16)
+        return ph_dyn_bytes(16, g.n_det, g.n_lm, ph_wrow(g.n_det, g.n_lm, e, ph_budget(tu)), e);
     size_t dyn = coef_bytes_of(g, prec, tu, e);
     const size_t scr = prologue_scratch_bytes(tu.tile_samples, g.n_det, g.n_lm);
     if (scr > (size_t)tu.tile_samples * kernel_threads(tu) * e) dyn += scr;
@@ -1435,6 +1963,19 @@ hipError_t ile_launch_contract_batched(ile_precision prec, const ile_tune &tu,
                                        int grid, size_t dyn, hipStream_t st)
 {
     if (!ile_tune_supported(prec, tu)) return hipErrorInvalidValue;
+    if (tu.engine == ENG_PH) {
+        if (prec == ILE_FP64)
+            return tu.threads == 256
+                       ? launch_batched_ph<double, 256>(geoms, pts, items, n_items, counter, grid,
+                                                        dyn, st)
+                       : launch_batched_ph<double, 512>(geoms, pts, items, n_items, counter, grid,
+                                                        dyn, st);
+        return tu.threads == 256
+                   ? launch_batched_ph<float, 256>(geoms, pts, items, n_items, counter, grid, dyn,
+                                                   st)
+                   : launch_batched_ph<float, 512>(geoms, pts, items, n_items, counter, grid, dyn,
+                                                   st);
+    }
 #define ILE_BATCHED(TQ, NT, ENG)                                                              \
     do {                                                                                      \
         hipLaunchKernelGGL((k_contract_batched<TQ, 16, NT, ENG>), dim3(grid), dim3(NT), dyn,   \

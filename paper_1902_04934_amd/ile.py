@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libile.so")
+# ILE_LIB names another build of the library (the host-sanitizer build)
+LIB_PATH = os.environ.get("ILE_LIB") or os.path.join(HERE, "libile.so")
 
 ILE_OK, ILE_E_ARG, ILE_E_STATE, ILE_E_RANGE, ILE_E_NUMERIC, ILE_E_DEVICE, \
     ILE_E_NOMEM, ILE_E_UNSUPPORTED = range(8)
@@ -26,6 +27,7 @@ ILE_OPT_SORT = 0
 ILE_OPT_ENGINE = 1
 ILE_OPT_THREADS = 2
 ILE_OPT_HARVEST_ROWS = 3
+ILE_OPT_LDS_KB = 4
 
 
 class IleError(RuntimeError):
@@ -471,7 +473,7 @@ class Context:
     """One intrinsic point on one GPU: create + set_data, then evaluate."""
 
     def __init__(self, inst, precision="fp64", device=0, stream=None, sort=True,
-                 engine=None, threads=None):
+                 engine=None, threads=None, lds_kb=None):
         self.inst = inst
         self.n_t = inst.n_t
         self.h = ile_create(inst.dets, inst.modes, inst.srate_hz, inst.n_t,
@@ -484,9 +486,12 @@ class Context:
             if not sort:
                 ile_set_option(self.h, ILE_OPT_SORT, 0)
             if engine is not None:
-                ile_set_option(self.h, ILE_OPT_ENGINE, {"valu": 0, "mfma": 1}[engine])
+                ile_set_option(self.h, ILE_OPT_ENGINE,
+                               {"valu": 0, "mfma": 1, "pipelined": 2}[engine])
             if threads is not None:
                 ile_set_option(self.h, ILE_OPT_THREADS, threads)
+            if lds_kb is not None:
+                ile_set_option(self.h, ILE_OPT_LDS_KB, lds_kb)
         except Exception:
             self.close()
             raise

@@ -103,31 +103,56 @@ def test_config1_fp64_all_samples(torch, c1, sort):
     print(f"config1 sort={sort}: max |d lnLmargT| = {err:.3e}")
 
 
-@pytest.mark.parametrize("sort,engine,threads", [
-    (True, "mfma", 256), (False, "mfma", 256), (True, "mfma", 512), (False, "mfma", 512),
-    (True, "mfma", 192), (False, "mfma", 128), (True, "valu", 256), (False, "valu", 512)])
-def test_config2_shape_fp64(torch, c2_small, sort, engine, threads):
+# engine "mfma" is the phased matrix-core engine (threads = workgroup size,
+# 512 or 256; lds_kb = its LDS budget: 36 KiB leaves 48-position blocks, so
+# unsorted tiles run in many passes), "pipelined" the producer/consumer one
+# (threads = positions per block), "valu" the vector FMA engine
+ENGINES_FP64 = [
+    (True, "mfma", 512, None), (False, "mfma", 512, None), (True, "mfma", 256, None),
+    (False, "mfma", 512, 36), (True, "mfma", 256, 36),
+    (True, "pipelined", 256, None), (False, "pipelined", 512, None),
+    (True, "pipelined", 192, None), (False, "pipelined", 128, None),
+    (True, "valu", 256, None), (False, "valu", 512, None)]
+
+
+@pytest.mark.parametrize("sort,engine,threads,lds_kb", ENGINES_FP64)
+def test_config2_shape_fp64(torch, c2_small, sort, engine, threads, lds_kb):
     from oracle import oracle as O
     inst, s, lp, want = c2_small
-    with ile.Context(inst, sort=sort, engine=engine, threads=threads) as ctx:
+    with ile.Context(inst, sort=sort, engine=engine, threads=threads, lds_kb=lds_kb) as ctx:
         got = ctx.eval(s)
     err = check_margT(got, want, s, O.Ctx(inst), inst)
-    print(f"config2 shape, 3001 samples, sort={sort} {engine} {threads}: max err {err:.3e}")
+    print(f"config2 shape, 3001 samples, sort={sort} {engine} {threads} {lds_kb}: "
+          f"max err {err:.3e}")
 
 
-@pytest.mark.parametrize("engine,threads", [("mfma", 256), ("mfma", 512), ("mfma", 192),
-                                            ("valu", 256)])
-def test_sorted_and_unsorted_bit_identical(torch, c2_small, engine, threads):
-    """A sample's result does not depend on which tile it lands in: at a
-    fixed workgroup width the bins a thread owns, and so the order of the
-    log-sum-exp, are fixed; repeated runs are bit-identical too."""
+@pytest.mark.parametrize("engine,threads,lds_kb", [
+    ("mfma", 512, None), ("mfma", 256, None), ("mfma", 512, 36), ("pipelined", 256, None),
+    ("pipelined", 512, None), ("pipelined", 192, None), ("valu", 256, None)])
+def test_sorted_and_unsorted_bit_identical(torch, c2_small, engine, threads, lds_kb):
+    """A sample's result does not depend on which tile it lands in: for a
+    given engine and workgroup width the bins a thread owns, and so the order
+    of the log-sum-exp, are fixed (for the phased engine also whatever the
+    chunking and the pass its tile needs); repeated runs are bit-identical."""
     inst, s, _, _ = c2_small
-    with ile.Context(inst, sort=True, engine=engine, threads=threads) as a, \
-            ile.Context(inst, sort=False, engine=engine, threads=threads) as b:
+    with ile.Context(inst, sort=True, engine=engine, threads=threads, lds_kb=lds_kb) as a, \
+            ile.Context(inst, sort=False, engine=engine, threads=threads, lds_kb=lds_kb) as b:
         x, y = a.eval(s), b.eval(s)
         x2 = a.eval(s)
     assert np.array_equal(x, y)
     assert np.array_equal(x, x2)
+
+
+def test_phased_chunking_does_not_change_bits(torch, c2_small):
+    """The phased engine's chunk length follows its LDS budget, and a tile
+    too wide for the budget runs in passes; neither changes a result."""
+    inst, s, _, _ = c2_small
+    outs = []
+    for kb in (None, 100, 60, 36):
+        with ile.Context(inst, engine="mfma", threads=512, lds_kb=kb) as ctx:
+            outs.append(ctx.eval(s))
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
 
 
 def test_series_per_bin(torch):
@@ -144,7 +169,8 @@ def test_series_per_bin(torch):
 
 
 @pytest.mark.parametrize("precision,engine,threads", [
-    ("fp32", "mfma", 256), ("fp32", "mfma", 192), ("fp32", "valu", 256), ("bf16", "mfma", 256),
+    ("fp32", "mfma", 512), ("fp32", "mfma", 256), ("fp32", "pipelined", 256),
+    ("fp32", "pipelined", 192), ("fp32", "valu", 256), ("bf16", "mfma", 256),
     ("bf16", "mfma", 192), ("bf16", "mfma", 128)])
 def test_reduced_precision_config2_shape(torch, c2_small, precision, engine, threads):
     """FP32 and BF16 hi/lo bulk contraction with FP64 log-sum-exp: per-sample
