@@ -547,7 +547,9 @@ const char *ile_prop_last_error(const ile_prop *p);
  * is set by hand or by ile_batch_autotune, which times the candidates and
  * caches the winner in a text file keyed by device, precision and the
  * points' shapes.  Defaults: matrix cores, 2 workgroups per CU, queue by
- * cost; 512 positions for FP32, 128 for BF16, 256 for FP64. */
+ * cost.  Default tuning: FP64 and FP32 on the phased matrix-core engine in
+ * 512-thread workgroups, two per compute unit; BF16 on the pipelined engine
+ * at 128 positions per block. */
 typedef struct ile_batch ile_batch;
 
 typedef struct {
@@ -557,11 +559,15 @@ typedef struct {
 } ile_batch_config;
 
 typedef struct {
-    int32_t threads;          /* positions per block: 256 or 512; 128 or 192
-                                 with the matrix cores                       */
+    int32_t threads;          /* engine 1 for FP64/FP32: workgroup size, 256
+                                 or 512; engines 2 and 0 (and 1 for BF16):
+                                 positions per block, 256 or 512, 128 or 192
+                                 with the matrix cores (BF16: 128 .. 256)    */
     int32_t wgs_per_cu;       /* persistent workgroups per compute unit, 1..4 */
     int32_t order;            /* 0: queue by decreasing cost, 1: point order  */
-    int32_t engine;           /* 1 matrix cores, 0 vector FMA (not for BF16)  */
+    int32_t engine;           /* 1 matrix cores (phased for FP64/FP32,
+                                 pipelined for BF16), 2 matrix cores
+                                 pipelined, 0 vector FMA (not for BF16)      */
 } ile_batch_tuning;
 
 ile_status ile_batch_create(const ile_batch_config *cfg, ile_batch **out);

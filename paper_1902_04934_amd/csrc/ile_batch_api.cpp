@@ -109,11 +109,16 @@ void drop_graph(ile_batch *b)
     b->g_n = -1;
 }
 
-ile_tune point_tune(const ile_batch *b)
+// The per-point tuning of a batch tuning: engine 1 is the phased matrix-core
+// engine for FP64 and FP32 (threads = workgroup size) and the pipelined one
+// for BF16; engine 2 the pipelined one (threads = positions per block).
+ile_tune point_tune(ile_precision prec, const ile_batch_tuning &bt)
 {
-    ile_tune t{16, b->tune.threads, b->tune.engine};
+    const int eng = bt.engine == 0 ? 0 : (bt.engine == 1 && prec != ILE_BF16) ? 3 : 1;
+    ile_tune t{16, bt.threads, eng, 0};
     return t;
 }
+ile_tune point_tune(const ile_batch *b) { return point_tune(b->cfg.precision, b->tune); }
 
 // the per-point geometry with the batch's 15-bit ordering key
 ile_geom batched_geom(const ile_ctx *c)
@@ -213,6 +218,7 @@ ile_status build(ile_batch *b, int64_t n, double dmin, double dmax, bool ext)
     for (int p = 0; p < P; p++) tmax = std::min(tmax, gs[p].t_ref_max);
 
     hipStream_t st = b->stream;
+    BHIP(b, ile_contract_batched_allow(b->cfg.precision, tu, dyn));
     BHIP(b, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     const int grid = b->cu_count * b->tune.wgs_per_cu;
     hipError_t e = hipSuccess;
@@ -359,11 +365,13 @@ ile_status ile_batch_create(const ile_batch_config *cfg, ile_batch **out)
     b->cu_count = prop.multiProcessorCount;
     b->lds_max = (int)prop.sharedMemPerBlock;
     b->dev_name = prop.gcnArchName;
+    // FP64 and FP32: the phased matrix-core engine in eight-wave
+    // workgroups, two per CU (its LDS budget); BF16: the pipelined engine at
+    // 128 positions per block, measured fastest on 32 points of the
+    // 5-21-mode, 201-1601-bin mix at 1e6 draws each
     b->tune.engine = 1;
-    // measured on 32 points of the 5-21-mode, 201-1601-bin mix at 1e6 draws
-    // each: FP32 fastest at 512 positions, BF16 at 128
-    if (cfg->precision == ILE_FP32) b->tune.threads = 512;
-    if (cfg->precision == ILE_BF16) b->tune.threads = 128;
+    b->tune.threads = cfg->precision == ILE_BF16 ? 128 : 512;
+    b->tune.wgs_per_cu = 2;
     if (cfg->stream) {
         b->stream = (hipStream_t)cfg->stream;
     } else if (hipStreamCreate(&b->stream) != hipSuccess) {
@@ -461,11 +469,17 @@ ile_status ile_batch_set_tuning(ile_batch *b, const ile_batch_tuning *t)
     if (!t || (t->threads != 128 && t->threads != 192 && t->threads != 256 && t->threads != 512) ||
         t->wgs_per_cu < 1 ||
         t->wgs_per_cu > 4 || (t->order != 0 && t->order != 1) ||
-        (t->engine != 0 && t->engine != 1))
+        t->engine < 0 || t->engine > 2)
         return bfail(b, ILE_E_ARG, "bad tuning");
-    ile_tune tu{16, t->threads, t->engine};
+    const ile_tune tu = point_tune(b->cfg.precision, *t);
     if (!ile_tune_supported(b->cfg.precision, tu))
         return bfail(b, ILE_E_UNSUPPORTED, "tuning not supported for this precision");
+    // the persistent BF16 kernel of 512-position blocks (1024 threads) is
+    // not offered: under the 128-register cap of such workgroups it spills
+    // and returned non-finite values (the one-point kernel of that width
+    // does not spill and stays available)
+    if (b->cfg.precision == ILE_BF16 && tu.engine == 1 && tu.threads == 512)
+        return bfail(b, ILE_E_UNSUPPORTED, "BF16 batches take 128 to 256 positions per block");
     b->tune = *t;
     return ILE_OK;
 }
@@ -498,12 +512,16 @@ ile_status ile_batch_autotune(ile_batch *b, int64_t n, const char *cache_path)
                 return ILE_OK;
         }
     }
+    // candidates: the phased engine (workgroups of 256 or 512 threads), the
+    // pipelined and the vector engine (positions per block); tunings a
+    // precision does not take are skipped
     std::vector<ile_batch_tuning> cand;
-    const int engines = b->cfg.precision == ILE_BF16 ? 1 : 2;
-    for (int th : {128, 192, 256, 512})
-        for (int w : {1, 2, 3})
-            for (int o : {0, 1})
-                for (int en = 0; en < engines; en++) cand.push_back({th, w, o, 1 - en});
+    for (int w : {1, 2, 3})
+        for (int o : {0, 1}) {
+            for (int th : {256, 512}) cand.push_back({th, w, o, 1});
+            for (int th : {128, 192, 256, 512}) cand.push_back({th, w, o, 2});
+            for (int th : {256, 512}) cand.push_back({th, w, o, 0});
+        }
     ile_batch_tuning best = b->tune;
     double best_ms = 1e300;
     for (const ile_batch_tuning &t : cand) {

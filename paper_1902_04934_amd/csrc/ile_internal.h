@@ -229,6 +229,9 @@ hipError_t ile_launch_hist_refit(const int32_t *bins, int64_t ld, const double *
                                  double *C, hipStream_t st);
 // Batched form (ile_batch.hip + the persistent contraction).
 size_t ile_contract_dyn_bytes(const ile_geom &g, ile_precision prec, const ile_tune &tu);
+// Allows the persistent kernel of this tuning `dyn` bytes of dynamic LDS;
+// call outside stream capture, before ile_launch_contract_batched.
+hipError_t ile_contract_batched_allow(ile_precision prec, const ile_tune &tu, size_t dyn);
 hipError_t ile_launch_contract_batched(ile_precision prec, const ile_tune &tu,
                                        const ile_geom *geoms, const ile_point_dev *pts,
                                        const int2 *items, int n_items, unsigned *counter,

@@ -48,15 +48,12 @@ __device__ inline double delay_dev(const ile_geom &g, int k, double ra,
 
 // Antenna patterns from the detector tensor: polarization basis X, Y of a
 // source at hour angle h = ra - gmst, declination dec, rotated by psi;
-// F+ = X.D.X - Y.D.Y, Fx = X.D.Y + Y.D.X.
-__device__ inline void antenna_dev(const ile_geom &g, int k, double ra,
-                                   double dec, double psi, double &fp,
-                                   double &fx)
+// F+ = X.D.X - Y.D.Y, Fx = X.D.Y + Y.D.X.  tr = (sin h, cos h, sin dec,
+// cos dec, sin psi, cos psi).
+__device__ inline void antenna_trig(const ile_geom &g, int k, const double tr[6], double &fp,
+                                    double &fx)
 {
-    double sh, ch, sd, cd, sp, cp;
-    sincos(ra - g.gmst, &sh, &ch);
-    sincos(dec, &sd, &cd);
-    sincos(psi, &sp, &cp);
+    const double sh = tr[0], ch = tr[1], sd = tr[2], cd = tr[3], sp = tr[4], cp = tr[5];
     const double eE[3] = {-sh, ch, 0.0};
     const double eN[3] = {-sd * ch, -sd * sh, cd};
     double X[3], Y[3];
@@ -77,10 +74,28 @@ __device__ inline void antenna_dev(const ile_geom &g, int k, double ra,
          (Y[0] * DX[0] + Y[1] * DX[1] + Y[2] * DX[2]);
 }
 
+__device__ inline void antenna_dev(const ile_geom &g, int k, double ra,
+                                   double dec, double psi, double &fp,
+                                   double &fx)
+{
+    double tr[6];
+    sincos(ra - g.gmst, &tr[0], &tr[1]);
+    sincos(dec, &tr[2], &tr[3]);
+    sincos(psi, &tr[4], &tr[5]);
+    antenna_trig(g, k, tr, fp, fx);
+}
+
+// Per-sample tables of the tile prologue: the sines and cosines of the
+// antenna patterns, powers 0 .. 2 ILE_LMAX of cos(iota/2) and sin(iota/2),
+// and e^{i m phi} for |m| <= ILE_LMAX.
+constexpr int kPw = 2 * ILE_LMAX + 1;
+constexpr int kProTab = 6 + 2 * kPw + 2 * kPw;   // doubles per sample
+
 __host__ __device__ inline size_t prologue_scratch_bytes(int ts, int nd, int nl)
 {
-    // s_th[7][ts], s_Y[ts][nl], s_F[ts][nd] (complex), s_qp[ts][nd*nl]
-    return sizeof(double) * (size_t)ts * (7 + 2 * nl + 2 * nd + nd * nl);
+    // s_th[7][ts], s_Y[ts][nl], s_F[ts][nd] (complex), s_qp[ts][nd*nl],
+    // the per-sample tables [ts][kProTab]
+    return sizeof(double) * (size_t)ts * (7 + 2 * nl + 2 * nd + nd * nl + kProTab);
 }
 
 __device__ inline bool sample_ok(const ile_geom &g, const double th[7])
@@ -667,8 +682,10 @@ __device__ __forceinline__ void tile_prologue(
     double2 *s_Y = reinterpret_cast<double2 *>(scr + 7 * TS);   // [TS][nl]
     double2 *s_F = s_Y + TS * nl;                        // [TS][nd]
     double *s_qp = reinterpret_cast<double *>(s_F + TS * nd);   // [TS][nd*nl]
+    double *s_tab = s_qp + TS * nd * nl;                 // [TS][kProTab]
 
-    // 1. samples of the tile
+    // 1. samples of the tile and, one thread per sample, the trigonometry
+    //    every mode and detector of the sample shares
     if (tid < TS) {
         int64_t i = base + tid;
         int idx = -1, ok = 0;
@@ -693,110 +710,184 @@ __device__ __forceinline__ void tile_prologue(
         }
 #pragma unroll
         for (int p = 0; p < 7; p++) s_th[p * TS + tid] = th[p];
-    }
-    __syncthreads();
-
-    // 2. harmonics and antenna patterns
-    for (int t = tid; t < TS * (nl + nd); t += NT) {
-        if (t < TS * nl) {
-            int al = t / nl, a = t - al * nl;
-            if (g.ext_y)   // surrogate form: the sample's basis vector z
-                s_Y[al * nl + a] = s_ok[al] ? g.ext_y[(int64_t)s_idx[al] * nl + a]
-                                            : make_double2(0.0, 0.0);
-            else
-                s_Y[al * nl + a] = sylm_dev(g, a, s_th[4 * TS + al], s_th[3 * TS + al]);
-        } else {
-            int u = t - TS * nl;
-            int al = u / nd, k = u - al * nd;
-            double fp, fx;
-            antenna_dev(g, k, s_th[0 * TS + al], s_th[1 * TS + al],
-                        s_th[2 * TS + al], fp, fx);
-            s_F[al * nd + k] = make_double2(fp, fx);   // F = F+ + i Fx
+        double *tb = s_tab + tid * kProTab;
+        sincos(th[0] - g.gmst, &tb[0], &tb[1]);
+        sincos(th[1], &tb[2], &tb[3]);
+        sincos(th[2], &tb[4], &tb[5]);
+        // powers of cos(iota/2), sin(iota/2) by repeated products from 1
+        const double c = sqrt(0.5 * (1.0 + th[4])), sn = sqrt(0.5 * (1.0 - th[4]));
+        double *cp = tb + 6, *sp = cp + kPw;
+        double pc = 1.0, ps = 1.0;
+        cp[0] = sp[0] = 1.0;
+        for (int q = 1; q < kPw; q++) {
+            pc *= c;
+            ps *= sn;
+            cp[q] = pc;
+            sp[q] = ps;
+        }
+        // e^{i m phi} = (e^{i phi})^m, m = -ILE_LMAX .. ILE_LMAX
+        double2 *em = reinterpret_cast<double2 *>(sp + kPw);
+        double s1, c1;
+        sincos(th[3], &s1, &c1);
+        double er = 1.0, ei = 0.0;
+        em[ILE_LMAX] = make_double2(1.0, 0.0);
+        for (int m = 1; m <= ILE_LMAX; m++) {
+            const double r2 = er * c1 - ei * s1, i2 = er * s1 + ei * c1;
+            er = r2;
+            ei = i2;
+            em[ILE_LMAX + m] = make_double2(er, ei);
+            em[ILE_LMAX - m] = make_double2(er, -ei);
         }
     }
     __syncthreads();
 
-    // 3. coefficients c = (d_ref/D) F_k Y_lm and rows of the quadratic term;
-    //    modes a in [nl, 2 KS) are the zero padding of the MFMA K dimension
-    //    samples fastest, so the 16 lanes of one (k, a) read the same U, V row
+    // 2. harmonics -2Y_lm(iota, phi) (the Wigner-d sum over the mode's
+    //    terms, then e^{i m phi}), or the surrogate form's basis vectors, and
+    //    the antenna patterns F = F+ + i Fx
+    for (int t = tid; t < TS * (nl + nd); t += NT) {
+        if (t < TS * nl) {
+            const int al = t / nl, a = t - al * nl;
+            if (g.ext_y) {
+                s_Y[al * nl + a] = s_ok[al] ? g.ext_y[(int64_t)s_idx[al] * nl + a]
+                                            : make_double2(0.0, 0.0);
+            } else {
+                const double *cp = s_tab + al * kProTab + 6, *sp = cp + kPw;
+                const int t0 = g.mode_first[a], nt = g.mode_nterm[a];
+                double sum = 0.0;
+                for (int u = t0; u < t0 + nt; u++)
+                    sum += g.term_a[u] * cp[g.term_pc[u]] * sp[g.term_ps[u]];
+                const double2 e = reinterpret_cast<const double2 *>(sp + kPw)[ILE_LMAX + g.mode_m[a]];
+                s_Y[al * nl + a] = make_double2(sum * e.x, sum * e.y);
+            }
+        } else {
+            const int u = t - TS * nl;
+            const int al = u / nd, k = u - al * nd;
+            double fp, fx;
+            antenna_trig(g, k, s_tab + al * kProTab, fp, fx);
+            s_F[al * nd + k] = make_double2(fp, fx);
+        }
+    }
+    __syncthreads();
+
+    // 3. per detector: the coefficients c = (d_ref/D) F_k Y_lm in the
+    //    engine's operand layout (modes a in [nl, 2 KSP) are the zero padding
+    //    of the matrix-core K dimension), and the rows of the quadratic term
+    //    of Eq. (7).  Only the Hermitian part of U and the symmetric part of V
+    //    enter it (Re(Y^H U Y) = Y^H U_h Y, Y^T V Y = Y^T V_s Y), so each row
+    //    a sums over b >= a only, the off-diagonal terms twice:
+    //      row_a = |F|^2 (U_h,aa |Y_a|^2 + 2 Re(conj(Y_a) sum_{b>a} U_h,ab Y_b))
+    //            + Re(F^2 (V_s,aa Y_a^2 + 2 Y_a sum_{b>a} V_s,ab Y_b)).
+    //    A thread takes rows a and nl - 1 - a (nl - 1 terms together).
     if (ENG == ENG_BF16) {
         unsigned short *cz = reinterpret_cast<unsigned short *>(coef);
         for (int t = tid; t < nd * KSB * 64 * 8; t += NT) cz[t] = 0;
         __syncthreads();
     }
-    //    per detector; U_k and V_k are first copied to LDS after the
-    //    scratch when the G buffers have room for them (one round trip
-    //    instead of a dependent global load per term)
     const int nlp = ENG == ENG_MFMA ? 2 * KSP : nl;
+    const int npr = (nl + 1) / 2;
     const size_t uv_off = (scr_bytes + 15) & ~(size_t)15;
     const bool stage_uv = uv_off + 2 * (size_t)nl * nl * sizeof(double2) <= scr_cap;
     double2 *s_U = reinterpret_cast<double2 *>(reinterpret_cast<unsigned char *>(scr) + uv_off);
     double2 *s_V = s_U + nl * nl;
     for (int k = 0; k < nd; k++) {
-      if (stage_uv) {
-        for (int e = tid; e < nl * nl; e += NT) {
-            s_U[e] = U[(int64_t)k * nl * nl + e];
-            s_V[e] = V[(int64_t)k * nl * nl + e];
-        }
-        __syncthreads();
-      }
-      for (int t = tid; t < TS * nlp; t += NT) {
-        const int al = t % TS, a = t / TS;
-        double cx = 0.0, cy = 0.0, row = 0.0;
-        if (a < nl) {
-            double kap = s_ok[al] ? g.d_ref / s_th[5 * TS + al] : 0.0;
-            double2 F = s_F[al * nd + k];
-            double2 Ya = s_Y[al * nl + a];
-            double fyr = F.x * Ya.x - F.y * Ya.y, fyi = F.x * Ya.y + F.y * Ya.x;
-            cx = kap * fyr;
-            cy = kap * fyi;
-            // |F|^2 Re(conj(Y_a) (U Y)_a) + Re(F^2 Y_a (V Y)_a)
-            double uyr = 0, uyi = 0, vyr = 0, vyi = 0;
-            const double2 *Ur = stage_uv ? s_U + a * nl : U + ((int64_t)k * nl + a) * nl;
-            const double2 *Vr = stage_uv ? s_V + a * nl : V + ((int64_t)k * nl + a) * nl;
-            for (int b = 0; b < nl; b++) {
-                double2 Yb = s_Y[al * nl + b], u = Ur[b], v = Vr[b];
-                uyr += u.x * Yb.x - u.y * Yb.y;
-                uyi += u.x * Yb.y + u.y * Yb.x;
-                vyr += v.x * Yb.x - v.y * Yb.y;
-                vyi += v.x * Yb.y + v.y * Yb.x;
+        const double2 *Uk = U + (int64_t)k * nl * nl, *Vk = V + (int64_t)k * nl * nl;
+        if (stage_uv) {
+            for (int e = tid; e < nl * nl; e += NT) {
+                const int a = e / nl, b = e - a * nl;
+                const double2 u1 = Uk[e], u2 = Uk[b * nl + a], v1 = Vk[e], v2 = Vk[b * nl + a];
+                s_U[e] = make_double2(0.5 * (u1.x + u2.x), 0.5 * (u1.y - u2.y));
+                s_V[e] = make_double2(0.5 * (v1.x + v2.x), 0.5 * (v1.y + v2.y));
             }
-            double f2 = F.x * F.x + F.y * F.y;
-            double F2r = F.x * F.x - F.y * F.y, F2i = 2.0 * F.x * F.y;
-            double yvr = Ya.x * vyr - Ya.y * vyi, yvi = Ya.x * vyi + Ya.y * vyr;
-            row = f2 * (Ya.x * uyr + Ya.y * uyi) + (F2r * yvr - F2i * yvi);
-            s_qp[al * (nd * nl) + k * nl + a] = row;
+            __syncthreads();
         }
-        if (ENG == ENG_VALU) {
-            coef[((k * nl + a) * TS + al) * 2] = (TQ)cx;
-            coef[((k * nl + a) * TS + al) * 2 + 1] = (TQ)cy;
-        } else if (ENG == ENG_BF16) {
-            // A row k' of [C_hi, C_hi, C_lo]: lane = 16 (k' % 32 / 8) + alpha,
-            // element k' % 8, k-step k' / 32
-            __bf16 *cb = reinterpret_cast<__bf16 *>(coef) + (size_t)k * KSB * 64 * 8;
-            const int R = 2 * nl;
-            const double cv[2] = {cx, cy};
+        // coefficients: samples fastest, so the 16 lanes of one (k, a)
+        // write neighbouring operand slots
+        for (int t = tid; t < TS * nlp; t += NT) {
+            const int al = t % TS, a = t / TS;
+            double cx = 0.0, cy = 0.0;
+            if (a < nl) {
+                const double kap = s_ok[al] ? g.d_ref / s_th[5 * TS + al] : 0.0;
+                const double2 F = s_F[al * nd + k], Ya = s_Y[al * nl + a];
+                cx = kap * (F.x * Ya.x - F.y * Ya.y);
+                cy = kap * (F.x * Ya.y + F.y * Ya.x);
+            }
+            if (ENG == ENG_VALU) {
+                coef[((k * nl + a) * TS + al) * 2] = (TQ)cx;
+                coef[((k * nl + a) * TS + al) * 2 + 1] = (TQ)cy;
+            } else if (ENG == ENG_BF16) {
+                // A row k' of [C_hi, C_hi, C_lo]: lane = 16 (k' % 32 / 8) + alpha,
+                // element k' % 8, k-step k' / 32
+                __bf16 *cb = reinterpret_cast<__bf16 *>(coef) + (size_t)k * KSB * 64 * 8;
+                const int R = 2 * nl;
+                const double cv[2] = {cx, cy};
 #pragma unroll
-            for (int c = 0; c < 2; c++) {
-                const __bf16 hi = (__bf16)(float)cv[c];
-                const __bf16 lo = (__bf16)(float)(cv[c] - (double)(float)hi);
-                const int r = 2 * a + c;
-                const int kk[3] = {r, R + r, 2 * R + r};
-                const __bf16 vv[3] = {hi, hi, lo};
+                for (int c = 0; c < 2; c++) {
+                    const __bf16 hi = (__bf16)(float)cv[c];
+                    const __bf16 lo = (__bf16)(float)(cv[c] - (double)(float)hi);
+                    const int r = 2 * a + c;
+                    const int kk[3] = {r, R + r, 2 * R + r};
+                    const __bf16 vv[3] = {hi, hi, lo};
 #pragma unroll
-                for (int q = 0; q < 3; q++) {
-                    const int kp = kk[q];
-                    cb[((kp >> 5) * 64 + ((kp & 31) >> 3) * 16 + al) * 8 + (kp & 7)] = vv[q];
+                    for (int q = 0; q < 3; q++) {
+                        const int kp = kk[q];
+                        cb[((kp >> 5) * 64 + ((kp & 31) >> 3) * 16 + al) * 8 + (kp & 7)] = vv[q];
+                    }
                 }
+            } else {
+                // A operand of k-step ks: lane = 16 * (row within the step) + alpha
+                const int r0 = 2 * a;
+                coef[(k * KSP + (r0 >> 2)) * 64 + (r0 & 3) * 16 + al] = (TQ)cx;
+                coef[(k * KSP + (r0 >> 2)) * 64 + ((r0 & 3) + 1) * 16 + al] = (TQ)cy;
             }
-        } else {
-            // A operand of k-step ks: lane = 16 * (row within the step) + alpha
-            const int r0 = 2 * a;
-            coef[(k * KSP + (r0 >> 2)) * 64 + (r0 & 3) * 16 + al] = (TQ)cx;
-            coef[(k * KSP + (r0 >> 2)) * 64 + ((r0 & 3) + 1) * 16 + al] = (TQ)cy;
         }
-      }
-      if (stage_uv) __syncthreads();   // before the next detector's copy
+        // rows of the quadratic term, two per thread
+        for (int t = tid; t < TS * npr; t += NT) {
+            const int al = t % TS, pr = t / TS;
+            const double2 F = s_F[al * nd + k];
+            const double f2 = F.x * F.x + F.y * F.y;
+            const double F2r = F.x * F.x - F.y * F.y, F2i = 2.0 * F.x * F.y;
+            const double2 *Yr = s_Y + al * nl;
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const int a = h == 0 ? pr : nl - 1 - pr;
+                if (h == 1 && a == pr) break;
+                double ur = 0, ui = 0, vr = 0, vi = 0;
+                for (int b = a + 1; b < nl; b++) {
+                    const double2 Yb = Yr[b];
+                    double2 u, v;
+                    if (stage_uv) {
+                        u = s_U[a * nl + b];
+                        v = s_V[a * nl + b];
+                    } else {
+                        const double2 u1 = Uk[a * nl + b], u2 = Uk[b * nl + a];
+                        const double2 v1 = Vk[a * nl + b], v2 = Vk[b * nl + a];
+                        u = make_double2(0.5 * (u1.x + u2.x), 0.5 * (u1.y - u2.y));
+                        v = make_double2(0.5 * (v1.x + v2.x), 0.5 * (v1.y + v2.y));
+                    }
+                    ur += u.x * Yb.x - u.y * Yb.y;
+                    ui += u.x * Yb.y + u.y * Yb.x;
+                    vr += v.x * Yb.x - v.y * Yb.y;
+                    vi += v.x * Yb.y + v.y * Yb.x;
+                }
+                const double2 Ya = Yr[a];
+                double2 ud, vd;
+                if (stage_uv) {
+                    ud = s_U[a * nl + a];
+                    vd = s_V[a * nl + a];
+                } else {
+                    const double2 u1 = Uk[a * nl + a], v1 = Vk[a * nl + a];
+                    ud = u1;
+                    vd = v1;
+                }
+                // Y_a (V_s,aa Y_a + 2 w): the complex sum of the V part
+                const double wr = vd.x * Ya.x - vd.y * Ya.y + 2.0 * vr;
+                const double wi = vd.x * Ya.y + vd.y * Ya.x + 2.0 * vi;
+                const double yvr = Ya.x * wr - Ya.y * wi, yvi = Ya.x * wi + Ya.y * wr;
+                const double uq = ud.x * (Ya.x * Ya.x + Ya.y * Ya.y) + 2.0 * (Ya.x * ur + Ya.y * ui);
+                s_qp[al * (nd * nl) + k * nl + a] = f2 * uq + (F2r * yvr - F2i * yvi);
+            }
+        }
+        if (stage_uv) __syncthreads();   // before the next detector's copy
     }
     __syncthreads();
 
@@ -1314,7 +1405,7 @@ __device__ __forceinline__ void contract_tile_ph(
     __shared__ int s_idx[TS], s_ok[TS], s_pass[TS];
     __shared__ int s_d[ILE_MAX_DET][TS];
     __shared__ int s_smin[ILE_MAX_DET], s_spread[ILE_MAX_DET];
-    __shared__ int s_npass;
+    __shared__ int s_npass, s_wide;
     extern __shared__ __align__(16) unsigned char dyn_lds[];
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -1334,9 +1425,35 @@ __device__ __forceinline__ void contract_tile_ph(
                                         gbytes > sbytes ? gbytes : sbytes, coef, s_q, s_idx,
                                         s_ok, s_d);
 
-    // passes: greedy in tile order, each adds the samples that keep every
-    // detector's spread within wcap - 16 (one pass for all but rare tiles)
-    if (tid == 0) {
+    // passes: one over all valid samples when every detector's spread is
+    // within wcap - 16 (all but rare tiles: decided by a 16-lane reduction);
+    // else greedy in tile order, each pass adding the samples that keep the
+    // spreads within that bound
+    bool wide = false;
+    if (tid < TS) {
+        const bool v = s_ok[tid];
+        for (int k = 0; k < nd; k++) {
+            int lo = v ? s_d[k][tid] : 0x7fffffff, hi = v ? s_d[k][tid] : -1;
+            for (int off = 8; off > 0; off >>= 1) {
+                lo = min(lo, __shfl_xor(lo, off, 16));
+                hi = max(hi, __shfl_xor(hi, off, 16));
+            }
+            wide = wide || (hi >= 0 && hi - lo > wcap - 16);
+            // the window range of the single pass (recomputed per pass below
+            // for a wide tile)
+            if (tid == 0) {
+                s_smin[k] = hi >= 0 ? lo : 0;
+                s_spread[k] = hi >= 0 ? hi - lo : 0;
+            }
+        }
+        if (!wide) {
+            s_pass[tid] = v ? 0 : -1;
+            const bool any = __ballot(v) != 0;
+            if (tid == 0) s_npass = any ? 1 : 0;
+        }
+        if (tid == 0) s_wide = wide;
+    }
+    if (tid == 0 && wide) {
         const int lim = wcap - 16;
         int np = 0;
         for (int al = 0; al < TS; al++) s_pass[al] = -1;
@@ -1370,8 +1487,9 @@ __device__ __forceinline__ void contract_tile_ph(
     const int al = tid / LPS, sub = tid % LPS;
     double m = -INFINITY, ssum = 0.0;
     const int npass = s_npass;
+    const bool multi = s_wide;
     for (int p = 0; p < npass; p++) {
-        if (tid < nd) {
+        if (multi && tid < nd) {
             int lo = 0x7fffffff, hi = -1;
             for (int b = 0; b < TS; b++)
                 if (s_pass[b] == p) {
@@ -1521,6 +1639,23 @@ __global__ __launch_bounds__(NT, (contract_min_waves<NT, ENG>())) void k_contrac
                                          P.perm, P.shifts, (const TQ *)P.Q, P.U, P.V,
                                          P.out, nullptr);
     }
+}
+
+// Many intrinsic points on the phased engine: one workgroup per (point,
+// tile) item, in list order (the host sorts the list by decreasing cost and
+// the dispatcher starts workgroups in that order).  Not persistent: every
+// load of the point's parameters precedes the kernel's only store, so they
+// are read through the scalar unit instead of being held in registers
+// across a queue loop.
+template <typename TQ, int TS, int NT>
+__global__ __launch_bounds__(NT, (contract_min_waves<NT, ENG_PH>())) void k_contract_items(
+    const ile_geom *__restrict__ geoms, const ile_point_dev *__restrict__ pts,
+    const int2 *__restrict__ items)
+{
+    const int2 w = items[blockIdx.x];
+    const ile_point_dev &P = pts[w.x];
+    contract_tile_ph<TQ, TS, NT, false>(geoms[w.x], (int64_t)w.y * TS, P.smp, P.N, P.perm,
+                                        P.shifts, (const TQ *)P.Q, P.U, P.V, P.out, nullptr);
 }
 
 // --------------------------------------------------------------- prior
@@ -1760,21 +1895,31 @@ hipError_t launch_contract_ph(const ile_geom &g, const double *smp, int64_t N,
     return hipGetLastError();
 }
 
+// Allows the persistent phased kernel `dyn` bytes of dynamic LDS (outside
+// any stream capture: the batch calls it before capturing its graph).
 template <typename TQ, int NT>
-hipError_t launch_batched_ph(const ile_geom *geoms, const ile_point_dev *pts, const int2 *items,
-                             int n_items, unsigned *counter, int grid, size_t dyn,
-                             hipStream_t st)
+hipError_t allow_batched_ph(size_t dyn)
 {
     static size_t allowed = 0;
     if (dyn > allowed) {
         hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&k_contract_batched<TQ, 16, NT, ENG_PH>),
+            reinterpret_cast<const void *>(&k_contract_items<TQ, 16, NT>),
             hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
         if (e != hipSuccess) return e;
         allowed = dyn;
     }
-    hipLaunchKernelGGL((k_contract_batched<TQ, 16, NT, ENG_PH>), dim3(grid), dim3(NT), dyn, st,
-                       geoms, pts, items, n_items, counter);
+    return hipSuccess;
+}
+
+template <typename TQ, int NT>
+hipError_t launch_batched_ph(const ile_geom *geoms, const ile_point_dev *pts, const int2 *items,
+                             int n_items, size_t dyn, hipStream_t st)
+{
+    hipError_t e = allow_batched_ph<TQ, NT>(dyn);
+    if (e != hipSuccess) return e;
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_contract_items<TQ, 16, NT>), dim3((unsigned)n_items), dim3(NT), dyn, st,
+                       geoms, pts, items);
     return hipGetLastError();
 }
 
@@ -1957,6 +2102,15 @@ size_t ile_contract_dyn_bytes(const ile_geom &g, ile_precision prec, const ile_t
     return dyn;
 }
 
+hipError_t ile_contract_batched_allow(ile_precision prec, const ile_tune &tu, size_t dyn)
+{
+    if (tu.engine != ENG_PH || prec == ILE_BF16) return hipSuccess;
+    if (prec == ILE_FP64)
+        return tu.threads == 256 ? allow_batched_ph<double, 256>(dyn)
+                                 : allow_batched_ph<double, 512>(dyn);
+    return tu.threads == 256 ? allow_batched_ph<float, 256>(dyn) : allow_batched_ph<float, 512>(dyn);
+}
+
 hipError_t ile_launch_contract_batched(ile_precision prec, const ile_tune &tu,
                                        const ile_geom *geoms, const ile_point_dev *pts,
                                        const int2 *items, int n_items, unsigned *counter,
@@ -1964,17 +2118,14 @@ hipError_t ile_launch_contract_batched(ile_precision prec, const ile_tune &tu,
 {
     if (!ile_tune_supported(prec, tu)) return hipErrorInvalidValue;
     if (tu.engine == ENG_PH) {
+        // one workgroup per item (grid and counter are for the persistent
+        // kernels of the other engines)
         if (prec == ILE_FP64)
             return tu.threads == 256
-                       ? launch_batched_ph<double, 256>(geoms, pts, items, n_items, counter, grid,
-                                                        dyn, st)
-                       : launch_batched_ph<double, 512>(geoms, pts, items, n_items, counter, grid,
-                                                        dyn, st);
-        return tu.threads == 256
-                   ? launch_batched_ph<float, 256>(geoms, pts, items, n_items, counter, grid, dyn,
-                                                   st)
-                   : launch_batched_ph<float, 512>(geoms, pts, items, n_items, counter, grid, dyn,
-                                                   st);
+                       ? launch_batched_ph<double, 256>(geoms, pts, items, n_items, dyn, st)
+                       : launch_batched_ph<double, 512>(geoms, pts, items, n_items, dyn, st);
+        return tu.threads == 256 ? launch_batched_ph<float, 256>(geoms, pts, items, n_items, dyn, st)
+                                 : launch_batched_ph<float, 512>(geoms, pts, items, n_items, dyn, st);
     }
 #define ILE_BATCHED(TQ, NT, ENG)                                                              \
     do {                                                                                      \

@@ -47,9 +47,19 @@ def test_batch_matches_oracle(torch, points, precision, tol, rel):
             b.add_point(inst)
         assert b.n_points == len(points)
         _check_batch(b, points, 500, 2003, tol, rel)
-        # other tunings give the same answers
-        b.set_tuning(threads=512, wgs_per_cu=1, order=1, engine=1)
+        # other tunings give the same answers: the pipelined engine (the
+        # only BF16 one, which takes at most 256 positions per block in a
+        # batch), one workgroup per CU, queue in point order
+        b.set_tuning(threads=256 if precision == "bf16" else 512, wgs_per_cu=1, order=1,
+                     engine=2)
         _check_batch(b, points, 501, 2003, tol, rel)
+
+
+def test_batch_bf16_widest_pipelined_block_refused(torch, points):
+    with ile.Batch("bf16") as b:
+        b.add_point(points[0])
+        with pytest.raises(ile.IleError):
+            b.set_tuning(threads=512, wgs_per_cu=1, order=0, engine=2)
 
 
 def test_batch_graph_replay_deterministic(torch, points):
@@ -71,7 +81,8 @@ def test_batch_autotune_and_cache(torch, points, tmp_path):
         for inst in points[:3]:
             b.add_point(inst)
         t = b.autotune(1000, cache)
-        assert t["threads"] in (256, 512) and 1 <= t["wgs_per_cu"] <= 3
+        assert t["threads"] in (128, 192, 256, 512) and 1 <= t["wgs_per_cu"] <= 3
+        assert t["engine"] in (0, 1, 2)
         lines = open(cache).read().splitlines()
         assert len(lines) == 1 and lines[0].split()[1] == str(t["threads"])
         _check_batch(b, points[:3], 42, 1000, 1e-4, True)
