@@ -8,12 +8,24 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "ile.h"
 #include "ile_internal.h"
+
+// Workspace of ile_integrate_dev_noalloc: a fixed array that every GPU the
+// library runs on holds until the process ends.  Up to ILE_NOALLOC_MAX_N
+// samples: 8 (lnL) + 4 n_det (window starts) + 8 (keys, order) bytes each,
+// plus up to 2^21 + 1 bucket counts, their scan and the reduction partials.
+// Host code never passes `scratch` itself to a kernel (in host code the name
+// is a stand-in, not a device address): it takes the per-device address that
+// hipGetSymbolAddress returned in ile_create.
+constexpr size_t kNoAllocBytes =
+    (size_t)ILE_NOALLOC_MAX_N * (8 + 4 * ILE_MAX_DET + 8) + ((size_t)9 << 20);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 namespace {
 
@@ -113,6 +125,31 @@ void release(DevBuf &b)
     if (b.p) (void)hipFree(b.p);
     b.p = nullptr;
     b.bytes = 0;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch[kMaxDevices] = {};
+
+// Look up this device's copy of `scratch` once (device `dev` current).
+hipError_t scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[dev]) return hipSuccess;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch[dev] = (unsigned char *)p;
+    return hipSuccess;
+}
+
+unsigned char *scratch_of(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch[dev];
 }
 
 double fact(int n)
@@ -232,8 +269,59 @@ hipEvent_t next_event(ile_ctx *c)
     return c->ev[c->n_ev_used++];
 }
 
+// Device scratch of one evaluation: window starts, ordering keys, the sample
+// order, the bucket counts and their scan, the reduction's partials.
+struct Work {
+    int32_t *shifts;
+    uint32_t *keys;
+    int32_t *perm;
+    uint32_t *hist;
+    uint32_t *scan_tmp;
+    double *red_tmp;
+};
+
+Work ctx_work(ile_ctx *c)
+{
+    return Work{(int32_t *)c->shifts.p, (uint32_t *)c->keys.p, (int32_t *)c->perm.p,
+                (uint32_t *)c->hist.p, (uint32_t *)c->scan_tmp.p, (double *)c->red_tmp.p};
+}
+
 // The hot path on device data: window starts and ordering, then the fused
-// contraction / time marginalization.  Stream-ordered.
+// contraction / time marginalization.  Stream-ordered; allocates nothing.
+// timed: bracket the contraction with a pair of the context's events.
+ile_status launch_eval(ile_ctx *c, const Work &w, const double *smp, int64_t N, double *out,
+                       double *series, bool timed)
+{
+    if (N <= 0) return ILE_OK;
+    const size_t lds_need = ile_contract_lds_bytes(c->g, c->cfg.precision, c->tune);
+    if (lds_need > (size_t)c->lds_max)
+        return fail(c, ILE_E_UNSUPPORTED,
+                    "contraction needs %zu bytes of LDS per workgroup, device has %d",
+                    lds_need, c->lds_max);
+    hipStream_t st = c->stream;
+    HIP_TRY(c, ile_launch_fill_u32(w.hist, 0u, c->n_buckets, st));
+    HIP_TRY(c, ile_launch_prep(c->g, smp, N, w.shifts, w.keys, w.hist, c->n_buckets,
+                               (int32_t *)c->errflag.p, st));
+    if (c->sort) {
+        HIP_TRY(c, ile_launch_scan(w.hist, c->n_buckets, w.scan_tmp, st));
+        HIP_TRY(c, ile_launch_scatter(w.keys, N, w.hist, w.perm, st));
+    } else {
+        HIP_TRY(c, ile_launch_identity(w.perm, N, st));
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        e0 = next_event(c);
+        e1 = next_event(c);
+        if (!e0 || !e1) return fail(c, ILE_E_DEVICE, "hipEventCreate failed");
+        HIP_TRY(c, hipEventRecord(e0, st));
+    }
+    HIP_TRY(c, ile_launch_contract(c->g, c->cfg.precision, c->tune, smp, N, w.perm, w.shifts,
+                                   c->Q.p, (const double *)c->U.p, (const double *)c->V.p,
+                                   out, series, st));
+    if (timed) HIP_TRY(c, hipEventRecord(e1, st));
+    return ILE_OK;
+}
+
 ile_status run_eval(ile_ctx *c, const double *smp, int64_t N, double *out,
                     double *series)
 {
@@ -241,33 +329,7 @@ ile_status run_eval(ile_ctx *c, const double *smp, int64_t N, double *out,
     if (N > 0x7fffffff) return fail(c, ILE_E_ARG, "N = %lld exceeds 2^31-1", (long long)N);
     ile_status s = ensure_work(c, N);
     if (s) return s;
-    const size_t lds_need = ile_contract_lds_bytes(c->g, c->cfg.precision, c->tune);
-    if (lds_need > (size_t)c->lds_max)
-        return fail(c, ILE_E_UNSUPPORTED,
-                    "contraction needs %zu bytes of LDS per workgroup, device has %d",
-                    lds_need, c->lds_max);
-    hipStream_t st = c->stream;
-    uint32_t *hist = (uint32_t *)c->hist.p;
-    HIP_TRY(c, ile_launch_fill_u32(hist, 0u, c->n_buckets, st));
-    HIP_TRY(c, ile_launch_prep(c->g, smp, N, (int32_t *)c->shifts.p, (uint32_t *)c->keys.p,
-                               hist, c->n_buckets, (int32_t *)c->errflag.p, st));
-    if (c->sort) {
-        HIP_TRY(c, ile_launch_scan(hist, c->n_buckets, (uint32_t *)c->scan_tmp.p, st));
-        HIP_TRY(c, ile_launch_scatter((const uint32_t *)c->keys.p, N, hist,
-                                      (int32_t *)c->perm.p, st));
-    } else {
-        HIP_TRY(c, ile_launch_identity((int32_t *)c->perm.p, N, st));
-    }
-    hipEvent_t e0 = next_event(c), e1 = next_event(c);
-    if (!e0 || !e1) return fail(c, ILE_E_DEVICE, "hipEventCreate failed");
-    HIP_TRY(c, hipEventRecord(e0, st));
-    HIP_TRY(c, ile_launch_contract(c->g, c->cfg.precision, c->tune, smp, N,
-                                   (const int32_t *)c->perm.p,
-                                   (const int32_t *)c->shifts.p, c->Q.p,
-                                   (const double *)c->U.p, (const double *)c->V.p,
-                                   out, series, st));
-    HIP_TRY(c, hipEventRecord(e1, st));
-    return ILE_OK;
+    return launch_eval(c, ctx_work(c), smp, N, out, series, true);
 }
 
 void begin_call(ile_ctx *c)
@@ -378,7 +440,8 @@ ile_status ile_create(const ile_config *cfg, ile_ctx **out)
         return ILE_E_DEVICE;
     }
     if (hipDeviceGetAttribute(&c->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock,
-                              cfg->device) != hipSuccess) {
+                              cfg->device) != hipSuccess ||
+        scratch_setup(cfg->device) != hipSuccess) {
         delete c;
         return ILE_E_DEVICE;
     }
@@ -839,6 +902,43 @@ ile_status ile_integrate_dev(ile_ctx *c, const double *smp, const double *lp,
     if (N < 0 || !res || (N > 0 && !smp)) return fail(c, ILE_E_ARG, "bad N or pointer");
     if ((s = ensure_work(c, N))) return s;
     return integrate_dev_impl(c, smp, lp, lq, N, res);
+}
+
+ile_status ile_integrate_dev_noalloc(ile_ctx *c, const double *smp, const double *lp,
+                                     const double *lq, int64_t N, double *res)
+{
+    ile_status s = check_ready(c);
+    if (s) return s;
+    if (N < 0 || !res || (N > 0 && !smp)) return fail(c, ILE_E_ARG, "bad N or pointer");
+    if (N > ILE_NOALLOC_MAX_N)
+        return fail(c, ILE_E_ARG, "N = %lld exceeds the allocation-free limit of %lld samples",
+                    (long long)N, (long long)ILE_NOALLOC_MAX_N);
+    unsigned char *base = scratch_of(c->cfg.device);
+    if (!base || !c->errflag.p)
+        return fail(c, ILE_E_STATE, "no workspace on device %d", c->cfg.device);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char *p = base + off;
+        off += (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+        return p;
+    };
+    const size_t n = (size_t)std::max<int64_t>(N, 1);
+    double *out = (double *)take(n * sizeof(double));
+    Work w;
+    w.shifts = (int32_t *)take(n * c->g.n_det * sizeof(int32_t));
+    w.keys = (uint32_t *)take(n * sizeof(uint32_t));
+    w.perm = (int32_t *)take(n * sizeof(int32_t));
+    w.hist = (uint32_t *)take((size_t)c->n_buckets * sizeof(uint32_t));
+    w.scan_tmp = (uint32_t *)take((size_t)ile_scan_tmp_words(c->n_buckets) * 4 + 16);
+    w.red_tmp = (double *)take(4 * (size_t)ile_reduce_blocks() * sizeof(double));
+    double *parts = (double *)take(8 * sizeof(double));
+    if (off > kNoAllocBytes)
+        return fail(c, ILE_E_UNSUPPORTED, "workspace needs %zu bytes, the fixed array has %zu",
+                    off, kNoAllocBytes);
+    if ((s = launch_eval(c, w, smp, N, out, nullptr, false))) return s;
+    HIP_TRY(c, ile_launch_reduce(out, lp, lq, N, w.red_tmp, parts, c->stream));
+    HIP_TRY(c, ile_launch_finish(parts, 1, res, c->stream));
+    return ILE_OK;
 }
 
 static void copy_result(const double *r, ile_result *out)

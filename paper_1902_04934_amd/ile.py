@@ -28,6 +28,7 @@ ILE_OPT_ENGINE = 1
 ILE_OPT_THREADS = 2
 ILE_OPT_HARVEST_ROWS = 3
 ILE_OPT_LDS_KB = 4
+NOALLOC_MAX_N = 1048576   # ile_integrate_dev_noalloc: samples per call
 
 
 class IleError(RuntimeError):
@@ -143,6 +144,7 @@ def lib():
         L.ile_integrate.argtypes = [_vp, _dp, _dp, _dp, C.c_int64, C.POINTER(Result)]
         L.ile_eval_dev.argtypes = [_vp, _vp, C.c_int64, _vp]
         L.ile_integrate_dev.argtypes = [_vp, _vp, _vp, _vp, C.c_int64, _vp]
+        L.ile_integrate_dev_noalloc.argtypes = [_vp, _vp, _vp, _vp, C.c_int64, _vp]
         L.ile_set_data_fd.argtypes = [_vp, _dp, _dp, _dp, C.c_int64, C.c_double, C.c_double,
                                       C.c_double, C.c_double, C.POINTER(Detector), _dp, _dp, _dp]
         L.ile_qvu_fd_dev.argtypes = [_vp, _vp, _vp, _vp, C.c_int64, C.c_double, C.c_double,
@@ -298,6 +300,11 @@ def ile_eval_dev(h, samples_dev, n, out_dev):
 def ile_integrate_dev(h, samples_dev, ln_p_dev, ln_q_dev, n, result_dev):
     _check(lib().ile_integrate_dev(h, _dev(samples_dev), _dev(ln_p_dev),
                                    _dev(ln_q_dev), int(n), _dev(result_dev)), h)
+
+
+def ile_integrate_dev_noalloc(h, samples_dev, ln_p_dev, ln_q_dev, n, result_dev):
+    _check(lib().ile_integrate_dev_noalloc(h, _dev(samples_dev), _dev(ln_p_dev),
+                                           _dev(ln_q_dev), int(n), _dev(result_dev)), h)
 
 
 def ile_set_data_fd(h, h_f, d_f, psd, df, f_min, f_max, t0_s, dets, want_data=False):
@@ -510,6 +517,9 @@ class Context:
 
     def integrate_dev(self, samples_dev, ln_p_dev, ln_q_dev, n, result_dev):
         ile_integrate_dev(self.h, samples_dev, ln_p_dev, ln_q_dev, n, result_dev)
+
+    def integrate_dev_noalloc(self, samples_dev, ln_p_dev, ln_q_dev, n, result_dev):
+        ile_integrate_dev_noalloc(self.h, samples_dev, ln_p_dev, ln_q_dev, n, result_dev)
 
     def harvest_dev(self, samples_dev, ln_p_dev, ln_q_dev, n, u_dev, n_out, idx_dev,
                     bin_dev, theta_dev=None, result_dev=None):
