@@ -220,17 +220,17 @@ ile_status ile_integrate_dev(ile_ctx *ctx, const double *samples_dev,
  * tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
  * kernels and result as ile_integrate_dev; the call itself allocates
  * nothing (no hipMalloc, hipFree, event or library allocation): its
- * workspace (per-sample lnL, window starts, sort keys and order, bucket
- * counts, reduction partials) is a fixed array of about 41 MiB that every
- * GPU the library runs on holds until the process ends, located in
- * ile_create.  N <= ILE_NOALLOC_MAX_N, else ILE_E_ARG and nothing runs.
- * The array is shared by every context and call on one GPU and keeps the
+ * workspace (per-sample lnL, window starts, sort keys and order, the
+ * per-sample terms of Eq. (7), bucket counts, reduction partials) is a fixed
+ * array of 50 MiB that every GPU the library runs on holds until the
+ * process ends, located in ile_create.  N <= ILE_NOALLOC_MAX_N, else
+ * ILE_E_ARG and nothing runs.  The array is shared by every context and call on one GPU and keeps the
  * last call's contents (each call clears what must start at zero): calls
  * that overlap on one GPU (contexts on different streams) race; calls on
  * one stream are ordered.  A range error of a device-side sample is
  * reported by ile_sync, as for ile_integrate_dev.  The contraction's kernel
  * time is not recorded (ile_last_kernel_ms is unchanged). */
-#define ILE_NOALLOC_MAX_N 1048576
+#define ILE_NOALLOC_MAX_N 65536
 ile_status ile_integrate_dev_noalloc(ile_ctx *ctx, const double *samples_dev,
                                      const double *ln_p_dev, const double *ln_q_dev,
                                      int64_t N, double *result_dev);

@@ -18,13 +18,15 @@
 
 // Workspace of ile_integrate_dev_noalloc: a fixed array that every GPU the
 // library runs on holds until the process ends.  Up to ILE_NOALLOC_MAX_N
-// samples: 8 (lnL) + 4 n_det (window starts) + 8 (keys, order) bytes each,
-// plus up to 2^21 + 1 bucket counts, their scan and the reduction partials.
+// samples: 8 (lnL) + 4 n_det (window starts) + 8 (keys, order) + 8 (2 +
+// 3 n_det + 2 n_lm) (the phased engine's per-sample terms) bytes each, plus
+// up to 2^21 + 1 bucket counts, their scan and the reduction partials.
 // Host code never passes `scratch` itself to a kernel (in host code the name
 // is a stand-in, not a device address): it takes the per-device address that
 // hipGetSymbolAddress returned in ile_create.
 constexpr size_t kNoAllocBytes =
-    (size_t)ILE_NOALLOC_MAX_N * (8 + 4 * ILE_MAX_DET + 8) + ((size_t)9 << 20);
+    (size_t)ILE_NOALLOC_MAX_N * (8 + 4 * ILE_MAX_DET + 8 + 8 * (2 + 3 * ILE_MAX_DET + 2 * ILE_MAX_LM)) +
+    ((size_t)9 << 20);
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 namespace {
@@ -60,8 +62,9 @@ struct ile_ctx {
     ile_tune tune{16, 256, 1};
     int lds_max = 0;
     DevBuf Q, U, V;
+    DevBuf uvt;                     // upper triangles of U_h and V_s (see ile_launch_contract)
     DevBuf smp, out, lnp, lnq, shifts, keys, perm, hist, scan_tmp, errflag,
-        red_tmp, parts, res, series;
+        red_tmp, parts, res, series, terms;
     DevBuf hP, hC, bins, hist_tmp;  // adaptive proposal state and scratch
     int hist_nb = 0;
     DevBuf trx, trw;                // training set of the learned sampler
@@ -177,11 +180,12 @@ bool build_ylm_table(ile_geom &g, const std::vector<ile_mode> &modes)
             if (nt >= ILE_MAX_TERMS) return false;
             double a_k = norm / (fact(l + m - k) * fact(l - 2 - k) * fact(k) * fact(k + 2 - m));
             g.term_a[nt] = (k % 2 == 0) ? a_k : -a_k;
-            g.term_pc[nt] = (signed char)(2 * l + m - 2 - 2 * k);
-            g.term_ps[nt] = (signed char)(2 * k + 2 - m);
+            g.term_pw[nt] = (2 * l + m - 2 - 2 * k) | (2 * k + 2 - m) << 8;
             nt++;
             g.mode_nterm[a]++;
         }
+        g.n_pw = std::max(g.n_pw, 2 * l + 1);
+        g.m_max = std::max(g.m_max, std::abs(m));
     }
     return true;
 }
@@ -244,6 +248,13 @@ ile_status check_samples(ile_ctx *c, const double *s, int64_t N)
     return ILE_OK;
 }
 
+// Positions per launch of the per-sample terms for N samples.
+int64_t terms_cap(int64_t N)
+{
+    const int64_t n = std::min<int64_t>(std::max<int64_t>(N, 1), ILE_TERMS_CHUNK);
+    return (n + 15) & ~(int64_t)15;
+}
+
 ile_status ensure_work(ile_ctx *c, int64_t N)
 {
     ile_status s;
@@ -256,6 +267,9 @@ ile_status ensure_work(ile_ctx *c, int64_t N)
     if ((s = ensure(c, c->errflag, 16))) return s;
     if ((s = ensure(c, c->red_tmp, 4 * (size_t)ile_reduce_blocks() * sizeof(double)))) return s;
     if ((s = ensure(c, c->res, 8 * sizeof(double)))) return s;
+    if (ile_contract_uses_terms(c->cfg.precision, c->tune) &&
+        (s = ensure(c, c->terms, (size_t)ile_terms_fields(c->g) * terms_cap(N) * sizeof(double))))
+        return s;
     return ILE_OK;
 }
 
@@ -278,12 +292,15 @@ struct Work {
     uint32_t *hist;
     uint32_t *scan_tmp;
     double *red_tmp;
+    double *terms;   // per-sample terms of the phased engine, cap positions
+    int64_t cap;
 };
 
-Work ctx_work(ile_ctx *c)
+Work ctx_work(ile_ctx *c, int64_t N)
 {
     return Work{(int32_t *)c->shifts.p, (uint32_t *)c->keys.p, (int32_t *)c->perm.p,
-                (uint32_t *)c->hist.p, (uint32_t *)c->scan_tmp.p, (double *)c->red_tmp.p};
+                (uint32_t *)c->hist.p, (uint32_t *)c->scan_tmp.p, (double *)c->red_tmp.p,
+                (double *)c->terms.p, terms_cap(N)};
 }
 
 // The hot path on device data: window starts and ordering, then the fused
@@ -317,7 +334,8 @@ ile_status launch_eval(ile_ctx *c, const Work &w, const double *smp, int64_t N, 
     }
     HIP_TRY(c, ile_launch_contract(c->g, c->cfg.precision, c->tune, smp, N, w.perm, w.shifts,
                                    c->Q.p, (const double *)c->U.p, (const double *)c->V.p,
-                                   out, series, st));
+                                   (const double *)c->uvt.p, w.terms, w.cap, out, series,
+                                   st));
     if (timed) HIP_TRY(c, hipEventRecord(e1, st));
     return ILE_OK;
 }
@@ -329,7 +347,7 @@ ile_status run_eval(ile_ctx *c, const double *smp, int64_t N, double *out,
     if (N > 0x7fffffff) return fail(c, ILE_E_ARG, "N = %lld exceeds 2^31-1", (long long)N);
     ile_status s = ensure_work(c, N);
     if (s) return s;
-    return launch_eval(c, ctx_work(c), smp, N, out, series, true);
+    return launch_eval(c, ctx_work(c, N), smp, N, out, series, true);
 }
 
 void begin_call(ile_ctx *c)
@@ -597,6 +615,25 @@ ile_status ile_set_data(ile_ctx *c, const double *Q, int64_t n_q, double t0_s,
     }
     HIP_TRY(c, hipMemcpy(c->U.p, U, nUV * 16, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->V.p, V, nUV * 16, hipMemcpyHostToDevice));
+    // the Hermitian part of U and the symmetric part of V: the only parts
+    // the quadratic term of Eq. (7) sees (Re(Y^H U Y) = Y^H U_h Y,
+    // Y^T V Y = Y^T V_s Y)
+    // (upper triangles, row by row, U_h and V_s interleaved per entry)
+    {
+        std::vector<double> t;
+        t.reserve((size_t)nd * nl * (nl + 1) * 2);
+        for (int k = 0; k < nd; k++)
+            for (int a = 0; a < nl; a++)
+                for (int b = a; b < nl; b++) {
+                    const size_t e = ((size_t)k * nl + a) * nl + b, f = ((size_t)k * nl + b) * nl + a;
+                    t.push_back(0.5 * (U[2 * e] + U[2 * f]));
+                    t.push_back(0.5 * (U[2 * e + 1] - U[2 * f + 1]));
+                    t.push_back(0.5 * (V[2 * e] + V[2 * f]));
+                    t.push_back(0.5 * (V[2 * e + 1] + V[2 * f + 1]));
+                }
+        if ((s = ensure(c, c->uvt, t.size() * sizeof(double)))) return s;
+        HIP_TRY(c, hipMemcpy(c->uvt.p, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     if ((s = ensure(c, c->errflag, 16))) return s;
     HIP_TRY(c, hipMemset(c->errflag.p, 0, 16));
     c->have_data = true;
@@ -931,6 +968,8 @@ ile_status ile_integrate_dev_noalloc(ile_ctx *c, const double *smp, const double
     w.hist = (uint32_t *)take((size_t)c->n_buckets * sizeof(uint32_t));
     w.scan_tmp = (uint32_t *)take((size_t)ile_scan_tmp_words(c->n_buckets) * 4 + 16);
     w.red_tmp = (double *)take(4 * (size_t)ile_reduce_blocks() * sizeof(double));
+    w.cap = terms_cap(N);
+    w.terms = (double *)take((size_t)ile_terms_fields(c->g) * w.cap * sizeof(double));
     double *parts = (double *)take(8 * sizeof(double));
     if (off > kNoAllocBytes)
         return fail(c, ILE_E_UNSUPPORTED, "workspace needs %zu bytes, the fixed array has %zu",
@@ -1518,7 +1557,6 @@ ile_status ile_set_option(ile_ctx *c, ile_option opt, int64_t v)
         return fail(c, ILE_E_UNSUPPORTED, "tuning not supported for this precision");
     c->tune = t;
     return ILE_OK;
-    return fail(c, ILE_E_ARG, "unknown option %d", (int)opt);
 }
 
 double ile_last_kernel_ms(const ile_ctx *c) { return c ? c->last_ms : 0.0; }
@@ -1533,7 +1571,8 @@ void ile_destroy(ile_ctx *c)
                       &c->errflag, &c->red_tmp, &c->parts, &c->res, &c->series,
                       &c->hP, &c->hC, &c->bins, &c->hist_tmp, &c->trx, &c->trw,
                       &c->hv_w, &c->hv_cdf, &c->hv_ws, &c->hv_part, &c->hv_flag, &c->hv_sel,
-                      &c->fd_tmp, &c->fd_flag, &c->fd_in, &c->fd_out, &c->rom_A, &c->rom_Z})
+                      &c->fd_tmp, &c->fd_flag, &c->fd_in, &c->fd_out, &c->rom_A, &c->rom_Z,
+                      &c->uvt, &c->terms})
         release(*b);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);

@@ -48,8 +48,11 @@ struct ile_geom {
     int mode_first[ILE_MAX_LM];
     int mode_nterm[ILE_MAX_LM];
     double term_a[ILE_MAX_TERMS];
-    signed char term_pc[ILE_MAX_TERMS];
-    signed char term_ps[ILE_MAX_TERMS];
+    // the powers pc_t | ps_t << 8, 32-bit so that the kernels read them with
+    // scalar loads (a byte field of a kernel argument is a vector load)
+    int term_pw[ILE_MAX_TERMS];
+    int n_pw;                        // powers 0 .. n_pw - 1 of cos and sin(i/2) used
+    int m_max;                       // largest |m| of the modes
     // surrogate form: per-sample vectors z [N][n_lm] used in place of -2Y_lm
     // (the n_lm "modes" are then basis functions), or null
     const double2 *ext_y;
@@ -159,7 +162,7 @@ __device__ inline double2 sylm_dev(const ile_geom &g, int a, double cos_iota,
     double sum = 0.0;
     const int t0 = g.mode_first[a], nt = g.mode_nterm[a];
     for (int t = t0; t < t0 + nt; t++)
-        sum += g.term_a[t] * ipow(c, g.term_pc[t]) * ipow(s, g.term_ps[t]);
+        sum += g.term_a[t] * ipow(c, g.term_pw[t] & 255) * ipow(s, g.term_pw[t] >> 8);
     double sm, cm;
     sincos((double)g.mode_m[a] * phi, &sm, &cm);
     return make_double2(sum * cm, sum * sm);
@@ -195,11 +198,31 @@ int64_t ile_scan_tmp_words(int64_t n);
 hipError_t ile_launch_scatter(const uint32_t *keys, int64_t N, uint32_t *offs,
                               int32_t *perm, hipStream_t st);
 hipError_t ile_launch_identity(int32_t *perm, int64_t N, hipStream_t st);
+// Per-sample terms of Eq. (7) that the phased engine reads instead of
+// forming them in its tiles (kernel k_terms, run by ile_launch_contract
+// before the tiles that read them): for tile position i (sample perm[i])
+// the fields f = 0 .. F - 1 (F = ile_terms_fields) at terms[16 F (r / 16) +
+// 16 f + r % 16], r = i - t0, t0 the first position of the launch (a
+// tile's fields are contiguous): q (the quadratic term), a validity flag (1
+// or 0), (d_ref/D) F_k (re, im) for each detector, -2Y_lm (re, im) for
+// each mode, then the window start of each detector; q, the F_k and the
+// window starts are zero for an invalid sample.
+int ile_terms_fields(const ile_geom &g);
+bool ile_contract_uses_terms(ile_precision prec, const ile_tune &tu);
+// Positions per launch of the terms (a multiple of 16): the buffer for N
+// samples holds ile_terms_fields x min(N, ILE_TERMS_CHUNK) doubles.
+#define ILE_TERMS_CHUNK ((int64_t)1 << 21)
+// uvt: per detector the upper triangles of the Hermitian part of U and the
+// symmetric part of V, row by row, entry (a, b >= a) at 4 (a n_lm -
+// a (a - 1) / 2 + b - a) as (Re U_h, Im U_h, Re V_s, Im V_s); terms: a buffer
+// of ile_terms_fields x cap doubles, cap >= 16 a multiple of 16 (both used
+// when ile_contract_uses_terms, else may be null).
 hipError_t ile_launch_contract(const ile_geom &g, ile_precision prec,
                                const ile_tune &tu, const double *smp, int64_t N,
                                const int32_t *perm, const int32_t *shifts,
                                const void *Q, const double *U, const double *V,
-                               double *out, double *series, hipStream_t st);
+                               const double *uvt, double *terms, int64_t cap, double *out,
+                               double *series, hipStream_t st);
 size_t ile_contract_lds_bytes(const ile_geom &g, ile_precision prec,
                               const ile_tune &tu);
 hipError_t ile_launch_prior(uint64_t seed, int64_t first, int64_t N,

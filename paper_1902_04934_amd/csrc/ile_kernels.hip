@@ -755,7 +755,7 @@ __device__ __forceinline__ void tile_prologue(
                 const int t0 = g.mode_first[a], nt = g.mode_nterm[a];
                 double sum = 0.0;
                 for (int u = t0; u < t0 + nt; u++)
-                    sum += g.term_a[u] * cp[g.term_pc[u]] * sp[g.term_ps[u]];
+                    sum += g.term_a[u] * cp[g.term_pw[u] & 255] * sp[g.term_pw[u] >> 8];
                 const double2 e = reinterpret_cast<const double2 *>(sp + kPw)[ILE_LMAX + g.mode_m[a]];
                 s_Y[al * nl + a] = make_double2(sum * e.x, sum * e.y);
             }
@@ -903,6 +903,199 @@ __device__ __forceinline__ void tile_prologue(
         }
     }
     __syncthreads();
+}
+
+// ------------------------------------------------- per-sample terms
+// The per-sample part of Eq. (7) for the phased engine, one lane per sample
+// in tile order, so that it runs once per sample over the whole GPU rather
+// than in one wave of each tile while the tile's other waves wait: the
+// harmonics -2Y_lm(iota, phi) (Wigner-d terms times e^{i m phi}, or the
+// surrogate form's vectors), the antenna patterns, the coefficient factors
+// (d_ref/D) F_k and the quadratic term
+//   q = (d_ref/D)^2 / 4 sum_k [ |F_k|^2 Y^H U_h,k Y + Re(F_k^2 Y^T V_s,k Y) ]
+// with U_h the Hermitian part of U_k and V_s the symmetric part of V_k, so
+// that only b >= a enters (the off-diagonal terms twice): per detector the
+// host packs the upper triangles row by row, entry (a, b >= a) at
+// 4 (a nl - a (a - 1) / 2 + b - a) as (Re U_h, Im U_h, Re V_s, Im V_s).
+// Output: tile-major, field f of position t0 + r at
+// terms[16 F (r / 16) + 16 f + r % 16].
+
+// One lane's sample: its validity, window starts, the sines and cosines of
+// the antenna angles, d_ref/D, and the tables the harmonics are read from:
+// powers of cos and sin of iota/2 and e^{i m phi}, register arrays (of the
+// caller, so that they stay in registers) read at indices that are the same
+// in every lane.
+struct TermsSample {
+    int idx, ok;
+    int sd[ILE_MAX_DET];
+    double tr[6], kap;
+};
+
+__device__ __forceinline__ void terms_intake(const ile_geom &g, const double *__restrict__ smp,
+                                             int64_t N, const int32_t *__restrict__ perm,
+                                             const int32_t *__restrict__ shifts, int64_t i,
+                                             TermsSample &S, double (&cp)[kPw],
+                                             double (&sp)[kPw], double (&er)[kPw],
+                                             double (&ei)[kPw])
+{
+    const int nd = g.n_det;
+    S.idx = perm[i];
+    double th[7];
+#pragma unroll
+    for (int p = 0; p < 7; p++) th[p] = smp[(int64_t)p * N + S.idx];
+#pragma unroll
+    for (int k = 0; k < ILE_MAX_DET; k++) S.sd[k] = k < nd ? shifts[(int64_t)k * N + S.idx] : 0;
+    bool ok = sample_ok(g, th);
+#pragma unroll
+    for (int k = 0; k < ILE_MAX_DET; k++)
+        ok = ok & (k >= nd || (S.sd[k] >= 0 && S.sd[k] <= g.s_max));
+    S.ok = ok;
+    if (!ok) {
+        th[0] = th[1] = th[2] = th[3] = th[4] = th[6] = 0.0;
+        th[5] = 1.0;
+    }
+    sincos(th[0] - g.gmst, &S.tr[0], &S.tr[1]);
+    sincos(th[1], &S.tr[2], &S.tr[3]);
+    sincos(th[2], &S.tr[4], &S.tr[5]);
+    S.kap = ok ? g.d_ref / th[5] : 0.0;
+    // powers of cos(iota/2), sin(iota/2) by repeated products from 1, and
+    // e^{i m phi} = (e^{i phi})^m, |m| <= ILE_LMAX
+    const double c = sqrt(0.5 * (1.0 + th[4])), sn = sqrt(0.5 * (1.0 - th[4]));
+    cp[0] = sp[0] = 1.0;
+#pragma unroll
+    for (int q = 1; q < kPw; q++) {
+        cp[q] = cp[q - 1] * c;
+        sp[q] = sp[q - 1] * sn;
+    }
+    double s1, c1;
+    sincos(th[3], &s1, &c1);
+    er[ILE_LMAX] = 1.0;
+    ei[ILE_LMAX] = 0.0;
+#pragma unroll
+    for (int m = 1; m <= ILE_LMAX; m++) {
+        const double pr = er[ILE_LMAX + m - 1], pi = ei[ILE_LMAX + m - 1];
+        er[ILE_LMAX + m] = pr * c1 - pi * s1;
+        ei[ILE_LMAX + m] = pr * s1 + pi * c1;
+        er[ILE_LMAX - m] = er[ILE_LMAX + m];
+        ei[ILE_LMAX - m] = -ei[ILE_LMAX + m];
+    }
+}
+
+// -2Y_lm of mode a: the mode's Wigner-d terms, then e^{i m phi}; or the
+// surrogate form's vector entry.
+__device__ __forceinline__ double2 terms_harmonic(const ile_geom &g, const TermsSample &S, int a,
+                                                  const double (&cp)[kPw],
+                                                  const double (&sp)[kPw],
+                                                  const double (&er)[kPw],
+                                                  const double (&ei)[kPw])
+{
+    if (g.ext_y) return S.ok ? g.ext_y[(int64_t)S.idx * g.n_lm + a] : make_double2(0.0, 0.0);
+    const int u0 = g.mode_first[a], nt = g.mode_nterm[a];
+    double sum = 0.0;
+    for (int u = u0; u < u0 + nt; u++)
+        sum += g.term_a[u] * cp[g.term_pw[u] & 255] * sp[g.term_pw[u] >> 8];
+    const int mi = ILE_LMAX + g.mode_m[a];
+    return make_double2(sum * er[mi], sum * ei[mi]);
+}
+
+// Row a of detector k's part of the quadratic term (the b > a sums w_U, w_V
+// over the row's entries given), with f2 = |F|^2 and F^2 = (F2r, F2i).
+__device__ __forceinline__ double terms_row(double2 Ya, double4 d, double ur, double ui,
+                                            double vr, double vi, double f2, double F2r,
+                                            double F2i)
+{
+    // Y_a (V_s,aa Y_a + 2 w_V): the complex sum of the V part
+    const double wr = d.z * Ya.x - d.w * Ya.y + 2.0 * vr;
+    const double wi = d.z * Ya.y + d.w * Ya.x + 2.0 * vi;
+    const double yvr = Ya.x * wr - Ya.y * wi, yvi = Ya.x * wi + Ya.y * wr;
+    const double uq = d.x * (Ya.x * Ya.x + Ya.y * Ya.y) + 2.0 * (Ya.x * ur + Ya.y * ui);
+    return f2 * uq + (F2r * yvr - F2i * yvi);
+}
+
+__device__ __forceinline__ void terms_mac(double2 Yb, double4 e, double &ur, double &ui,
+                                          double &vr, double &vi)
+{
+    ur = fma(e.x, Yb.x, fma(-e.y, Yb.y, ur));
+    ui = fma(e.x, Yb.y, fma(e.y, Yb.x, ui));
+    vr = fma(e.z, Yb.x, fma(-e.w, Yb.y, vr));
+    vi = fma(e.z, Yb.y, fma(e.w, Yb.x, vi));
+}
+
+__device__ __forceinline__ void terms_store(const ile_geom &g, const TermsSample &S, double q,
+                                            double *tp)
+{
+    const int nd = g.n_det, nl = g.n_lm;
+    tp[0] = 0.25 * S.kap * S.kap * q;
+    tp[16] = S.ok ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < ILE_MAX_DET; k++)
+        if (k < nd) tp[(2 + 2 * nd + 2 * nl + k) * 16] = S.ok ? (double)S.sd[k] : 0.0;
+}
+
+__device__ __forceinline__ double *terms_slot(const ile_geom &g, double *terms, int64_t r)
+{
+    return terms + (r >> 4) * (16 * (int64_t)(2 + 3 * g.n_det + 2 * g.n_lm)) + (r & 15);
+}
+
+constexpr int kTermsT = 64;    // lanes per block
+
+// Any number of modes: a lane's harmonics are an LDS row of 64 lanes
+// (conflict free, and no lane reads another's: no barrier); the triangles
+// are read at uniform addresses (scalar loads), four entries per step.
+__global__ __launch_bounds__(kTermsT) void k_terms(
+    ile_geom g, const double *__restrict__ smp, int64_t N, const int32_t *__restrict__ perm,
+    const int32_t *__restrict__ shifts, const double4 *__restrict__ uvt, int64_t t0, int64_t n,
+    double *__restrict__ terms)
+{
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
+    const int lane = threadIdx.x;
+    const int64_t r = (int64_t)blockIdx.x * kTermsT + lane;   // position t0 + r
+    if (r >= n) return;
+    const int nd = g.n_det, nl = g.n_lm, ntri = nl * (nl + 1) / 2;
+    double2 *Yl = reinterpret_cast<double2 *>(dyn_lds);   // [nl][64]
+    double *tp = terms_slot(g, terms, r);
+    TermsSample S;
+    double cp[kPw], sp[kPw], er[kPw], ei[kPw];
+    terms_intake(g, smp, N, perm, shifts, t0 + r, S, cp, sp, er, ei);
+    for (int a = 0; a < nl; a++) {
+        const double2 y = terms_harmonic(g, S, a, cp, sp, er, ei);
+        Yl[a * kTermsT + lane] = y;
+        tp[(2 + 2 * nd + 2 * a) * 16] = y.x;
+        tp[(3 + 2 * nd + 2 * a) * 16] = y.y;
+    }
+    double qs = 0.0;
+    for (int k = 0; k < nd; k++) {
+        double fp, fx;
+        antenna_trig(g, k, S.tr, fp, fx);
+        tp[(2 + 2 * k) * 16] = S.kap * fp;
+        tp[(3 + 2 * k) * 16] = S.kap * fx;
+        const double f2 = fp * fp + fx * fx, F2r = fp * fp - fx * fx, F2i = 2.0 * fp * fx;
+        const double4 *row = uvt + (int64_t)k * ntri;
+        for (int a = 0; a < nl; a++) {
+            double ur = 0, ui = 0, vr = 0, vi = 0;
+            int b = a + 1;
+            for (; b + 3 < nl; b += 4) {
+                double2 Yb[4];
+                double4 e[4];
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    Yb[q] = Yl[(b + q) * kTermsT + lane];
+                    e[q] = row[b + q - a];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; q++) terms_mac(Yb[q], e[q], ur, ui, vr, vi);
+            }
+            for (; b < nl; b++) terms_mac(Yl[b * kTermsT + lane], row[b - a], ur, ui, vr, vi);
+            qs += terms_row(Yl[a * kTermsT + lane], row[0], ur, ui, vr, vi, f2, F2r, F2i);
+            row += nl - a;
+        }
+    }
+    terms_store(g, S, qs, tp);
+}
+
+static size_t terms_lds_bytes(const ile_geom &g)
+{
+    return (size_t)kTermsT * g.n_lm * sizeof(double2);
 }
 
 // One tile: samples perm[base .. base + TS) of a point (those below N).
@@ -1390,13 +1583,16 @@ __device__ __forceinline__ void ph_lphase(const TQ *G, const int (&go)[ILE_MAX_D
     if (i < Jc) fold(xsum(i));
 }
 
-template <typename TQ, int TS, int NT, bool DUMP>
+// PRE: the per-sample terms come from k_terms (the tile's block of the
+// terms, tile-major from position t0), else the tile forms them
+// (tile_prologue).
+template <typename TQ, int TS, int NT, bool DUMP, bool PRE>
 __device__ __forceinline__ void contract_tile_ph(
     const ile_geom &g, int64_t base, const double *__restrict__ smp, int64_t N,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ shifts,
     const TQ *__restrict__ Q, const double2 *__restrict__ U,
-    const double2 *__restrict__ V, double *__restrict__ out,
-    double *__restrict__ series)
+    const double2 *__restrict__ V, const double *__restrict__ terms, int64_t t0,
+    double *__restrict__ out, double *__restrict__ series)
 {
     static_assert(TS == 16 && (NT == 256 || NT == 512), "phased tile: 16 samples, 4 or 8 waves");
     constexpr int NW = NT / 64;    // waves
@@ -1420,10 +1616,59 @@ __device__ __forceinline__ void contract_tile_ph(
     // one buffer resource over all of Q (the host keeps it below 2 GiB)
     const __amdgpu_buffer_rsrc_t rs = q_rsrc<TQ>(Q, nd * RP * nq * (int)sizeof(TQ));
 
-    tile_prologue<TQ, TS, NT, ENG_MFMA>(g, base, smp, N, perm, shifts, U, V,
-                                        reinterpret_cast<double *>(G),
-                                        gbytes > sbytes ? gbytes : sbytes, coef, s_q, s_idx,
-                                        s_ok, s_d);
+    if constexpr (PRE) {
+        // samples, validity, window starts and q of the tile; the
+        // coefficients c = (d_ref/D) F_k Y_lm in the matrix-core A layout
+        // (modes a in [nl, 2 KSP) are the zero padding of K)
+        const double *tb = terms + ((base - t0) >> 4) * (16 * (int64_t)(2 + 3 * nd + 2 * nl));
+        if (tid < TS) {
+            const int64_t i = base + tid;
+            int idx = -1, ok = 0;
+            double q = 0.0;
+            if (i < N) {
+                const double *tk = tb + tid;
+                idx = perm[i];
+                ok = tk[16] != 0.0;
+                q = tk[0];
+                for (int k = 0; k < nd; k++) s_d[k][tid] = (int)tk[(2 + 2 * nd + 2 * nl + k) * 16];
+            } else {
+                for (int k = 0; k < nd; k++) s_d[k][tid] = 0;
+            }
+            s_idx[tid] = idx;
+            s_ok[tid] = ok;
+            s_q[tid] = q;
+        }
+        // the factors (d_ref/D) F_k and -2Y_lm of the tile's samples to LDS
+        // (the free G blocks) in one round of loads, then the products
+        double *s_fy = reinterpret_cast<double *>(G);   // [2 (nd + nl)][TS]
+        const int nfy = 2 * (nd + nl);
+        for (int t = tid; t < TS * nfy; t += NT)
+            s_fy[t] = base + t % TS < N ? tb[2 * TS + t] : 0.0;
+        __syncthreads();
+        const int nlp = 2 * KSP;
+        for (int t = tid; t < TS * nd * nlp; t += NT) {
+            const int al = t % TS, r = t / TS, k = r / nlp, a = r - k * nlp;
+            double cx = 0.0, cy = 0.0;
+            if (a < nl) {
+                const double fr = s_fy[(2 * k) * TS + al], fi = s_fy[(2 * k + 1) * TS + al];
+                const double yr = s_fy[(2 * nd + 2 * a) * TS + al];
+                const double yi = s_fy[(2 * nd + 2 * a + 1) * TS + al];
+                cx = fr * yr - fi * yi;
+                cy = fr * yi + fi * yr;
+            }
+            const int r0 = 2 * a;
+            coef[(k * KSP + (r0 >> 2)) * 64 + (r0 & 3) * 16 + al] = (TQ)cx;
+            coef[(k * KSP + (r0 >> 2)) * 64 + ((r0 & 3) + 1) * 16 + al] = (TQ)cy;
+        }
+        (void)gbytes;
+        (void)sbytes;
+        __syncthreads();
+    } else {
+        tile_prologue<TQ, TS, NT, ENG_MFMA>(g, base, smp, N, perm, shifts, U, V,
+                                            reinterpret_cast<double *>(G),
+                                            gbytes > sbytes ? gbytes : sbytes, coef, s_q,
+                                            s_idx, s_ok, s_d);
+    }
 
     // passes: one over all valid samples when every detector's spread is
     // within wcap - 16 (all but rare tiles: decided by a 16-lane reduction);
@@ -1595,7 +1840,8 @@ __device__ __forceinline__ void run_tile(
     double *__restrict__ series)
 {
     if constexpr (ENG == ENG_PH)
-        contract_tile_ph<TQ, TS, NT, DUMP>(g, base, smp, N, perm, shifts, Q, U, V, out, series);
+        contract_tile_ph<TQ, TS, NT, DUMP, false>(g, base, smp, N, perm, shifts, Q, U, V,
+                                                  nullptr, 0, out, series);
     else
         contract_tile<TQ, TS, NT, ENG, DUMP>(g, base, smp, N, perm, shifts, Q, U, V, out, series);
 }
@@ -1654,8 +1900,24 @@ __global__ __launch_bounds__(NT, (contract_min_waves<NT, ENG_PH>())) void k_cont
 {
     const int2 w = items[blockIdx.x];
     const ile_point_dev &P = pts[w.x];
-    contract_tile_ph<TQ, TS, NT, false>(geoms[w.x], (int64_t)w.y * TS, P.smp, P.N, P.perm,
-                                        P.shifts, (const TQ *)P.Q, P.U, P.V, P.out, nullptr);
+    contract_tile_ph<TQ, TS, NT, false, false>(geoms[w.x], (int64_t)w.y * TS, P.smp, P.N,
+                                               P.perm, P.shifts, (const TQ *)P.Q, P.U, P.V,
+                                               nullptr, 0, P.out, nullptr);
+}
+
+// One point on the phased engine with its per-sample terms precomputed:
+// tiles of tile positions t0 + 16 blockIdx.x .. (below N), their terms
+// tile-major from position t0.
+template <typename TQ, int NT, bool DUMP>
+__global__ __launch_bounds__(NT, (contract_min_waves<NT, ENG_PH>())) void k_contract_ph(
+    ile_geom g, const double *__restrict__ smp, int64_t N, const int32_t *__restrict__ perm,
+    const int32_t *__restrict__ shifts, const TQ *__restrict__ Q,
+    const double *__restrict__ terms, int64_t t0, double *__restrict__ out,
+    double *__restrict__ series)
+{
+    contract_tile_ph<TQ, 16, NT, DUMP, true>(g, t0 + (int64_t)blockIdx.x * 16, smp, N, perm,
+                                             shifts, Q, nullptr, nullptr, terms, t0, out,
+                                             series);
 }
 
 // --------------------------------------------------------------- prior
@@ -1874,24 +2136,38 @@ int ph_wrow(int nd, int nl, size_t e, size_t budget)
 
 constexpr size_t kPhBudget = 78 * 1024;   // two workgroups per CU
 
+static hipError_t launch_terms(const ile_geom &g, const double *smp, int64_t N,
+                               const int32_t *perm, const int32_t *shifts, const double4 *uvt,
+                               int64_t t0, int64_t n, double *terms, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_terms, dim3(nblk(n, kTermsT)), dim3(kTermsT), terms_lds_bytes(g), st,
+                       g, smp, N, perm, shifts, uvt, t0, n, terms);
+    return hipGetLastError();
+}
+
 template <typename TQ, int NT, bool DUMP>
 hipError_t launch_contract_ph(const ile_geom &g, const double *smp, int64_t N,
                               const int32_t *perm, const int32_t *shifts, const void *Q,
-                              const double *U, const double *V, double *out, double *series,
-                              size_t dyn, hipStream_t st)
+                              const double4 *uvt, double *terms, int64_t cap, double *out,
+                              double *series, size_t dyn, hipStream_t st)
 {
     // dynamic LDS above the default limit must be allowed per kernel
     static size_t allowed = 0;
     if (dyn > allowed) {
         hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&k_contract<TQ, 16, NT, ENG_PH, DUMP>),
+            reinterpret_cast<const void *>(&k_contract_ph<TQ, NT, DUMP>),
             hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
         if (e != hipSuccess) return e;
         allowed = dyn;
     }
-    hipLaunchKernelGGL((k_contract<TQ, 16, NT, ENG_PH, DUMP>), dim3(nblk(N, 16)), dim3(NT),
-                       dyn, st, g, smp, N, perm, shifts, (const TQ *)Q, (const double2 *)U,
-                       (const double2 *)V, out, series);
+    for (int64_t t0 = 0; t0 < N; t0 += cap) {
+        const int64_t n = N - t0 < cap ? N - t0 : cap;
+        hipError_t e = launch_terms(g, smp, N, perm, shifts, uvt, t0, n, terms, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_contract_ph<TQ, NT, DUMP>), dim3(nblk(n, 16)), dim3(NT), dyn, st, g,
+                           smp, N, perm, shifts, (const TQ *)Q, (const double *)terms, t0, out,
+                           series);
+    }
     return hipGetLastError();
 }
 
@@ -2031,11 +2307,19 @@ bool ile_tune_supported(ile_precision prec, const ile_tune &tu)
     return tu.engine == ENG_MFMA || tu.engine == ENG_VALU;
 }
 
+int ile_terms_fields(const ile_geom &g) { return 2 + 3 * g.n_det + 2 * g.n_lm; }
+
+bool ile_contract_uses_terms(ile_precision prec, const ile_tune &tu)
+{
+    return tu.engine == ENG_PH && prec != ILE_BF16;
+}
+
 hipError_t ile_launch_contract(const ile_geom &g, ile_precision prec,
                                const ile_tune &tu, const double *smp, int64_t N,
                                const int32_t *perm, const int32_t *shifts,
                                const void *Q, const double *U, const double *V,
-                               double *out, double *series, hipStream_t st)
+                               const double *uvt, double *terms, int64_t cap, double *out,
+                               double *series, hipStream_t st)
 {
     if (N <= 0) return hipSuccess;
     if (!ile_tune_supported(prec, tu)) return hipErrorInvalidValue;
@@ -2043,15 +2327,19 @@ hipError_t ile_launch_contract(const ile_geom &g, ile_precision prec,
         ile_geom gp = g;
         ile_contract_prepare(gp, prec, tu);
         if (gp.wcap < 32) return hipErrorInvalidValue;
+        if (!uvt || !terms || cap < 16 || cap % 16) return hipErrorInvalidValue;
+        if (terms_lds_bytes(g) > 64 * 1024) return hipErrorInvalidValue;
         const size_t e = prec == ILE_FP64 ? 8 : 4;
         // one 32-bit buffer range covers the whole series
         if ((size_t)g.n_det * 4 * ksp_of(g.n_lm) * g.n_q * e > 0x7fffffffu)
             return hipErrorInvalidValue;
         const size_t dyn = ph_dyn_bytes(16, g.n_det, g.n_lm, gp.wrow, e);
-#define ILE_PH(TQ, NT)                                                                      \
-    return series ? launch_contract_ph<TQ, NT, true>(gp, smp, N, perm, shifts, Q, U, V, out,  \
-                                                     series, dyn, st)                        \
-                  : launch_contract_ph<TQ, NT, false>(gp, smp, N, perm, shifts, Q, U, V, out, \
+#define ILE_PH(TQ, NT)                                                                       \
+    return series ? launch_contract_ph<TQ, NT, true>(gp, smp, N, perm, shifts, Q,               \
+                                                     (const double4 *)uvt, terms, cap, out,    \
+                                                     series, dyn, st)                          \
+                  : launch_contract_ph<TQ, NT, false>(gp, smp, N, perm, shifts, Q,              \
+                                                      (const double4 *)uvt, terms, cap, out,   \
                                                       series, dyn, st)
         if (prec == ILE_FP64) {
             if (tu.threads == 256) ILE_PH(double, 256);

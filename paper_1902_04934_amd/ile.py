@@ -28,7 +28,7 @@ ILE_OPT_ENGINE = 1
 ILE_OPT_THREADS = 2
 ILE_OPT_HARVEST_ROWS = 3
 ILE_OPT_LDS_KB = 4
-NOALLOC_MAX_N = 1048576   # ile_integrate_dev_noalloc: samples per call
+NOALLOC_MAX_N = 65536   # ile_integrate_dev_noalloc: samples per call
 
 
 class IleError(RuntimeError):
