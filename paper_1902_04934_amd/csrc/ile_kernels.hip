@@ -1372,20 +1372,20 @@ __device__ __forceinline__ void contract_tile(
 // The tile is therefore not split into producer and consumer waves (which
 // leaves the matrix work on some SIMDs and the vector work on others):
 // every wave takes both roles in turn, per chunk of J bins:
-//   G phase: the G blocks of all detectors, G_k[alpha][p] =
-//            sum_r C_k[alpha][r] Qm_k[r][P_k + p] over the union of the
-//            chunk's windows (P_k = smin_k + j0), as 16-wide N-tiles dealt
-//            to the waves in turn (the first wave rotates with the
-//            detector), each written to its LDS block;
+//   G phase, one detector k at a time: the windowed products
+//            G_k[alpha][p] = sum_r C_k[alpha][r] Qm_k[r][P_k + p] over the
+//            union of the chunk's windows (P_k = smin_k + j0), as 16-wide
+//            N-tiles dealt to the waves in turn, each result moved to its
+//            sample's chunk bin: X[alpha][jj] with jj = p - (s_alpha,k -
+//            smin_k), stored for the first detector and added for the
+//            others (a barrier between detectors), so X holds the sum over
+//            the detectors in ascending order;
 //   L phase: lane (alpha, sub), LPS = 16 or 32 lanes per sample, owns the
-//            bins j = sub (mod LPS); it sums G_k[alpha][s_alpha,k - smin_k + j - j0]
-//            over the detectors (k ascending) and folds each bin into its
+//            bins j = sub (mod LPS) and folds X[alpha][j - j0] into its
 //            log-sum-exp.
-// J = floor16(wcap - spread), spread the widest detector's range of window
-// starts in the tile, so each block fits wcap positions.  A tile whose
-// spread exceeds wcap - 16 is processed in passes over subsets of its
-// samples (greedy in tile order); rows of samples outside a pass are
-// computed but not read.
+// X has one row of J bins per sample whatever the spread of the tile's
+// window starts (which only widens the unions), so J is set by the LDS
+// budget alone.
 //
 // Log-sum-exp with a lagging reference: each lane keeps (m, s) with
 // s = sum exp(x - m) over its bins, and moves m to x only at its first bin
@@ -1458,82 +1458,79 @@ __device__ inline __amdgpu_buffer_rsrc_t q_rsrc(const TQ *Qk, int bytes)
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<TQ *>(Qk), (short)0, bytes, 0x00020000);
 }
 
-// Up to four (detector, N-tile) pairs of a wave, computed together so that
-// four accumulations are always in flight.
-struct PhPairs {
-    int k[4], t[4], p0[4];
-};
-
-// NU pairs: lane l supplies A[l%16][l/16] (coefficients of the pair's
-// detector, LDS) and B[l/16][l%16] = Qm_k[4 ks + l/16][P0 + 16 t + l%16] by
-// buffer loads, the lane's offset in a VGPR and the k-step's in an SGPR, so a
-// load costs no vector instruction.  Columns past the end of Q are clamped
-// (their results are never read).  Operands are double-buffered: the loads
-// of k-step ks + 1 are issued before the products of k-step ks.
+// NU N-tiles t[u] of detector k, computed together so that NU accumulations
+// are in flight: lane l supplies A[l%16][l/16] (the detector's
+// coefficients, LDS; one read per k-step serves all NU tiles) and
+// B[l/16][l%16] = Qm_k[4 ks + l/16][P0 + 16 t + l%16] by buffer loads, the
+// lane's offset in a VGPR and the k-step's in an SGPR, so a load costs no
+// vector instruction.  Columns past the end of Q are clamped (past every
+// sample's window: never moved to X).  Operands are double-buffered: the
+// loads of k-step ks + 1 are issued before the products of k-step ks.  The
+// result D[alpha][16 t + c] goes to X[alpha][16 t + c - dd[v]] (alpha =
+// row(lane / 16, v), dd its window start minus smin_k) when that bin is in
+// [0, Jc): stored when `add` is false, else added.  Each (alpha, bin) comes
+// from exactly one lane of one tile.
 template <typename TQ, int NU>
-__device__ inline void ph_pairs(TQ *G, int wrow, const TQ *coef, __amdgpu_buffer_rsrc_t rs,
-                                int nq, int KSP, int RP, const PhPairs &pp, int lane)
+__device__ inline void ph_tiles(TQ *X, int xrow, const TQ *coefk, __amdgpu_buffer_rsrc_t rs,
+                                int qrow0, int nq, int KSP, int P0, const int (&t)[4],
+                                const int (&dd)[4], int Jc, bool add, int lane)
 {
     using M = mfma_acc<TQ>;
     const int row = lane >> 4, col = lane & 15;
     typename M::type acc[NU];
-    int vo[NU], ao[NU];
+    int vo[NU];
 #pragma unroll
     for (int u = 0; u < NU; u++) {
         acc[u] = typename M::type{0, 0, 0, 0};
-        vo[u] = ((pp.k[u] * RP + row) * nq + min(pp.p0[u] + 16 * pp.t[u] + col, nq - 1)) *
-                (int)sizeof(TQ);
-        ao[u] = pp.k[u] * KSP * 64 + lane;
+        vo[u] = ((qrow0 + row) * nq + min(P0 + 16 * t[u] + col, nq - 1)) * (int)sizeof(TQ);
     }
     const int kstep = 4 * nq * (int)sizeof(TQ);
-    TQ a0[NU], b0[NU], a1[NU], b1[NU];
+    TQ a0 = coefk[lane], a1, b0[NU], b1[NU];
 #pragma unroll
-    for (int u = 0; u < NU; u++) {
-        a0[u] = coef[ao[u]];
-        b0[u] = qload<TQ>::ld(rs, vo[u], 0);
-    }
+    for (int u = 0; u < NU; u++) b0[u] = qload<TQ>::ld(rs, vo[u], 0);
     // k-steps in pairs with every load and product unconditional (a load
     // under a branch is sunk next to its use); an odd last step follows
     int ks = 0;
     for (; ks + 1 < KSP; ks += 2) {
         const int k2 = min(ks + 2, KSP - 1);
+        a1 = coefk[(ks + 1) * 64 + lane];
 #pragma unroll
-        for (int u = 0; u < NU; u++) {
-            a1[u] = coef[ao[u] + (ks + 1) * 64];
-            b1[u] = qload<TQ>::ld(rs, vo[u], (ks + 1) * kstep);
-        }
+        for (int u = 0; u < NU; u++) b1[u] = qload<TQ>::ld(rs, vo[u], (ks + 1) * kstep);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int u = 0; u < NU; u++) acc[u] = M::step(a0[u], b0[u], acc[u]);
+        for (int u = 0; u < NU; u++) acc[u] = M::step(a0, b0[u], acc[u]);
+        __builtin_amdgcn_sched_barrier(0);
+        a0 = coefk[k2 * 64 + lane];
+#pragma unroll
+        for (int u = 0; u < NU; u++) b0[u] = qload<TQ>::ld(rs, vo[u], k2 * kstep);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int u = 0; u < NU; u++) {
-            a0[u] = coef[ao[u] + k2 * 64];
-            b0[u] = qload<TQ>::ld(rs, vo[u], k2 * kstep);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int u = 0; u < NU; u++) acc[u] = M::step(a1[u], b1[u], acc[u]);
+        for (int u = 0; u < NU; u++) acc[u] = M::step(a1, b1[u], acc[u]);
         __builtin_amdgcn_sched_barrier(0);
     }
     if (ks < KSP) {
 #pragma unroll
-        for (int u = 0; u < NU; u++) acc[u] = M::step(a0[u], b0[u], acc[u]);
+        for (int u = 0; u < NU; u++) acc[u] = M::step(a0, b0[u], acc[u]);
     }
 #pragma unroll
     for (int u = 0; u < NU; u++) {
-        TQ *Gu = G + (pp.k[u] * 16) * wrow + 16 * pp.t[u] + col;
 #pragma unroll
-        for (int v = 0; v < 4; v++) Gu[M::row(row, v) * wrow] = (TQ)acc[u][v];
+        for (int v = 0; v < 4; v++) {
+            const int jj = 16 * t[u] + col - dd[v];
+            if (jj >= 0 && jj < Jc) {
+                TQ *x = X + M::row(row, v) * xrow + jj;
+                *x = add ? *x + (TQ)acc[u][v] : (TQ)acc[u][v];
+            }
+        }
     }
 }
 
 // LDS of the phased tile beyond its static arrays: coefficients
-// [nd][KSP][64], then the G blocks [nd][TS][wrow] (the prologue's scratch
+// [nd][KSP][64], then the chunk bins X [TS][xrow] (the prologue's scratch
 // lives there first).
 __host__ __device__ inline size_t ph_dyn_bytes(int ts, int nd, int nl, int wrow, size_t e)
 {
-    const size_t gb = (size_t)nd * ts * wrow * e;
+    const size_t gb = (size_t)ts * wrow * e;
     const size_t sb = prologue_scratch_bytes(ts, nd, nl);
     return coef_bytes<ENG_MFMA>(ts, nd, nl, e) + (gb > sb ? gb : sb);
 }
@@ -1541,20 +1538,17 @@ __host__ __device__ inline size_t ph_dyn_bytes(int ts, int nd, int nl, int wrow,
 // L phase of one chunk for one lane of the phased tile: the chunk's bins
 // j0 + i, i = o, o + LPS, o + 2 LPS, ... < Jc, of its sample (o chosen by
 // the caller so that the lane owns the bins j = sub (mod LPS) whatever the
-// chunking), each the sum of the ND detectors' G entries (k ascending),
-// folded into the lane's log-sum-exp (m, s).  srow: the sample's series row
-// at bin j0 when the per-bin values are wanted (minus q), else null.
-template <typename TQ, int ND, int LPS, bool DUMP>
-__device__ __forceinline__ void ph_lphase(const TQ *G, const int (&go)[ILE_MAX_DET], int Jc,
-                                          int o, double &m, double &ssum, double *srow,
-                                          double q)
+// chunking), x = X[i] (the sum over the detectors), folded into the lane's
+// log-sum-exp (m, s).  srow: the sample's series row at bin j0 when the
+// per-bin values are wanted (minus q), else null.
+template <typename TQ, int LPS, bool DUMP>
+__device__ __forceinline__ void ph_lphase(const TQ *X, int Jc, int o, double &m, double &ssum,
+                                          double *srow, double q)
 {
-    const auto xsum = [&](int i) {
-        TQ xs = G[go[0] + i];
-#pragma unroll
-        for (int k = 1; k < ND; k++) xs += G[go[k] + i];
-        if (DUMP) srow[i] = (double)xs - q;
-        return (double)xs;
+    const auto xval = [&](int i) {
+        const double x = (double)X[i];
+        if (DUMP) srow[i] = x - q;
+        return x;
     };
     const auto fold = [&](double x) {
         double d = x - m;
@@ -1569,7 +1563,7 @@ __device__ __forceinline__ void ph_lphase(const TQ *G, const int (&go)[ILE_MAX_D
     // independent (the sums are still taken in bin order, as fold would)
     int i = o;
     for (; i + LPS < Jc; i += 2 * LPS) {
-        const double x0 = xsum(i), x1 = xsum(i + LPS);
+        const double x0 = xval(i), x1 = xval(i + LPS);
         const double d0 = x0 - m, d1 = x1 - m;
         if (d0 > kLseSlack || d1 > kLseSlack) {
             fold(x0);
@@ -1580,7 +1574,7 @@ __device__ __forceinline__ void ph_lphase(const TQ *G, const int (&go)[ILE_MAX_D
             ssum += e1;
         }
     }
-    if (i < Jc) fold(xsum(i));
+    if (i < Jc) fold(xval(i));
 }
 
 // PRE: the per-sample terms come from k_terms (the tile's block of the
@@ -1598,10 +1592,9 @@ __device__ __forceinline__ void contract_tile_ph(
     constexpr int NW = NT / 64;    // waves
     constexpr int LPS = NT / TS;   // lanes per sample in the L phase
     __shared__ double s_q[TS];
-    __shared__ int s_idx[TS], s_ok[TS], s_pass[TS];
+    __shared__ int s_idx[TS], s_ok[TS];
     __shared__ int s_d[ILE_MAX_DET][TS];
     __shared__ int s_smin[ILE_MAX_DET], s_spread[ILE_MAX_DET];
-    __shared__ int s_npass, s_wide;
     extern __shared__ __align__(16) unsigned char dyn_lds[];
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -1611,7 +1604,7 @@ __device__ __forceinline__ void contract_tile_ph(
     const int wcap = g.wcap, wrow = g.wrow;
     TQ *coef = reinterpret_cast<TQ *>(dyn_lds);   // [nd][KSP][64]
     TQ *G = reinterpret_cast<TQ *>(dyn_lds + coef_bytes<ENG_MFMA>(TS, nd, nl, sizeof(TQ)));
-    const size_t gbytes = (size_t)nd * TS * wrow * sizeof(TQ);
+    const size_t gbytes = (size_t)TS * wrow * sizeof(TQ);
     const size_t sbytes = prologue_scratch_bytes(TS, nd, nl);
     // one buffer resource over all of Q (the host keeps it below 2 GiB)
     const __amdgpu_buffer_rsrc_t rs = q_rsrc<TQ>(Q, nd * RP * nq * (int)sizeof(TQ));
@@ -1670,11 +1663,7 @@ __device__ __forceinline__ void contract_tile_ph(
                                             s_idx, s_ok, s_d);
     }
 
-    // passes: one over all valid samples when every detector's spread is
-    // within wcap - 16 (all but rare tiles: decided by a 16-lane reduction);
-    // else greedy in tile order, each pass adding the samples that keep the
-    // spreads within that bound
-    bool wide = false;
+    // window range of each detector over the tile's valid samples
     if (tid < TS) {
         const bool v = s_ok[tid];
         for (int k = 0; k < nd; k++) {
@@ -1683,143 +1672,55 @@ __device__ __forceinline__ void contract_tile_ph(
                 lo = min(lo, __shfl_xor(lo, off, 16));
                 hi = max(hi, __shfl_xor(hi, off, 16));
             }
-            wide = wide || (hi >= 0 && hi - lo > wcap - 16);
-            // the window range of the single pass (recomputed per pass below
-            // for a wide tile)
             if (tid == 0) {
                 s_smin[k] = hi >= 0 ? lo : 0;
                 s_spread[k] = hi >= 0 ? hi - lo : 0;
             }
         }
-        if (!wide) {
-            s_pass[tid] = v ? 0 : -1;
-            const bool any = __ballot(v) != 0;
-            if (tid == 0) s_npass = any ? 1 : 0;
-        }
-        if (tid == 0) s_wide = wide;
-    }
-    if (tid == 0 && wide) {
-        const int lim = wcap - 16;
-        int np = 0;
-        for (int al = 0; al < TS; al++) s_pass[al] = -1;
-        for (;;) {
-            int lo[ILE_MAX_DET] = {}, hi[ILE_MAX_DET] = {};
-            bool any = false;
-            for (int al = 0; al < TS; al++) {
-                if (!s_ok[al] || s_pass[al] >= 0) continue;
-                bool fits = true;
-#pragma unroll
-                for (int k = 0; k < ILE_MAX_DET; k++)
-                    if (any && k < nd)
-                        fits = fits && max(hi[k], s_d[k][al]) - min(lo[k], s_d[k][al]) <= lim;
-                if (!fits) continue;
-#pragma unroll
-                for (int k = 0; k < ILE_MAX_DET; k++)
-                    if (k < nd) {
-                        lo[k] = any ? min(lo[k], s_d[k][al]) : s_d[k][al];
-                        hi[k] = any ? max(hi[k], s_d[k][al]) : s_d[k][al];
-                    }
-                any = true;
-                s_pass[al] = np;
-            }
-            if (!any) break;
-            np++;
-        }
-        s_npass = np;
     }
     __syncthreads();
 
-    const int al = tid / LPS, sub = tid % LPS;
+    using MA = mfma_acc<TQ>;
+    const int al = tid / LPS, sub = tid % LPS, row = lane >> 4;
+    const bool mem = s_ok[al];
+    TQ *X = G;   // [TS][wrow], the chunk's bins of every sample
     double m = -INFINITY, ssum = 0.0;
-    const int npass = s_npass;
-    const bool multi = s_wide;
-    for (int p = 0; p < npass; p++) {
-        if (multi && tid < nd) {
-            int lo = 0x7fffffff, hi = -1;
-            for (int b = 0; b < TS; b++)
-                if (s_pass[b] == p) {
-                    lo = min(lo, s_d[tid][b]);
-                    hi = max(hi, s_d[tid][b]);
+    const int J = wcap;   // a multiple of 16, at most wrow
+    for (int j0 = 0; j0 < n_t; j0 += J) {
+        const int Jc = min(J, n_t - j0);
+        // G phase, detector by detector: N-tiles wv, wv + NW, ..., four at
+        // a time
+        for (int k = 0; k < nd; k++) {
+            const int smin = s_smin[k];
+            const int T = (Jc + s_spread[k] + 15) >> 4;
+            int dd[4];
+#pragma unroll
+            for (int v = 0; v < 4; v++) dd[v] = s_d[k][MA::row(row, v)] - smin;
+            const TQ *coefk = coef + k * KSP * 64;
+            for (int tb = wv; tb < T; tb += 4 * NW) {
+                int t[4], nu = 0;
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int tt = tb + u * NW;
+                    t[u] = tt < T ? tt : tb;
+                    nu += tt < T;
                 }
-            s_smin[tid] = lo;
-            s_spread[tid] = hi - lo;
+                switch (__builtin_amdgcn_readfirstlane(nu)) {
+                case 4: ph_tiles<TQ, 4>(X, wrow, coefk, rs, k * RP, nq, KSP, smin + j0, t, dd, Jc, k > 0, lane); break;
+                case 3: ph_tiles<TQ, 3>(X, wrow, coefk, rs, k * RP, nq, KSP, smin + j0, t, dd, Jc, k > 0, lane); break;
+                case 2: ph_tiles<TQ, 2>(X, wrow, coefk, rs, k * RP, nq, KSP, smin + j0, t, dd, Jc, k > 0, lane); break;
+                default: ph_tiles<TQ, 1>(X, wrow, coefk, rs, k * RP, nq, KSP, smin + j0, t, dd, Jc, k > 0, lane); break;
+                }
+            }
+            __syncthreads();
+        }
+        // L phase
+        if (mem) {
+            double *srow = DUMP ? series + (int64_t)s_idx[al] * n_t + j0 : nullptr;
+            const int o = (sub - j0) & (LPS - 1);   // first bin j = sub (mod LPS)
+            ph_lphase<TQ, LPS, DUMP>(X + al * wrow, Jc, o, m, ssum, srow, s_q[al]);
         }
         __syncthreads();
-        int smax = 0, sx = 0;
-        for (int k = 0; k < nd; k++) {
-            smax = max(smax, s_spread[k]);
-            sx += (s_spread[k] + 15) >> 4;
-        }
-        // chunk length: the blocks fit wcap positions, and where it keeps
-        // at least 16 bins, the chunk has at most 32 pairs (J/16 tiles per
-        // detector plus the spreads' extra tiles): whole groups of four for
-        // eight waves, two for four
-        int J = (wcap - smax) & ~15;   // >= 16
-        const int jp = ((32 - sx) / nd) * 16;
-        if (jp >= 16 && jp < J) J = jp;
-        const bool mem = s_pass[al] == p;
-        // this lane's sample's entry of every G block at the chunk's first bin
-        int go[ILE_MAX_DET];
-#pragma unroll
-        for (int k = 0; k < ILE_MAX_DET; k++)
-            go[k] = k < nd ? (k * TS + al) * wrow + (mem ? s_d[k][al] - s_smin[k] : 0) : 0;
-        for (int j0 = 0; j0 < n_t; j0 += J) {
-            const int Jc = min(J, n_t - j0);
-            // G phase: the chunk's (detector, N-tile) pairs in detector
-            // order, dealt round-robin: wave wv takes pairs wv, wv + NW, ...
-            // (counts differ by at most one), four at a time
-            {
-                int kk = 0, tt = wv;   // pair wv: detector kk, tile tt
-                const auto norm = [&]() {
-                    while (kk < nd) {
-                        const int T = (Jc + s_spread[kk] + 15) >> 4;
-                        if (tt < T) break;
-                        tt -= T;
-                        kk++;
-                    }
-                };
-                norm();
-                while (kk < nd) {
-                    PhPairs pp;
-                    int nu = 0;
-#pragma unroll
-                    for (int u = 0; u < 4; u++) {
-                        if (kk < nd) {
-                            pp.k[u] = kk;
-                            pp.t[u] = tt;
-                            pp.p0[u] = s_smin[kk] + j0;
-                            nu++;
-                            tt += NW;
-                            norm();
-                        } else {
-                            pp.k[u] = pp.k[0];
-                            pp.t[u] = pp.t[0];
-                            pp.p0[u] = pp.p0[0];
-                        }
-                    }
-                    switch (__builtin_amdgcn_readfirstlane(nu)) {
-                    case 4: ph_pairs<TQ, 4>(G, wrow, coef, rs, nq, KSP, RP, pp, lane); break;
-                    case 3: ph_pairs<TQ, 3>(G, wrow, coef, rs, nq, KSP, RP, pp, lane); break;
-                    case 2: ph_pairs<TQ, 2>(G, wrow, coef, rs, nq, KSP, RP, pp, lane); break;
-                    default: ph_pairs<TQ, 1>(G, wrow, coef, rs, nq, KSP, RP, pp, lane); break;
-                    }
-                }
-            }
-            __syncthreads();
-            // L phase
-            if (mem) {
-                double *srow = DUMP ? series + (int64_t)s_idx[al] * n_t + j0 : nullptr;
-                const double q = s_q[al];
-                const int o = (sub - j0) & (LPS - 1);   // first bin j = sub (mod LPS)
-                switch (nd) {
-                case 1: ph_lphase<TQ, 1, LPS, DUMP>(G, go, Jc, o, m, ssum, srow, q); break;
-                case 2: ph_lphase<TQ, 2, LPS, DUMP>(G, go, Jc, o, m, ssum, srow, q); break;
-                case 3: ph_lphase<TQ, 3, LPS, DUMP>(G, go, Jc, o, m, ssum, srow, q); break;
-                default: ph_lphase<TQ, 4, LPS, DUMP>(G, go, Jc, o, m, ssum, srow, q); break;
-                }
-            }
-            __syncthreads();
-        }
     }
     // merge the LPS lanes of each sample (fixed tree: 16-lane rows, then the
     // row pair), then the result (M - q) + log S - log n_t
@@ -2120,16 +2021,16 @@ hipError_t launch_contract_t(const ile_geom &g, const double *smp, int64_t N,
     return hipGetLastError();
 }
 
-// Positions per G block of the phased engine (also its LDS row stride): the
-// largest that keeps the workgroup's dynamic LDS within `budget` bytes, an odd
-// multiple of 128 bytes so that the four rows of one store start in
-// alternate halves of the 256-byte bank period.  0 if none fits.
+// Bins per chunk of the phased engine (also the LDS row stride of its bin
+// rows): the largest that keeps the workgroup's dynamic LDS within `budget`
+// bytes, an odd multiple of 128 bytes so that rows of neighbouring samples
+// start in alternate halves of the 256-byte bank period.  0 if none fits.
 int ph_wrow(int nd, int nl, size_t e, size_t budget)
 {
     const size_t fixed = coef_bytes<ENG_MFMA>(16, nd, nl, e);
     if (budget <= fixed) return 0;
     const int unit = (int)(128 / e);
-    const int w = (int)((budget - fixed) / ((size_t)nd * 16 * e));
+    const int w = (int)((budget - fixed) / ((size_t)16 * e));
     const int q = (w / unit - 1) / 2;
     return q < 0 ? 0 : unit * (2 * q + 1);
 }
@@ -2282,8 +2183,8 @@ size_t ile_contract_lds_bytes(const ile_geom &g, ile_precision prec,
     const size_t e = prec == ILE_FP64 ? 8 : 4;
     if (tu.engine == ENG_PH && prec != ILE_BF16) {
         const int w = ph_wrow(g.n_det, g.n_lm, e, ph_budget(tu));
-        // a block narrower than 32 positions cannot hold a 16-bin chunk
-        if (w < 32) return (size_t)1 << 30;
+        // a chunk has at least 16 bins
+        if (w < 16) return (size_t)1 << 30;
         return ph_dyn_bytes(16, g.n_det, g.n_lm, w, e) + 2048;
     }
     const size_t gs = (size_t)tu.tile_samples * (tu.engine == ENG_MFMA ? 2 : 1) * tu.threads * e;
@@ -2326,7 +2227,7 @@ hipError_t ile_launch_contract(const ile_geom &g, ile_precision prec,
     if (tu.engine == ENG_PH) {
         ile_geom gp = g;
         ile_contract_prepare(gp, prec, tu);
-        if (gp.wcap < 32) return hipErrorInvalidValue;
+        if (gp.wcap < 16) return hipErrorInvalidValue;
         if (!uvt || !terms || cap < 16 || cap % 16) return hipErrorInvalidValue;
         if (terms_lds_bytes(g) > 64 * 1024) return hipErrorInvalidValue;
         const size_t e = prec == ILE_FP64 ? 8 : 4;
