@@ -43,13 +43,14 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def committed_traffic(precision, threads):
-    """HBM bytes of one contraction launch from the committed rocprofv3
-    summary of this workload (FETCH_SIZE + WRITE_SIZE, calibrated), if it was
-    taken on the current kernel sources and launch shape; else None."""
+def committed_traffic(precision, engine, threads):
+    """HBM bytes of one contraction launch (the terms pass and the tiles for
+    the phased engine) from the committed rocprofv3 summary of this workload
+    (FETCH_SIZE + WRITE_SIZE, calibrated), if it was taken on the current
+    kernel sources, engine and launch shape; else None."""
     import glob
     want = kernel_source_hash()
-    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "k_contract_*.md"))):
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         fields = {}
         with open(path) as fh:
             for line in fh:
@@ -58,7 +59,8 @@ def committed_traffic(precision, threads):
                         k, _, v = kv.partition("=")
                         fields[k] = v
         if (fields.get("source_sha256") == want and fields.get("precision") == precision
-                and fields.get("threads") == str(threads) and "bytes" in fields):
+                and fields.get("engine") == engine and fields.get("threads") == str(threads)
+                and "bytes" in fields):
             return int(fields["bytes"])
     return None
 
@@ -70,14 +72,22 @@ def flops_per_sample(n_det, n_lm, n_t):
     return 4 * n_det * n_lm * n_t + 16 * n_det * n_lm * n_lm
 
 
-def cpu_baseline(inst, n_total, seed, target_s=15.0):
-    """Time the FP64 oracle on the host on the first M samples of the same
-    workload, M sized for about target_s seconds of CPU work (capped at the
-    whole workload), from a first timing of 20000 samples."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_rate(octx, n_total, n_t, seed, threads, target_s):
+    """sample*bin/s of the FP64 oracle on the first M prior draws of the
+    stream, M sized for about target_s seconds from a first timing of 2000."""
     from oracle import oracle as O
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
-    octx = O.Ctx(inst)
-    m0 = 20000
+    m0 = min(2000, n_total)
     s0, _ = O.prior_draw(seed, 0, m0)
     t = time.perf_counter()
     octx.eval(s0, n_threads=threads)
@@ -87,10 +97,34 @@ def cpu_baseline(inst, n_total, seed, target_s=15.0):
     t = time.perf_counter()
     octx.eval(sub, n_threads=threads)
     dt = time.perf_counter() - t
-    return {"value": m * inst.n_t / dt, "unit": "sample*bin/s", "cores": threads,
-            "kind": "oracle",
+    return m * n_t / dt, m, dt
+
+
+def cpu_baseline(inst, n_total, seed, target_s=8.0):
+    """The FP64 oracle on the host cores: the benchmark workload with all
+    threads (the reported value) and with one, and the small two-detector
+    workload (2 detectors, 5 modes, 4096 Hz, 201 bins, 1e4 samples) with both,
+    each on a bounded sample of the same prior stream (about target_s seconds
+    of CPU work per timing)."""
+    from oracle import oracle as O
+    from paper_1902_04934_amd import synth
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    rate, m, dt = _oracle_rate(O.Ctx(inst), n_total, inst.n_t, seed, threads, target_s)
+    rate1, m1, dt1 = _oracle_rate(O.Ctx(inst), n_total, inst.n_t, seed, 1, target_s)
+    i1 = synth.config1()
+    n1, seed1 = synth.CONFIG_SAMPLES[1]
+    c1 = O.Ctx(i1)
+    r1a, m1a, _ = _oracle_rate(c1, n1, i1.n_t, seed1, threads, target_s / 4)
+    r1b, m1b, _ = _oracle_rate(c1, n1, i1.n_t, seed1, 1, target_s / 4)
+    return {"value": rate, "unit": "sample*bin/s", "cores": threads, "kind": "oracle",
             "sample": f"first {m} of the {n_total} prior samples, all {inst.n_t} bins, "
-                      f"FP64 C oracle with OpenMP ({dt:.1f} s)"}
+                      f"FP64 C oracle with OpenMP ({dt:.1f} s)",
+            "cpu_model": cpu_model(),
+            "one_thread": {"value": rate1, "sample": f"first {m1} samples ({dt1:.1f} s)"},
+            "small_workload": {"workload": "2 detectors, 5 modes (l=2), Q 4096 points at "
+                                           "4096 Hz, 201 time bins",
+                               "all_threads": r1a, "one_thread": r1b,
+                               "samples": [m1a, m1b]}}
 
 
 LEARNED_SEEDS = tuple(range(41, 49))
@@ -421,12 +455,71 @@ def precision_forms(inst, n, seed, steps, m_oracle=2000):
             if x is None:
                 x = xd.cpu().numpy()
                 want = O.Ctx(inst).eval(x)
-        err = float(np.max(np.abs(got - want) / np.maximum(1.0, np.abs(want))))
+        rel = np.abs(got - want) / np.maximum(1.0, np.abs(want))
         out[prec] = {"kernel_ms": kernel_ms, "evals_per_s": n * inst.n_t / (kernel_ms * 1e-3),
                      "frac_of_peak": fl / (kernel_ms * 1e-3) / 1e12 / peak[prec],
-                     "max_rel_err_lnL_vs_oracle": err}
+                     "max_rel_err_lnL_vs_oracle": float(np.max(rel)),
+                     "p99_rel_err_lnL_vs_oracle": float(np.percentile(rel, 99))}
     out["oracle_samples"] = m_oracle
     return out
+
+
+def mode_scaling_leg(n=200_000, steps=3):
+    """Contraction time against the number of modes (Sec. III.B: the cost
+    grows with the modes) for every engine and precision: 3 detectors, Q of
+    16384 points at 16384 Hz, 1601 bins, n prior samples, n_lm in
+    {5, 9, 13, 21} (l = 2, then l = 2..3 with |m| <= 1 for 9, ...; the
+    stand-in instances of synth.make_instance).  Per engine: event-timed
+    milliseconds per launch scaled to 1e6 samples, and the fraction of the
+    precision's peak at the algorithmic flop count."""
+    from paper_1902_04934_amd import ile, synth
+    peak = {"fp64": FP64_PEAK_TFLOPS, "fp32": FP32_PEAK_TFLOPS}
+    rows = []
+    for n_lm in (5, 9, 13, 21):
+        inst = synth.make_instance(["D1", "D2", "D3"], n_lm, 16384, 16384.0, 1601, 3000 + n_lm)
+        fl = flops_per_sample(3, n_lm, 1601) * n
+        for prec in ("fp64", "fp32"):
+            for eng in ("mfma", "pipelined", "valu"):
+                with ile.Context(inst, precision=prec, engine=eng) as ctx:
+                    ctx.run_prior(5, n)
+                    kms = []
+                    for _ in range(steps):
+                        ctx.run_prior(5, n)
+                        kms.append(ctx.last_kernel_ms())
+                ms = min(kms)
+                rows.append({"n_lm": n_lm, "precision": prec,
+                             "engine": "phased" if eng == "mfma" else eng,
+                             "ms_per_1e6": ms * 1e6 / n,
+                             "frac_of_peak": fl / (ms * 1e-3) / 1e12 / peak[prec]})
+    return {"workload": f"3 detectors, Q 16384 points at 16384 Hz, 1601 bins, {n} prior "
+                        "samples per launch", "rows": rows}
+
+
+def latency_leg(calls=50):
+    """The small workload as a latency: 2 detectors, 5 modes (l = 2), Q of
+    4096 points at 4096 Hz, 201 bins, 1e4 prior samples per call; host wall
+    time of one whole call (device prior draw, ordering, contraction,
+    reduction, result to the host) and the contraction's event time."""
+    import statistics
+    from paper_1902_04934_amd import ile, synth
+    inst = synth.config1()
+    n, seed = synth.CONFIG_SAMPLES[1]
+    with ile.Context(inst) as ctx:
+        for _ in range(5):
+            ctx.run_prior(seed, n)
+        walls, kms = [], []
+        for _ in range(calls):
+            t0 = time.perf_counter()
+            r = ctx.run_prior(seed, n)
+            walls.append((time.perf_counter() - t0) * 1e3)
+            kms.append(ctx.last_kernel_ms())
+    walls.sort()
+    return {"workload": "2 detectors, 5 modes (l=2), Q 4096 points at 4096 Hz, "
+                        f"{n} prior samples, {inst.n_t} time bins, FP64",
+            "calls": calls, "wall_ms_median": statistics.median(walls),
+            "wall_ms_p90": walls[int(0.9 * (calls - 1))],
+            "kernel_ms_median": statistics.median(kms),
+            "ln_L_marg": r["ln_L_marg"], "n_eff": r["n_eff"]}
 
 
 def main():
@@ -436,9 +529,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--samples", type=int, default=None)
-    ap.add_argument("--engine", default=None, choices=["mfma", "valu"],
-                    help="contraction engine (default: matrix cores for FP64)")
+    ap.add_argument("--engine", default=None, choices=["mfma", "pipelined", "valu"],
+                    help="contraction engine: mfma = the phased matrix-core engine (the "
+                         "default; BF16: the pipelined one), pipelined = producer/consumer "
+                         "matrix-core waves, valu = vector FMA")
     ap.add_argument("--threads", type=int, default=None, choices=[128, 192, 256, 512])
+    ap.add_argument("--lds-kb", type=int, default=None,
+                    help="LDS budget of a phased workgroup in KiB (default by precision)")
+    ap.add_argument("--no-modes", action="store_true",
+                    help="skip the engine x precision x mode-count table")
+    ap.add_argument("--no-latency", action="store_true",
+                    help="skip the small-workload latency leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-plain sampler comparison")
@@ -471,7 +572,7 @@ def main():
     n_total, seed = synth.CONFIG_SAMPLES[2]
     n = args.samples or n_total
     ctx = ile.Context(inst, precision=args.precision, device=0, engine=args.engine,
-                      threads=args.threads)
+                      threads=args.threads, lds_kb=args.lds_kb)
     torch.cuda.synchronize()
     if args.calib_copy:
         a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
@@ -490,8 +591,9 @@ def main():
     dt = time.perf_counter() - t0
     ms_step = 1e3 * dt / args.steps
     kernel_ms = sum(kms) / len(kms)
-    threads = args.threads or (256 if args.engine == "valu" or args.precision == "fp32"
-                               else 128)
+    phased = args.precision != "bf16" and args.engine in (None, "mfma")
+    engine = "phased" if phased else (args.engine or "pipelined")
+    threads = args.threads or (512 if phased else 256 if engine == "valu" else 128)
     fl = flops_per_sample(inst.n_det, inst.n_lm, inst.n_t) * n
     achieved = fl / (kernel_ms * 1e-3) / 1e12
     peak = {"fp64": FP64_PEAK_TFLOPS, "fp32": FP32_PEAK_TFLOPS,
@@ -510,18 +612,19 @@ def main():
                                f"{n} prior samples, {inst.n_t} time bins",
                    "n_samples": n, "n_t": inst.n_t, "n_det": inst.n_det,
                    "n_lm": inst.n_lm, "precision": args.precision,
-                   "engine": args.engine or "mfma",
-                   "threads": threads},
+                   "engine": engine, "threads": threads},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": committed_traffic(args.precision, threads),
-                     "kernel": "k_contract", "kernel_ms": kernel_ms,
-                     "flops_per_launch": fl},
+                     "traffic": committed_traffic(args.precision, engine, threads),
+                     "kernel": ("k_terms + k_contract_ph" if phased else "k_contract"),
+                     "kernel_ms": kernel_ms, "flops_per_launch": fl},
         "result": {"ln_L_marg": res["ln_L_marg"], "n_eff": res["n_eff"],
                    "sigma_ln_L": res["sigma_ln_L"]},
     }
     ctx.close()
     out["precision_forms"] = None if args.no_forms else precision_forms(inst, n, seed, 3)
+    out["mode_scaling"] = None if args.no_modes else mode_scaling_leg()
+    out["latency"] = None if args.no_latency else latency_leg()
     out["harvest"] = None if args.no_harvest else harvest_leg(inst, n, seed)
     out["learned"] = None if args.no_learned else learned_leg()
     out["qvu"] = None if args.no_qvu else qvu_leg()

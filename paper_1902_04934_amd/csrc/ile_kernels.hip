@@ -2035,7 +2035,11 @@ int ph_wrow(int nd, int nl, size_t e, size_t budget)
     return q < 0 ? 0 : unit * (2 * q + 1);
 }
 
-constexpr size_t kPhBudget = 78 * 1024;   // two workgroups per CU
+// Default LDS budgets of a phased workgroup: FP64 tiles hold four waves per
+// SIMD in registers, two workgroups per CU; FP32 tiles need fewer registers
+// and run three per CU.
+constexpr size_t kPhBudget64 = 78 * 1024;
+constexpr size_t kPhBudget32 = 50 * 1024;
 
 static hipError_t launch_terms(const ile_geom &g, const double *smp, int64_t N,
                                const int32_t *perm, const int32_t *shifts, const double4 *uvt,
@@ -2155,16 +2159,17 @@ static int kernel_threads(const ile_tune &tu)
     return tu.engine == ENG_MFMA ? 2 * tu.threads : tu.threads;
 }
 
-static size_t ph_budget(const ile_tune &tu)
+static size_t ph_budget(const ile_tune &tu, size_t e)
 {
-    return tu.lds_budget > 0 ? (size_t)tu.lds_budget : kPhBudget;
+    if (tu.lds_budget > 0) return (size_t)tu.lds_budget;
+    return e == 8 ? kPhBudget64 : kPhBudget32;
 }
 
 void ile_contract_prepare(ile_geom &g, ile_precision prec, const ile_tune &tu)
 {
     if (tu.engine == ENG_PH && prec != ILE_BF16) {
         const size_t e = prec == ILE_FP64 ? 8 : 4;
-        g.wrow = g.wcap = ph_wrow(g.n_det, g.n_lm, e, ph_budget(tu));
+        g.wrow = g.wcap = ph_wrow(g.n_det, g.n_lm, e, ph_budget(tu, e));
     } else {
         g.wrow = g.wcap = 0;
     }
@@ -2182,7 +2187,7 @@ size_t ile_contract_lds_bytes(const ile_geom &g, ile_precision prec,
 {
     const size_t e = prec == ILE_FP64 ? 8 : 4;
     if (tu.engine == ENG_PH && prec != ILE_BF16) {
-        const int w = ph_wrow(g.n_det, g.n_lm, e, ph_budget(tu));
+        const int w = ph_wrow(g.n_det, g.n_lm, e, ph_budget(tu, e));
         // a chunk has at least 16 bins
         if (w < 16) return (size_t)1 << 30;
         return ph_dyn_bytes(16, g.n_det, g.n_lm, w, e) + 2048;
@@ -2284,7 +2289,7 @@ size_t ile_contract_dyn_bytes(const ile_geom &g, ile_precision prec, const ile_t
 {
     const size_t e = prec == ILE_FP64 ? 8 : 4;
     if (tu.engine == ENG_PH && prec != ILE_BF16)
-        return ph_dyn_bytes(16, g.n_det, g.n_lm, ph_wrow(g.n_det, g.n_lm, e, ph_budget(tu)), e);
+        return ph_dyn_bytes(16, g.n_det, g.n_lm, ph_wrow(g.n_det, g.n_lm, e, ph_budget(tu, e)), e);
     size_t dyn = coef_bytes_of(g, prec, tu, e);
     const size_t scr = prologue_scratch_bytes(tu.tile_samples, g.n_det, g.n_lm);
     if (scr > (size_t)tu.tile_samples * kernel_threads(tu) * e) dyn += scr;

@@ -27,11 +27,21 @@ def test_flops_per_sample_of_the_benchmark_point():
     assert bench.flops_per_sample(3, 21, 1601) == 424620
 
 
-def test_traffic_lookup_needs_matching_sources(monkeypatch):
-    assert bench.committed_traffic("fp64", 999) is None
-    assert bench.committed_traffic("bf16", 128) is None
+def test_traffic_lookup_needs_matching_sources(monkeypatch, tmp_path):
+    assert bench.committed_traffic("fp64", "phased", 999) is None
+    assert bench.committed_traffic("bf16", "pipelined", 128) is None
+    # a record is found only for its own sources, precision, engine and shape
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "x.md").write_text("traffic-record: source_sha256=abc precision=fp64 "
+                               "engine=phased threads=512 bytes=123\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "abc")
+    assert bench.committed_traffic("fp64", "phased", 512) == 123
+    assert bench.committed_traffic("fp64", "pipelined", 512) is None
+    assert bench.committed_traffic("fp32", "phased", 512) is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 64)
-    assert bench.committed_traffic("fp64", 128) is None
+    assert bench.committed_traffic("fp64", "phased", 512) is None
 
 
 def test_profiles_hold_text_only():
