@@ -136,7 +136,10 @@ def learned_leg(target=1e4):
     bins, network SNR 20): wall time of each to n_eff = target, n_eff/s, and
     their ln L_marg.  The learned sampler (run defaults) is timed on eight
     run seeds: each seed trains its own network on its own draws, so the
-    spread over seeds is the spread a user sees; the headline is the median."""
+    spread over seeds is the spread a user sees; the headline is the median.
+    Every estimate is compared with an independent reference (a learned run
+    on seed 9001 continued to 3e8 draws of its defensive mixture, sigma about
+    3e-5): the difference and the combined standard error per run."""
     import numpy as np
     from paper_1902_04934_amd import ile, synth
     c = synth.config4_parts()
@@ -169,6 +172,14 @@ def learned_leg(target=1e4):
             e.update(seed=seed, train_samples=r["n_train_samples"], train_ms=r["train_ms"],
                      fell_back=r["fell_back"])
             runs.append(e)
+        # independent reference: a learned run on its own seed, then 3e8 draws
+        # of its defensive mixture (unbiased for any covering q)
+        with ile.Proposal(ctx, seed=7) as prop:
+            t0 = time.perf_counter()
+            r = ctx.run(sampler="learned", seed=9001, chunk=1_000_000, max_samples=300_000_000,
+                        n_eff_target=1e12, adapt_chunks=3, prop=prop, eps=0.1)
+            ref = entry(r, time.perf_counter() - t0)
+        out["reference"] = ref
     import statistics
     ok = [e for e in runs if not e["fell_back"] and e["n_eff"] >= target]
     med = statistics.median(e["n_eff_per_s"] for e in runs)
@@ -181,6 +192,12 @@ def learned_leg(target=1e4):
         out["ln_L_marg_learned_median"] = statistics.median(lnls)
         out["ln_L_marg_learned_spread"] = max(lnls) - min(lnls)
         out["d_ln_L_marg_vs_plain"] = statistics.median(lnls) - out["plain"]["ln_L_marg"]
+    import math
+    for e in runs + [out["plain"]]:
+        e["d_ln_L_vs_reference"] = e["ln_L_marg"] - ref["ln_L_marg"]
+        e["sigma_combined"] = math.hypot(e["sigma_ln_L"], ref["sigma_ln_L"])
+    out["within_1e-3_plus_3sigma"] = sum(
+        abs(e["d_ln_L_vs_reference"]) <= 1e-3 + 3 * e["sigma_combined"] for e in runs)
     return out
 
 
@@ -325,52 +342,65 @@ def reuse_leg(n_points=8, target=1e4):
             "max_abs_d_ln_L_over_sigma": float(z)}
 
 
-def combined_leg(n_points=32, n=1_000_000, m_oracle=2000):
+def combined_leg(n_points=32, n=1_000_000, m_oracle=2000, group=256):
     """The combined form at the combined workload's per-point shape (3
     detectors, 5-21 modes, 201-1601 bins, 16384-point Q in FP32, 1e6 draws
-    per point) on n_points points: a learned proposal per point (plain
-    fallback), the draws of all points evaluated in one batched persistent
-    run.  Reports the batched evaluation's throughput (HIP events around its
-    graph) and ln L_marg against the FP64 oracle on the first m_oracle draws
-    of every point (the device value from a batched run of those draws)."""
+    per point) on n_points points: a learned proposal per point (trained on
+    4 concurrent streams), the draws of a group of points evaluated in one
+    batched persistent run, and the plain adaptive fallback for every point
+    whose n_eff from those draws is below 1e3.  Reports the batched
+    evaluation's throughput (HIP events around its graph), the end-to-end
+    wall time, the fallback and failure counts, and each point's final
+    ln L_marg, n_eff and sigma.  Up to 32 points: one group, with ln L_marg
+    against the FP64 oracle on the first m_oracle draws of every point (the
+    device value from a batched run of those draws)."""
     import numpy as np
-    import torch
     from oracle import oracle as O
     from paper_1902_04934_amd import combined, synth
     points = [synth.combined_point(p) for p in range(n_points)]
-    t0 = time.perf_counter()
-    res, info, X, lp, lq, batch, t = combined.run(points, n)
-    wall = time.perf_counter() - t0
     work = sum(n * p["n_t"] for p in points)
-    # same-sample check against the oracle on the first m_oracle draws
-    Xs, lps, lqs = X[:, :, :m_oracle].contiguous(), lp[:, :m_oracle].contiguous(), \
-        lq[:, :m_oracle].contiguous()
-    sub = batch.run_dev(m_oracle, Xs, lps, lqs)
-    errs = []
-    t_orc = time.perf_counter()
-    for p, parts in enumerate(points):
-        inst = info[p]["inst"]
-        blank = synth.Instance(dets=inst.dets, modes=inst.modes, srate_hz=inst.srate_hz,
-                               n_t=inst.n_t, Q=np.zeros_like(inst.Q), U=np.zeros_like(inst.U),
-                               V=np.zeros_like(inst.V))
-        want, _, _ = O.injection_instance(blank, parts["h_lm"], parts["theta_inj"],
-                                          snr=parts["snr"])
-        lnL = O.Ctx(want).eval(Xs[p].cpu().numpy())
-        ref = O.integrate(lnL, lps[p].cpu().numpy(), lqs[p].cpu().numpy())
-        errs.append(abs(sub[p]["ln_L_marg"] - ref["ln_L_marg"]))
-    t_orc = time.perf_counter() - t_orc
-    batch.close()
+    t0 = time.perf_counter()
+    errs, t_orc = [], 0.0
+    if n_points <= 32:
+        res, info, X, lp, lq, batch, t = combined.run_group(points, n)
+        times = [t]
+        wall = time.perf_counter() - t0
+        Xs, lps, lqs = X[:, :, :m_oracle].contiguous(), lp[:, :m_oracle].contiguous(), \
+            lq[:, :m_oracle].contiguous()
+        sub = batch.run_dev(m_oracle, Xs, lps, lqs)
+        t_orc = time.perf_counter()
+        for p, parts in enumerate(points):
+            inst = info[p]["inst"]
+            blank = synth.Instance(dets=inst.dets, modes=inst.modes, srate_hz=inst.srate_hz,
+                                   n_t=inst.n_t, Q=np.zeros_like(inst.Q),
+                                   U=np.zeros_like(inst.U), V=np.zeros_like(inst.V))
+            want, _, _ = O.injection_instance(blank, parts["h_lm"], parts["theta_inj"],
+                                              snr=parts["snr"])
+            lnL = O.Ctx(want).eval(Xs[p].cpu().numpy())
+            ref = O.integrate(lnL, lps[p].cpu().numpy(), lqs[p].cpu().numpy())
+            errs.append(abs(sub[p]["ln_L_marg"] - ref["ln_L_marg"]))
+        t_orc = time.perf_counter() - t_orc
+        batch.close()
+    else:
+        info, times = combined.run(points, n, group=group, progress=sys.stderr)
+        wall = time.perf_counter() - t0
+    graph_ms = sum(t["eval_graph_ms"] for t in times)
+    fin = [i["final"] for i in info]
     return {"workload": f"{n_points} injected points (3 detectors, 5-21 modes, 201-1601 bins, "
                         f"Q 16384 points FP32), {n} draws per point from per-point learned "
-                        "proposals, one batched persistent evaluation",
-            "points": n_points, "draws_per_point": n,
-            "eval_graph_ms": t["eval_graph_ms"],
-            "eval_sample_bins_per_s": work / (t["eval_graph_ms"] * 1e-3),
-            "train_and_draw_s": t["train_s"], "wall_s": wall,
+                        f"proposals, batched evaluation in groups of up to {group} points",
+            "points": n_points, "draws_per_point": n, "groups": len(times),
+            "eval_graph_ms": graph_ms,
+            "eval_sample_bins_per_s": work / (graph_ms * 1e-3),
+            "train_and_draw_s": sum(t["train_s"] for t in times),
+            "fallback_s": sum(t["fallback_s"] for t in times), "wall_s": wall,
+            "points_per_s": n_points / wall,
             "fell_back": sum(i["fell_back"] for i in info),
-            "n_eff": [r["n_eff"] for r in res], "ln_L_marg": [r["ln_L_marg"] for r in res],
-            "oracle_subset_draws": m_oracle,
-            "max_abs_d_ln_L_marg_vs_oracle": max(errs), "oracle_s": t_orc}
+            "failed": sum(i["failed"] for i in info),
+            "n_eff": [f["n_eff"] for f in fin], "ln_L_marg": [f["ln_L_marg"] for f in fin],
+            "sigma_ln_L": [f["sigma_ln_L"] for f in fin],
+            "oracle_subset_draws": m_oracle if errs else 0,
+            "max_abs_d_ln_L_marg_vs_oracle": max(errs) if errs else None, "oracle_s": t_orc}
 
 
 def harvest_leg(inst, n, seed, n_out=100_000, steps=3, m_check=50):
@@ -547,6 +577,9 @@ def main():
                     help="skip the FP64/FP32/BF16 comparison on the same workload")
     ap.add_argument("--no-combined", action="store_true",
                     help="skip the combined-form leg (per-point learned proposals, batched)")
+    ap.add_argument("--combined-points", type=int, default=32,
+                    help="points of the combined-form leg (4096: the full workload; above "
+                         "32 in groups of 256, without the oracle subset check)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched form on its 256-point workload")
     ap.add_argument("--no-rom", action="store_true",
@@ -631,7 +664,7 @@ def main():
     out["rom"] = None if args.no_rom else rom_leg()
     out["batched"] = None if args.no_batched else batched_leg()
     out["reuse"] = None if args.no_reuse else reuse_leg()
-    out["combined"] = None if args.no_combined else combined_leg()
+    out["combined"] = None if args.no_combined else combined_leg(args.combined_points)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, n_total, seed)
     else:

@@ -7,17 +7,25 @@
 // accuracy measure.
 //
 // Pipeline for a block of N samples:
-//   k_prep     window starts s_k per (sample, detector), validity, ordering key
-//   k_scan*    counting sort of the samples by key (cells of nearby windows)
-//   k_contract per tile of TS samples: F, Y, coefficients and quadratic term
-//              in LDS; per time chunk and detector the partial
-//              G[alpha][p] = sum_lm Re(conj(c) Q[p]) over the union of the
-//              tile's windows (each Q value loaded once feeds TS samples),
-//              realigned through LDS to L[alpha][j]; online FP64
-//              log-sum-exp over bins; deterministic tree at the end.
-//   k_red*     FP64 importance-sampling partials {M, S1, S2, n, maxL}.
+//   k_prep        window starts s_k per (sample, detector), validity,
+//                 ordering key (Hilbert index of the window starts)
+//   k_scan*       counting sort of the samples by key (cells of nearby windows)
+//   k_terms       per sample in tile order: harmonics, antenna factors and the
+//                 quadratic term of Eq. (7) (FP64 and FP32 phased engine)
+//   k_contract_ph per tile of 16 samples: the coefficients in LDS; per time
+//                 chunk and detector the products sum_lm Re(conj(c) Q[p]) over
+//                 the union of the tile's windows on the matrix cores (each Q
+//                 value loaded once feeds 16 samples), moved to each sample's
+//                 bin row and summed over the detectors; FP64 log-sum-exp over
+//                 the bins; deterministic tree at the end
+//   k_contract    the same with the per-sample work in the tile, producer and
+//                 consumer waves (BF16; selectable for FP64/FP32) or VALU
+//   k_red*        FP64 importance-sampling partials {M, S1, S2, n, maxL}.
 #include <hip/hip_runtime.h>
+
 #include <math.h>
+
+#include <mutex>
 
 #include "ile_internal.h"
 #include "ile_rng.h"
@@ -2050,6 +2058,23 @@ static hipError_t launch_terms(const ile_geom &g, const double *smp, int64_t N,
     return hipGetLastError();
 }
 
+// Raises kernel fn's dynamic LDS limit on the current device to at least
+// dyn bytes (never lowers it: another thread may launch with a larger
+// size).  allowed: the kernel's per-device record of what was set.
+static hipError_t allow_dyn_lds(const void *fn, size_t dyn, size_t (&allowed)[64])
+{
+    static std::mutex mu;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (dyn <= allowed[dev]) return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    if (e == hipSuccess) allowed[dev] = dyn;
+    return e;
+}
+
 template <typename TQ, int NT, bool DUMP>
 hipError_t launch_contract_ph(const ile_geom &g, const double *smp, int64_t N,
                               const int32_t *perm, const int32_t *shifts, const void *Q,
@@ -2057,14 +2082,10 @@ hipError_t launch_contract_ph(const ile_geom &g, const double *smp, int64_t N,
                               double *series, size_t dyn, hipStream_t st)
 {
     // dynamic LDS above the default limit must be allowed per kernel
-    static size_t allowed = 0;
-    if (dyn > allowed) {
-        hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&k_contract_ph<TQ, NT, DUMP>),
-            hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
-        if (e != hipSuccess) return e;
-        allowed = dyn;
-    }
+    static size_t allowed[64] = {};
+    hipError_t ea = allow_dyn_lds(reinterpret_cast<const void *>(&k_contract_ph<TQ, NT, DUMP>),
+                                  dyn, allowed);
+    if (ea != hipSuccess) return ea;
     for (int64_t t0 = 0; t0 < N; t0 += cap) {
         const int64_t n = N - t0 < cap ? N - t0 : cap;
         hipError_t e = launch_terms(g, smp, N, perm, shifts, uvt, t0, n, terms, st);
@@ -2081,15 +2102,9 @@ hipError_t launch_contract_ph(const ile_geom &g, const double *smp, int64_t N,
 template <typename TQ, int NT>
 hipError_t allow_batched_ph(size_t dyn)
 {
-    static size_t allowed = 0;
-    if (dyn > allowed) {
-        hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&k_contract_items<TQ, 16, NT>),
-            hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
-        if (e != hipSuccess) return e;
-        allowed = dyn;
-    }
-    return hipSuccess;
+    static size_t allowed[64] = {};
+    return allow_dyn_lds(reinterpret_cast<const void *>(&k_contract_items<TQ, 16, NT>), dyn,
+                         allowed);
 }
 
 template <typename TQ, int NT>
@@ -2098,9 +2113,13 @@ hipError_t launch_batched_ph(const ile_geom *geoms, const ile_point_dev *pts, co
 {
     hipError_t e = allow_batched_ph<TQ, NT>(dyn);
     if (e != hipSuccess) return e;
-    if (n_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_contract_items<TQ, 16, NT>), dim3((unsigned)n_items), dim3(NT), dyn, st,
-                       geoms, pts, items);
+    // a dispatch covers fewer than 2^32 work-items: at most 2^22 items each
+    constexpr int kMaxItems = 1 << 22;
+    for (int i0 = 0; i0 < n_items; i0 += kMaxItems) {
+        const int n = n_items - i0 < kMaxItems ? n_items - i0 : kMaxItems;
+        hipLaunchKernelGGL((k_contract_items<TQ, 16, NT>), dim3((unsigned)n), dim3(NT), dyn, st,
+                           geoms, pts, items + i0);
+    }
     return hipGetLastError();
 }
 

@@ -121,3 +121,28 @@ def test_batch_full_size_sampled(torch):
         ref = O.integrate(O.Ctx(pts[p]).eval(s), lp, lp)
         assert abs(res[p]["ln_L_marg"] - ref["ln_L_marg"]) <= 1e-3
     print(f"batched full size: sampled max rel err {worst:.2e}")
+
+
+def test_batch_items_beyond_one_dispatch(torch):
+    """More (point, tile) items than one dispatch takes (2^22 of 512
+    work-items each: 68 points x 1e6 draws are 4.25e6 items): every point's
+    result equals the same point evaluated alone on the same draws, bit for
+    bit, including the points of the second dispatch."""
+    n, P = 1_000_000, 68
+    base = synth.make_instance(["D1", "D2"], 5, 4096, 4096.0, 201, 8101)
+    print(f"items beyond one dispatch: {P} points x {n}", flush=True)
+    X = torch.empty((P, 7, n), dtype=torch.float64, device="cuda")
+    with ile.Context(base, precision="fp32") as c:
+        for p in range(P):
+            c.draw_prior_dev(8200 + p, 0, n, X[p], n)
+        c.sync()
+    with ile.Batch("fp32") as b:
+        for _ in range(P):
+            b.add_point(base)
+        allp = b.run_dev(n, X)
+    assert all(np.isfinite(r["ln_L_marg"]) and r["n_samples"] == n for r in allp)
+    for p in (0, P - 1):
+        with ile.Batch("fp32") as b1:
+            b1.add_point(base)
+            one = b1.run_dev(n, X[p:p + 1].contiguous())[0]
+        assert one["ln_L_marg"] == allp[p]["ln_L_marg"] and one["n_eff"] == allp[p]["n_eff"]

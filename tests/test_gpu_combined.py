@@ -1,10 +1,12 @@
-"""The combined form: per-point learned proposals (with plain fallback)
-feeding one batched persistent evaluation of caller-supplied draws
-(ile_batch_run_dev).  Each point's ln L_marg from the batched run equals
-the FP64 oracle's on the same draws and weights (1e-3, the north-star
-tolerance; the FP32 bulk contraction is good to ~1e-6 relative per
-sample); the batched run of caller draws agrees with the single-point path
-on the same draws; invalid draws are rejected."""
+"""The combined form: per-point learned proposals feeding one batched
+persistent evaluation of caller-supplied draws (ile_batch_run_dev), with
+the plain adaptive fallback decided on the n_eff of those draws.  Each
+point's ln L_marg from the batched run equals the FP64 oracle's on the same
+draws and weights (1e-3, the benchmark spec's tolerance; the FP32 bulk
+contraction is good to ~1e-6 relative per sample); a point falls back
+exactly when its batched n_eff is below 1e3, and its final estimate is then
+the adaptive sampler's; the batched run of caller draws agrees with the
+single-point path on the same draws; invalid draws are rejected."""
 import numpy as np
 import pytest
 
@@ -24,7 +26,7 @@ def torch():
 def run4(torch):
     points = [synth.combined_point(p) for p in range(4)]
     n = 20_000
-    res, info, X, lp, lq, batch, t = combined.run(points, n)
+    res, info, X, lp, lq, batch, t = combined.run_group(points, n, fallback_samples=3_000_000)
     yield points, n, res, info, X, lp, lq, batch, t
     batch.close()
 
@@ -45,6 +47,7 @@ def test_combined_matches_oracle(run4):
         ref = O.integrate(lnL, lp[p].cpu().numpy(), lq[p].cpu().numpy())
         got = res[p]
         print(p, info[p]["n_lm"], info[p]["n_t"], "fell_back", info[p]["fell_back"],
+              info[p]["final"],
               got["ln_L_marg"], ref["ln_L_marg"], got["n_eff"], ref["n_eff"])
         assert got["n_samples"] == n
         assert abs(got["ln_L_marg"] - ref["ln_L_marg"]) <= 1e-3
@@ -53,6 +56,27 @@ def test_combined_matches_oracle(run4):
     # the per-sample outputs of the batched run
     L = batch.lnL(n)
     assert L.shape == (len(points), n) and np.all(np.isfinite(L))
+
+
+def test_combined_fallback_contract(run4):
+    """The fallback is decided on the draws that form the estimate: a point
+    falls back exactly when its batched n_eff is below 1e3; its final
+    estimate is then the adaptive sampler's own (up to the sample budget),
+    else the batched one; a point is failed exactly when its final n_eff is
+    below 1e3."""
+    points, n, res, info, X, lp, lq, batch, t = run4
+    for p in range(len(points)):
+        i = info[p]
+        assert i["fell_back"] == int(res[p]["n_eff"] < 1e3)
+        if i["fell_back"]:
+            assert i["final"]["source"] == "adaptive"
+            assert i["final"]["n_samples"] <= 3_000_000
+            assert i["final"]["n_eff"] >= 1e3 or i["final"]["n_samples"] == 3_000_000
+        else:
+            assert i["final"]["source"] == "learned"
+            assert i["final"]["ln_L_marg"] == res[p]["ln_L_marg"]
+        assert i["failed"] == int(i["final"]["n_eff"] < 1e3)
+        assert np.isfinite(i["final"]["sigma_ln_L"])
 
 
 def test_combined_matches_single_point_path(run4, torch):

@@ -6,10 +6,11 @@ modes, 16384 samples at 16384 Hz, 1601 bins, network SNR 20).
 * P2 through the device path: ln L at the injected parameters and centre
   bin equals rho^2/2 = 200.
 * The learned sampler against the plain adaptive sampler, both run to
-  n_eff = 1e4: the estimates agree within their combined standard error,
-  the learned one gets there at a higher n_eff per second, and on one
-  chunk of its own draws the device ln L_marg equals the oracle's (same
-  samples, same weights) within 1e-3.
+  n_eff = 1e4: every learned seed reaches the target without falling back
+  and agrees with an independent long-run reference (sigma <= 1e-4) within
+  1e-3 plus three combined standard errors, the learned one gets there at a
+  higher n_eff per second, and on one chunk of its own draws the device
+  ln L_marg equals the oracle's (same samples, same weights) within 1e-3.
 """
 import time
 
@@ -85,14 +86,24 @@ def test_injection_recovered_on_device():
     assert np.all(np.delete(L, jc) < rho2 / 2)
 
 
+def _reference(ctx, seed=9001, n=300_000_000):
+    """An independent estimate of ln L_marg on the same workload: a learned
+    run on a seed outside the judged ones, its network trained as usual, then
+    n draws of its defensive mixture (1 - eps) q_net + eps q_hist, which is
+    unbiased for any q that covers the support (Eq. (4); the defensive part
+    does).  sigma: the relative standard error of the weights' mean (Sec.
+    II.C), about 3e-5 here (n_eff, sum w / max w, a few 1e5)."""
+    with ile.Proposal(ctx, seed=7) as p:
+        return ctx.run(sampler="learned", seed=seed, chunk=1_000_000, max_samples=n,
+                       n_eff_target=1e12, adapt_chunks=3, prop=p, eps=0.1)
+
+
 def test_learned_beats_plain_to_neff_1e4(torch):
     """Learned vs plain to n_eff = 1e4 on the injection workload.  Each run
-    seed trains its own network on its own draws, and a run falls back to the
-    plain sampler when its first estimation chunk has n_eff < 1e3, which a
-    minority of seeds do (rounding changes anywhere in the chain move which
-    ones); four seeds are run and at least two must reach the target
-    without falling back.  Every run's estimate must agree with the plain
-    one within its standard error, the median rate must beat the plain
+    seed trains its own network on its own draws; all four seeds must reach
+    the target without falling back.  Each estimate must agree with an
+    independent reference of sigma <= 1e-4 (a long defensive-mixture run,
+    _reference) within 1e-3 + 3 sigma, the median rate must beat the plain
     rate, and the device ln L_marg of fresh draws must equal the oracle's on
     the same samples."""
     from oracle import oracle as O
@@ -124,6 +135,9 @@ def test_learned_beats_plain_to_neff_1e4(torch):
                     x, lpv, lqv = xd.cpu().numpy(), lp.cpu().numpy(), lq.cpu().numpy()
                     got = ctx.integrate(x, lpv, lqv)
             runs.append((lrn, t_lrn, ok))
+        ref = _reference(ctx)
+    print(f"reference: {ref}")
+    assert ref["sigma_ln_L"] <= 1e-4
     ne_plain = plain["n_eff"] / t_plain
     print(f"plain:   {plain} in {t_plain:.2f} s ({ne_plain:.1f} n_eff/s)")
     rates = []
@@ -131,9 +145,12 @@ def test_learned_beats_plain_to_neff_1e4(torch):
         rates.append(lrn["n_eff"] / t_lrn)
         print(f"learned: ok={ok} n_eff={lrn['n_eff']:.0f} in {t_lrn:.2f} s ({rates[-1]:.0f} n_eff/s) "
               f"ln L {lrn['ln_L_marg']:.4f} +- {lrn['sigma_ln_L']:.4f} fell_back={lrn['fell_back']}")
-        sig = np.hypot(plain["sigma_ln_L"], lrn["sigma_ln_L"])
-        assert abs(plain["ln_L_marg"] - lrn["ln_L_marg"]) < 4 * sig + 1e-3
-    assert sum(ok for _, _, ok in runs) >= 2
+        assert ok
+        sig = np.hypot(ref["sigma_ln_L"], lrn["sigma_ln_L"])
+        assert abs(ref["ln_L_marg"] - lrn["ln_L_marg"]) <= 1e-3 + 3 * sig
+        # the plain run (n_eff about 20 at its budget) is far less precise
+        sig_p = np.hypot(ref["sigma_ln_L"], plain["sigma_ln_L"])
+        assert abs(ref["ln_L_marg"] - plain["ln_L_marg"]) <= 4 * sig_p
     assert np.median(rates) > ne_plain
     # same samples, same weights: device vs oracle ln L_marg
     cfg = synth.config4_parts()
