@@ -48,6 +48,7 @@ const void *ile_ctx_Q(const ile_ctx *c);
 const double *ile_ctx_U(const ile_ctx *c);
 const double *ile_ctx_V(const ile_ctx *c);
 ile_precision ile_ctx_precision(const ile_ctx *c);
+const double *ile_ctx_uvt(const ile_ctx *c);
 
 struct ile_ctx {
     ile_config cfg{};
@@ -398,6 +399,7 @@ const void *ile_ctx_Q(const ile_ctx *c) { return c->Q.p; }
 const double *ile_ctx_U(const ile_ctx *c) { return (const double *)c->U.p; }
 const double *ile_ctx_V(const ile_ctx *c) { return (const double *)c->V.p; }
 ile_precision ile_ctx_precision(const ile_ctx *c) { return c->cfg.precision; }
+const double *ile_ctx_uvt(const ile_ctx *c) { return (const double *)c->uvt.p; }
 hipStream_t ile_ctx_stream(const ile_ctx *c) { return c->stream; }
 int ile_ctx_hist(const ile_ctx *c, const double **P, const double **C)
 {

@@ -23,6 +23,7 @@ const ile_geom &ile_ctx_geom(const ile_ctx *c);
 const void *ile_ctx_Q(const ile_ctx *c);
 const double *ile_ctx_U(const ile_ctx *c);
 const double *ile_ctx_V(const ile_ctx *c);
+const double *ile_ctx_uvt(const ile_ctx *c);
 
 namespace {
 
@@ -32,6 +33,9 @@ struct Buf {
 };
 
 constexpr int kKeyBits = 15;   // ordering key bits per point (buckets 2^15 + 1)
+// Largest per-sample terms buffer of one batched run (the phased engine);
+// a run that needs more forms the terms in its tiles.
+constexpr size_t kMaxTermsBytes = (size_t)32 << 30;
 
 }  // namespace
 
@@ -45,7 +49,7 @@ struct ile_batch {
     int cu_count = 0, lds_max = 0;
     std::string dev_name;
     Buf geoms, pdev, items, offs, seed, counter, smp, out, shifts, keys, perm, hist, scan_tmp,
-        errflag, res, lw;
+        errflag, res, lw, terms;
     // graph of one run and what it was built for
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -180,6 +184,14 @@ ile_status build(ile_batch *b, int64_t n, double dmin, double dmax, bool ext)
     if ((s = bensure(b, b->errflag, 16))) return s;
     if ((s = bensure(b, b->res, (size_t)P * 6 * sizeof(double)))) return s;
     if (ext && (s = bensure(b, b->lw, (size_t)NT * sizeof(double)))) return s;
+    // the phased engine's per-sample terms, per point, when they fit in
+    // kMaxTermsBytes (else the tiles form them)
+    std::vector<size_t> toff(P + 1, 0);
+    const bool ph = ile_contract_uses_terms(b->cfg.precision, tu);
+    for (int p = 0; p < P; p++)
+        toff[p + 1] = toff[p] + (size_t)ile_terms_fields(gs[p]) * (size_t)((n + 15) & ~15);
+    const bool use_terms = ph && toff[P] * sizeof(double) <= kMaxTermsBytes;
+    if (use_terms && (s = bensure(b, b->terms, toff[P] * sizeof(double)))) return s;
     double *smp = (double *)b->smp.p, *out = (double *)b->out.p;
     int32_t *sh = (int32_t *)b->shifts.p, *perm = (int32_t *)b->perm.p;
     for (int p = 0; p < P; p++) {
@@ -191,6 +203,7 @@ ile_status build(ile_batch *b, int64_t n, double dmin, double dmax, bool ext)
         pd[p].perm = perm + offs[p];
         pd[p].shifts = sh + (int64_t)ILE_MAX_DET * offs[p];
         pd[p].out = out + offs[p];
+        pd[p].terms = use_terms ? (const double *)b->terms.p + toff[p] : nullptr;
     }
     // queue: tiles of every point; order 0 = decreasing per-tile cost
     std::vector<int> order(P);
@@ -236,10 +249,14 @@ ile_status build(ile_batch *b, int64_t n, double dmin, double dmax, bool ext)
     step(ile_launch_scan((uint32_t *)b->hist.p, nb, (uint32_t *)b->scan_tmp.p, st));
     step(ile_launch_scatter_multi((const uint32_t *)b->keys.p, (const int64_t *)b->offs.p, P,
                                   NT, (uint32_t *)b->hist.p, perm, st));
+    if (use_terms)
+        for (int p = 0; p < P; p++)
+            step(ile_launch_terms(gs[p], pd[p].smp, n, pd[p].perm, pd[p].shifts,
+                                  ile_ctx_uvt(b->pts[p]), (double *)pd[p].terms, st));
     step(ile_launch_contract_batched(b->cfg.precision, tu, (const ile_geom *)b->geoms.p,
                                      (const ile_point_dev *)b->pdev.p,
                                      (const int2 *)b->items.p, (int)items.size(),
-                                     (unsigned *)b->counter.p, grid, dyn, st));
+                                     (unsigned *)b->counter.p, grid, dyn, use_terms, st));
     step(ile_launch_reduce_points(out, ext ? (const double *)b->lw.p : nullptr,
                                   (const int64_t *)b->offs.p, P, (double *)b->res.p, st));
     hipGraph_t g = nullptr;
@@ -557,7 +574,7 @@ void ile_batch_destroy(ile_batch *b)
     for (ile_ctx *c : b->pts) ile_destroy(c);
     for (Buf *x : {&b->geoms, &b->pdev, &b->items, &b->offs, &b->seed, &b->counter, &b->smp,
                    &b->out, &b->shifts, &b->keys, &b->perm, &b->hist, &b->scan_tmp, &b->errflag,
-                   &b->res})
+                   &b->res, &b->lw, &b->terms})
         if (x->p) (void)hipFree(x->p);
     if (b->e0) (void)hipEventDestroy(b->e0);
     if (b->e1) (void)hipEventDestroy(b->e1);

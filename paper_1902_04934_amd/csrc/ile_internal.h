@@ -67,6 +67,9 @@ struct ile_point_dev {
     const int32_t *perm;      // sorted order (local indices)
     const int32_t *shifts;    // window starts [n_det][N]
     double *out;              // lnLmargT [N]
+    // phased engine: the point's per-sample terms (ile_launch_terms, tile
+    // order from position 0), or null to form them in the tiles
+    const double *terms;
 };
 
 // Increment table[key] by one for every active lane, aggregated over the
@@ -209,6 +212,11 @@ hipError_t ile_launch_identity(int32_t *perm, int64_t N, hipStream_t st);
 // window starts are zero for an invalid sample.
 int ile_terms_fields(const ile_geom &g);
 bool ile_contract_uses_terms(ile_precision prec, const ile_tune &tu);
+// The terms of positions 0 .. N-1 of one point into terms (16 F round16(N)
+// doubles); uvt as for ile_launch_contract.
+hipError_t ile_launch_terms(const ile_geom &g, const double *smp, int64_t N,
+                            const int32_t *perm, const int32_t *shifts, const double *uvt,
+                            double *terms, hipStream_t st);
 // Positions per launch of the terms (a multiple of 16): the buffer for N
 // samples holds ile_terms_fields x min(N, ILE_TERMS_CHUNK) doubles.
 #define ILE_TERMS_CHUNK ((int64_t)1 << 21)
@@ -258,7 +266,7 @@ hipError_t ile_contract_batched_allow(ile_precision prec, const ile_tune &tu, si
 hipError_t ile_launch_contract_batched(ile_precision prec, const ile_tune &tu,
                                        const ile_geom *geoms, const ile_point_dev *pts,
                                        const int2 *items, int n_items, unsigned *counter,
-                                       int grid, size_t dyn, hipStream_t st);
+                                       int grid, size_t dyn, bool terms, hipStream_t st);
 hipError_t ile_launch_prior_multi(const uint64_t *seed_dev, const int64_t *offs, int n_points,
                                   int64_t n_total, double d_min, double d_max,
                                   double t_ref_max, double *smp, hipStream_t st);

@@ -1798,20 +1798,26 @@ __global__ __launch_bounds__(NT, (contract_min_waves<NT, ENG>())) void k_contrac
 
 // Many intrinsic points on the phased engine: one workgroup per (point,
 // tile) item, in list order (the host sorts the list by decreasing cost and
-// the dispatcher starts workgroups in that order).  Not persistent: every
+// the dispatcher starts workgroups in that order).  PRE: every point carries
+// its per-sample terms; else the tiles form them.  Not persistent: every
 // load of the point's parameters precedes the kernel's only store, so they
 // are read through the scalar unit instead of being held in registers
 // across a queue loop.
-template <typename TQ, int TS, int NT>
+template <typename TQ, int TS, int NT, bool PRE>
 __global__ __launch_bounds__(NT, (contract_min_waves<NT, ENG_PH>())) void k_contract_items(
     const ile_geom *__restrict__ geoms, const ile_point_dev *__restrict__ pts,
     const int2 *__restrict__ items)
 {
     const int2 w = items[blockIdx.x];
     const ile_point_dev &P = pts[w.x];
-    contract_tile_ph<TQ, TS, NT, false, false>(geoms[w.x], (int64_t)w.y * TS, P.smp, P.N,
-                                               P.perm, P.shifts, (const TQ *)P.Q, P.U, P.V,
-                                               nullptr, 0, P.out, nullptr);
+    if (PRE)
+        contract_tile_ph<TQ, TS, NT, false, true>(geoms[w.x], (int64_t)w.y * TS, P.smp, P.N,
+                                                  P.perm, P.shifts, (const TQ *)P.Q, P.U, P.V,
+                                                  P.terms, 0, P.out, nullptr);
+    else
+        contract_tile_ph<TQ, TS, NT, false, false>(geoms[w.x], (int64_t)w.y * TS, P.smp, P.N,
+                                                   P.perm, P.shifts, (const TQ *)P.Q, P.U, P.V,
+                                                   nullptr, 0, P.out, nullptr);
 }
 
 // One point on the phased engine with its per-sample terms precomputed:
@@ -2102,14 +2108,17 @@ hipError_t launch_contract_ph(const ile_geom &g, const double *smp, int64_t N,
 template <typename TQ, int NT>
 hipError_t allow_batched_ph(size_t dyn)
 {
-    static size_t allowed[64] = {};
-    return allow_dyn_lds(reinterpret_cast<const void *>(&k_contract_items<TQ, 16, NT>), dyn,
-                         allowed);
+    static size_t allowed[64] = {}, allowed_pre[64] = {};
+    hipError_t e = allow_dyn_lds(reinterpret_cast<const void *>(&k_contract_items<TQ, 16, NT, false>),
+                                 dyn, allowed);
+    if (e != hipSuccess) return e;
+    return allow_dyn_lds(reinterpret_cast<const void *>(&k_contract_items<TQ, 16, NT, true>), dyn,
+                         allowed_pre);
 }
 
 template <typename TQ, int NT>
 hipError_t launch_batched_ph(const ile_geom *geoms, const ile_point_dev *pts, const int2 *items,
-                             int n_items, size_t dyn, hipStream_t st)
+                             int n_items, size_t dyn, bool pre, hipStream_t st)
 {
     hipError_t e = allow_batched_ph<TQ, NT>(dyn);
     if (e != hipSuccess) return e;
@@ -2117,8 +2126,12 @@ hipError_t launch_batched_ph(const ile_geom *geoms, const ile_point_dev *pts, co
     constexpr int kMaxItems = 1 << 22;
     for (int i0 = 0; i0 < n_items; i0 += kMaxItems) {
         const int n = n_items - i0 < kMaxItems ? n_items - i0 : kMaxItems;
-        hipLaunchKernelGGL((k_contract_items<TQ, 16, NT>), dim3((unsigned)n), dim3(NT), dyn, st,
-                           geoms, pts, items + i0);
+        if (pre)
+            hipLaunchKernelGGL((k_contract_items<TQ, 16, NT, true>), dim3((unsigned)n), dim3(NT),
+                               dyn, st, geoms, pts, items + i0);
+        else
+            hipLaunchKernelGGL((k_contract_items<TQ, 16, NT, false>), dim3((unsigned)n), dim3(NT),
+                               dyn, st, geoms, pts, items + i0);
     }
     return hipGetLastError();
 }
@@ -2234,6 +2247,15 @@ bool ile_tune_supported(ile_precision prec, const ile_tune &tu)
 
 int ile_terms_fields(const ile_geom &g) { return 2 + 3 * g.n_det + 2 * g.n_lm; }
 
+hipError_t ile_launch_terms(const ile_geom &g, const double *smp, int64_t N,
+                            const int32_t *perm, const int32_t *shifts, const double *uvt,
+                            double *terms, hipStream_t st)
+{
+    if (N <= 0) return hipSuccess;
+    if (terms_lds_bytes(g) > 64 * 1024) return hipErrorInvalidValue;
+    return launch_terms(g, smp, N, perm, shifts, (const double4 *)uvt, 0, N, terms, st);
+}
+
 bool ile_contract_uses_terms(ile_precision prec, const ile_tune &tu)
 {
     return tu.engine == ENG_PH && prec != ILE_BF16;
@@ -2327,7 +2349,7 @@ hipError_t ile_contract_batched_allow(ile_precision prec, const ile_tune &tu, si
 hipError_t ile_launch_contract_batched(ile_precision prec, const ile_tune &tu,
                                        const ile_geom *geoms, const ile_point_dev *pts,
                                        const int2 *items, int n_items, unsigned *counter,
-                                       int grid, size_t dyn, hipStream_t st)
+                                       int grid, size_t dyn, bool terms, hipStream_t st)
 {
     if (!ile_tune_supported(prec, tu)) return hipErrorInvalidValue;
     if (tu.engine == ENG_PH) {
@@ -2335,10 +2357,11 @@ hipError_t ile_launch_contract_batched(ile_precision prec, const ile_tune &tu,
         // kernels of the other engines)
         if (prec == ILE_FP64)
             return tu.threads == 256
-                       ? launch_batched_ph<double, 256>(geoms, pts, items, n_items, dyn, st)
-                       : launch_batched_ph<double, 512>(geoms, pts, items, n_items, dyn, st);
-        return tu.threads == 256 ? launch_batched_ph<float, 256>(geoms, pts, items, n_items, dyn, st)
-                                 : launch_batched_ph<float, 512>(geoms, pts, items, n_items, dyn, st);
+                       ? launch_batched_ph<double, 256>(geoms, pts, items, n_items, dyn, terms, st)
+                       : launch_batched_ph<double, 512>(geoms, pts, items, n_items, dyn, terms, st);
+        return tu.threads == 256
+                   ? launch_batched_ph<float, 256>(geoms, pts, items, n_items, dyn, terms, st)
+                   : launch_batched_ph<float, 512>(geoms, pts, items, n_items, dyn, terms, st);
     }
 #define ILE_BATCHED(TQ, NT, ENG)                                                              \
     do {                                                                                      \
