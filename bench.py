@@ -227,7 +227,7 @@ def batched_leg(n_points=256, n=200_000, steps=3, seed=11):
     g = sum(gms) / len(gms)
     flops = n * sum(4 * p.n_det * p.n_lm * p.n_t + 16 * p.n_det * p.n_lm ** 2 for p in pts)
     return {"workload": f"{n_points} points (3 detectors, 5-21 modes, 201-1601 bins, Q 16384 "
-                        f"points FP32), {n} prior samples each, one persistent graph",
+                        f"points FP32), {n} prior samples each, one graph",
             "graph_ms": g, "wall_ms_per_run": wall, "sample_bins_per_s": work / (g * 1e-3),
             "samples_per_s": n * n_points / (g * 1e-3), "tuning": tune,
             "fp32_tflops": flops / (g * 1e-3) / 1e12,
