@@ -222,7 +222,7 @@ ile_status ile_integrate_dev(ile_ctx *ctx, const double *samples_dev,
  * nothing (no hipMalloc, hipFree, event or library allocation): its
  * workspace (per-sample lnL, window starts, sort keys and order, the
  * per-sample terms of Eq. (7), bucket counts, reduction partials) is a fixed
- * array of 50 MiB that every GPU the library runs on holds until the
+ * array of about 55 MiB that every GPU the library runs on holds until the
  * process ends, located in ile_create.  N <= ILE_NOALLOC_MAX_N, else
  * ILE_E_ARG and nothing runs.  The array is shared by every context and call on one GPU and keeps the
  * last call's contents (each call clears what must start at zero): calls

@@ -19,13 +19,15 @@
 // Workspace of ile_integrate_dev_noalloc: a fixed array that every GPU the
 // library runs on holds until the process ends.  Up to ILE_NOALLOC_MAX_N
 // samples: 8 (lnL) + 4 n_det (window starts) + 8 (keys, order) + 8 (2 +
-// 3 n_det + 2 n_lm) (the phased engine's per-sample terms) bytes each, plus
+// 3 n_det + 2 n_lm) (the phased engine's per-sample terms) + 56 + 4 n_det
+// (samples and window starts in tile order) bytes each, plus
 // up to 2^21 + 1 bucket counts, their scan and the reduction partials.
 // Host code never passes `scratch` itself to a kernel (in host code the name
 // is a stand-in, not a device address): it takes the per-device address that
 // hipGetSymbolAddress returned in ile_create.
 constexpr size_t kNoAllocBytes =
-    (size_t)ILE_NOALLOC_MAX_N * (8 + 4 * ILE_MAX_DET + 8 + 8 * (2 + 3 * ILE_MAX_DET + 2 * ILE_MAX_LM)) +
+    (size_t)ILE_NOALLOC_MAX_N *
+        (8 + 4 * ILE_MAX_DET + 8 + 8 * (2 + 3 * ILE_MAX_DET + 2 * ILE_MAX_LM) + 56 + 4 * ILE_MAX_DET) +
     ((size_t)9 << 20);
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
@@ -65,7 +67,7 @@ struct ile_ctx {
     DevBuf Q, U, V;
     DevBuf uvt;                     // upper triangles of U_h and V_s (see ile_launch_contract)
     DevBuf smp, out, lnp, lnq, shifts, keys, perm, hist, scan_tmp, errflag,
-        red_tmp, parts, res, series, terms;
+        red_tmp, parts, res, series, terms, smp_s, sh_s;
     DevBuf hP, hC, bins, hist_tmp;  // adaptive proposal state and scratch
     int hist_nb = 0;
     DevBuf trx, trw;                // training set of the learned sampler
@@ -268,9 +270,13 @@ ile_status ensure_work(ile_ctx *c, int64_t N)
     if ((s = ensure(c, c->errflag, 16))) return s;
     if ((s = ensure(c, c->red_tmp, 4 * (size_t)ile_reduce_blocks() * sizeof(double)))) return s;
     if ((s = ensure(c, c->res, 8 * sizeof(double)))) return s;
-    if (ile_contract_uses_terms(c->cfg.precision, c->tune) &&
-        (s = ensure(c, c->terms, (size_t)ile_terms_fields(c->g) * terms_cap(N) * sizeof(double))))
-        return s;
+    if (ile_contract_uses_terms(c->cfg.precision, c->tune)) {
+        if ((s = ensure(c, c->terms,
+                        (size_t)ile_terms_fields(c->g) * terms_cap(N) * sizeof(double))))
+            return s;
+        if ((s = ensure(c, c->smp_s, n * 7 * sizeof(double)))) return s;
+        if ((s = ensure(c, c->sh_s, n * c->g.n_det * sizeof(int32_t)))) return s;
+    }
     return ILE_OK;
 }
 
@@ -295,13 +301,16 @@ struct Work {
     double *red_tmp;
     double *terms;   // per-sample terms of the phased engine, cap positions
     int64_t cap;
+    double *smp_s;   // the samples [7][N] and window starts [n_det][N] in tile
+    int32_t *sh_s;   // order, for the phased engine's terms pass (or null)
 };
 
 Work ctx_work(ile_ctx *c, int64_t N)
 {
     return Work{(int32_t *)c->shifts.p, (uint32_t *)c->keys.p, (int32_t *)c->perm.p,
                 (uint32_t *)c->hist.p, (uint32_t *)c->scan_tmp.p, (double *)c->red_tmp.p,
-                (double *)c->terms.p, terms_cap(N)};
+                (double *)c->terms.p, terms_cap(N), (double *)c->smp_s.p,
+                (int32_t *)c->sh_s.p};
 }
 
 // The hot path on device data: window starts and ordering, then the fused
@@ -320,11 +329,25 @@ ile_status launch_eval(ile_ctx *c, const Work &w, const double *smp, int64_t N, 
     HIP_TRY(c, ile_launch_fill_u32(w.hist, 0u, c->n_buckets, st));
     HIP_TRY(c, ile_launch_prep(c->g, smp, N, w.shifts, w.keys, w.hist, c->n_buckets,
                                (int32_t *)c->errflag.p, st));
+    // the phased engine's terms pass reads the samples in tile order: the
+    // sort moves them there (or, unsorted, they are there already)
+    const bool terms = ile_contract_uses_terms(c->cfg.precision, c->tune);
+    const double *smp_s = nullptr;
+    const int32_t *sh_s = nullptr;
     if (c->sort) {
         HIP_TRY(c, ile_launch_scan(w.hist, c->n_buckets, w.scan_tmp, st));
-        HIP_TRY(c, ile_launch_scatter(w.keys, N, w.hist, w.perm, st));
+        if (terms && w.smp_s && w.sh_s) {
+            HIP_TRY(c, ile_launch_scatter_copy(w.keys, N, w.hist, w.perm, smp, w.shifts,
+                                               c->g.n_det, w.smp_s, w.sh_s, st));
+            smp_s = w.smp_s;
+            sh_s = w.sh_s;
+        } else {
+            HIP_TRY(c, ile_launch_scatter(w.keys, N, w.hist, w.perm, st));
+        }
     } else {
         HIP_TRY(c, ile_launch_identity(w.perm, N, st));
+        smp_s = smp;
+        sh_s = w.shifts;
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
@@ -335,8 +358,8 @@ ile_status launch_eval(ile_ctx *c, const Work &w, const double *smp, int64_t N, 
     }
     HIP_TRY(c, ile_launch_contract(c->g, c->cfg.precision, c->tune, smp, N, w.perm, w.shifts,
                                    c->Q.p, (const double *)c->U.p, (const double *)c->V.p,
-                                   (const double *)c->uvt.p, w.terms, w.cap, out, series,
-                                   st));
+                                   smp_s, sh_s, (const double *)c->uvt.p, w.terms, w.cap, out,
+                                   series, st));
     if (timed) HIP_TRY(c, hipEventRecord(e1, st));
     return ILE_OK;
 }
@@ -972,6 +995,8 @@ ile_status ile_integrate_dev_noalloc(ile_ctx *c, const double *smp, const double
     w.red_tmp = (double *)take(4 * (size_t)ile_reduce_blocks() * sizeof(double));
     w.cap = terms_cap(N);
     w.terms = (double *)take((size_t)ile_terms_fields(c->g) * w.cap * sizeof(double));
+    w.smp_s = (double *)take(n * 7 * sizeof(double));
+    w.sh_s = (int32_t *)take(n * c->g.n_det * sizeof(int32_t));
     double *parts = (double *)take(8 * sizeof(double));
     if (off > kNoAllocBytes)
         return fail(c, ILE_E_UNSUPPORTED, "workspace needs %zu bytes, the fixed array has %zu",
@@ -1574,7 +1599,7 @@ void ile_destroy(ile_ctx *c)
                       &c->hP, &c->hC, &c->bins, &c->hist_tmp, &c->trx, &c->trw,
                       &c->hv_w, &c->hv_cdf, &c->hv_ws, &c->hv_part, &c->hv_flag, &c->hv_sel,
                       &c->fd_tmp, &c->fd_flag, &c->fd_in, &c->fd_out, &c->rom_A, &c->rom_Z,
-                      &c->uvt, &c->terms})
+                      &c->uvt, &c->terms, &c->smp_s, &c->sh_s})
         release(*b);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);

@@ -200,6 +200,11 @@ hipError_t ile_launch_scan(uint32_t *v, int64_t n, uint32_t *tmp, hipStream_t st
 int64_t ile_scan_tmp_words(int64_t n);
 hipError_t ile_launch_scatter(const uint32_t *keys, int64_t N, uint32_t *offs,
                               int32_t *perm, hipStream_t st);
+// The scatter plus copies of the samples [7][N] and window starts [nd][N]
+// in tile order into smp_s, sh_s.
+hipError_t ile_launch_scatter_copy(const uint32_t *keys, int64_t N, uint32_t *offs,
+                                   int32_t *perm, const double *smp, const int32_t *shifts,
+                                   int nd, double *smp_s, int32_t *sh_s, hipStream_t st);
 hipError_t ile_launch_identity(int32_t *perm, int64_t N, hipStream_t st);
 // Per-sample terms of Eq. (7) that the phased engine reads instead of
 // forming them in its tiles (kernel k_terms, run by ile_launch_contract
@@ -225,12 +230,16 @@ hipError_t ile_launch_terms(const ile_geom &g, const double *smp, int64_t N,
 // a (a - 1) / 2 + b - a) as (Re U_h, Im U_h, Re V_s, Im V_s); terms: a buffer
 // of ile_terms_fields x cap doubles, cap >= 16 a multiple of 16 (both used
 // when ile_contract_uses_terms, else may be null).
+// smp_s, sh_s: the samples and window starts already in tile order (the
+// terms pass then reads them in order), or null (it gathers them through
+// perm).
 hipError_t ile_launch_contract(const ile_geom &g, ile_precision prec,
                                const ile_tune &tu, const double *smp, int64_t N,
                                const int32_t *perm, const int32_t *shifts,
                                const void *Q, const double *U, const double *V,
-                               const double *uvt, double *terms, int64_t cap, double *out,
-                               double *series, hipStream_t st);
+                               const double *smp_s, const int32_t *sh_s, const double *uvt,
+                               double *terms, int64_t cap, double *out, double *series,
+                               hipStream_t st);
 size_t ile_contract_lds_bytes(const ile_geom &g, ile_precision prec,
                               const ile_tune &tu);
 hipError_t ile_launch_prior(uint64_t seed, int64_t first, int64_t N,

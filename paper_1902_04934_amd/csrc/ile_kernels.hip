@@ -340,6 +340,25 @@ __global__ __launch_bounds__(256) void k_scatter(const uint32_t *__restrict__ ke
     perm[pos] = (int32_t)i;
 }
 
+// The scatter that also moves each sample's parameters and window starts
+// to its place in tile order (read in sample order, so the terms pass then
+// reads them coalesced instead of gathering them through perm).
+__global__ __launch_bounds__(256) void k_scatter_copy(const uint32_t *__restrict__ keys,
+                                                      int64_t N, uint32_t *offs, int32_t *perm,
+                                                      const double *__restrict__ smp,
+                                                      const int32_t *__restrict__ shifts, int nd,
+                                                      double *__restrict__ smp_s,
+                                                      int32_t *__restrict__ sh_s)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const uint32_t pos = wave_count_slot(offs, keys[i]);
+    perm[pos] = (int32_t)i;
+#pragma unroll
+    for (int p = 0; p < 7; p++) smp_s[(int64_t)p * N + pos] = smp[(int64_t)p * N + i];
+    for (int k = 0; k < nd; k++) sh_s[(int64_t)k * N + pos] = shifts[(int64_t)k * N + i];
+}
+
 __global__ __launch_bounds__(256) void k_identity(int32_t *perm, int64_t N)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -942,17 +961,20 @@ struct TermsSample {
 __device__ __forceinline__ void terms_intake(const ile_geom &g, const double *__restrict__ smp,
                                              int64_t N, const int32_t *__restrict__ perm,
                                              const int32_t *__restrict__ shifts, int64_t i,
-                                             TermsSample &S, double (&cp)[kPw],
+                                             bool in_order, TermsSample &S, double (&cp)[kPw],
                                              double (&sp)[kPw], double (&er)[kPw],
                                              double (&ei)[kPw])
 {
     const int nd = g.n_det;
     S.idx = perm[i];
+    // in_order: smp and shifts are already in tile order (a coalesced read);
+    // else gathered through the permutation
+    const int64_t src = in_order ? i : S.idx;
     double th[7];
 #pragma unroll
-    for (int p = 0; p < 7; p++) th[p] = smp[(int64_t)p * N + S.idx];
+    for (int p = 0; p < 7; p++) th[p] = smp[(int64_t)p * N + src];
 #pragma unroll
-    for (int k = 0; k < ILE_MAX_DET; k++) S.sd[k] = k < nd ? shifts[(int64_t)k * N + S.idx] : 0;
+    for (int k = 0; k < ILE_MAX_DET; k++) S.sd[k] = k < nd ? shifts[(int64_t)k * N + src] : 0;
     bool ok = sample_ok(g, th);
 #pragma unroll
     for (int k = 0; k < ILE_MAX_DET; k++)
@@ -1052,8 +1074,8 @@ constexpr int kTermsT = 64;    // lanes per block
 // are read at uniform addresses (scalar loads), four entries per step.
 __global__ __launch_bounds__(kTermsT) void k_terms(
     ile_geom g, const double *__restrict__ smp, int64_t N, const int32_t *__restrict__ perm,
-    const int32_t *__restrict__ shifts, const double4 *__restrict__ uvt, int64_t t0, int64_t n,
-    double *__restrict__ terms)
+    const int32_t *__restrict__ shifts, bool in_order, const double4 *__restrict__ uvt,
+    int64_t t0, int64_t n, double *__restrict__ terms)
 {
     extern __shared__ __align__(16) unsigned char dyn_lds[];
     const int lane = threadIdx.x;
@@ -1064,7 +1086,7 @@ __global__ __launch_bounds__(kTermsT) void k_terms(
     double *tp = terms_slot(g, terms, r);
     TermsSample S;
     double cp[kPw], sp[kPw], er[kPw], ei[kPw];
-    terms_intake(g, smp, N, perm, shifts, t0 + r, S, cp, sp, er, ei);
+    terms_intake(g, smp, N, perm, shifts, t0 + r, in_order, S, cp, sp, er, ei);
     for (int a = 0; a < nl; a++) {
         const double2 y = terms_harmonic(g, S, a, cp, sp, er, ei);
         Yl[a * kTermsT + lane] = y;
@@ -2056,11 +2078,12 @@ constexpr size_t kPhBudget64 = 78 * 1024;
 constexpr size_t kPhBudget32 = 50 * 1024;
 
 static hipError_t launch_terms(const ile_geom &g, const double *smp, int64_t N,
-                               const int32_t *perm, const int32_t *shifts, const double4 *uvt,
-                               int64_t t0, int64_t n, double *terms, hipStream_t st)
+                               const int32_t *perm, const int32_t *shifts, bool in_order,
+                               const double4 *uvt, int64_t t0, int64_t n, double *terms,
+                               hipStream_t st)
 {
     hipLaunchKernelGGL(k_terms, dim3(nblk(n, kTermsT)), dim3(kTermsT), terms_lds_bytes(g), st,
-                       g, smp, N, perm, shifts, uvt, t0, n, terms);
+                       g, smp, N, perm, shifts, in_order, uvt, t0, n, terms);
     return hipGetLastError();
 }
 
@@ -2083,9 +2106,10 @@ static hipError_t allow_dyn_lds(const void *fn, size_t dyn, size_t (&allowed)[64
 
 template <typename TQ, int NT, bool DUMP>
 hipError_t launch_contract_ph(const ile_geom &g, const double *smp, int64_t N,
-                              const int32_t *perm, const int32_t *shifts, const void *Q,
-                              const double4 *uvt, double *terms, int64_t cap, double *out,
-                              double *series, size_t dyn, hipStream_t st)
+                              const int32_t *perm, const int32_t *shifts, const double *smp_s,
+                              const int32_t *sh_s, const void *Q, const double4 *uvt,
+                              double *terms, int64_t cap, double *out, double *series, size_t dyn,
+                              hipStream_t st)
 {
     // dynamic LDS above the default limit must be allowed per kernel
     static size_t allowed[64] = {};
@@ -2094,7 +2118,8 @@ hipError_t launch_contract_ph(const ile_geom &g, const double *smp, int64_t N,
     if (ea != hipSuccess) return ea;
     for (int64_t t0 = 0; t0 < N; t0 += cap) {
         const int64_t n = N - t0 < cap ? N - t0 : cap;
-        hipError_t e = launch_terms(g, smp, N, perm, shifts, uvt, t0, n, terms, st);
+        hipError_t e = smp_s ? launch_terms(g, smp_s, N, perm, sh_s, true, uvt, t0, n, terms, st)
+                             : launch_terms(g, smp, N, perm, shifts, false, uvt, t0, n, terms, st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_contract_ph<TQ, NT, DUMP>), dim3(nblk(n, 16)), dim3(NT), dyn, st, g,
                            smp, N, perm, shifts, (const TQ *)Q, (const double *)terms, t0, out,
@@ -2179,6 +2204,16 @@ hipError_t ile_launch_scatter(const uint32_t *keys, int64_t N, uint32_t *offs,
     return hipGetLastError();
 }
 
+hipError_t ile_launch_scatter_copy(const uint32_t *keys, int64_t N, uint32_t *offs,
+                                   int32_t *perm, const double *smp, const int32_t *shifts,
+                                   int nd, double *smp_s, int32_t *sh_s, hipStream_t st)
+{
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_copy, dim3(nblk(N, 256)), dim3(256), 0, st, keys, N, offs, perm,
+                       smp, shifts, nd, smp_s, sh_s);
+    return hipGetLastError();
+}
+
 hipError_t ile_launch_identity(int32_t *perm, int64_t N, hipStream_t st)
 {
     if (N <= 0) return hipSuccess;
@@ -2253,7 +2288,7 @@ hipError_t ile_launch_terms(const ile_geom &g, const double *smp, int64_t N,
 {
     if (N <= 0) return hipSuccess;
     if (terms_lds_bytes(g) > 64 * 1024) return hipErrorInvalidValue;
-    return launch_terms(g, smp, N, perm, shifts, (const double4 *)uvt, 0, N, terms, st);
+    return launch_terms(g, smp, N, perm, shifts, false, (const double4 *)uvt, 0, N, terms, st);
 }
 
 bool ile_contract_uses_terms(ile_precision prec, const ile_tune &tu)
@@ -2265,8 +2300,9 @@ hipError_t ile_launch_contract(const ile_geom &g, ile_precision prec,
                                const ile_tune &tu, const double *smp, int64_t N,
                                const int32_t *perm, const int32_t *shifts,
                                const void *Q, const double *U, const double *V,
-                               const double *uvt, double *terms, int64_t cap, double *out,
-                               double *series, hipStream_t st)
+                               const double *smp_s, const int32_t *sh_s, const double *uvt,
+                               double *terms, int64_t cap, double *out, double *series,
+                               hipStream_t st)
 {
     if (N <= 0) return hipSuccess;
     if (!ile_tune_supported(prec, tu)) return hipErrorInvalidValue;
@@ -2282,12 +2318,12 @@ hipError_t ile_launch_contract(const ile_geom &g, ile_precision prec,
             return hipErrorInvalidValue;
         const size_t dyn = ph_dyn_bytes(16, g.n_det, g.n_lm, gp.wrow, e);
 #define ILE_PH(TQ, NT)                                                                       \
-    return series ? launch_contract_ph<TQ, NT, true>(gp, smp, N, perm, shifts, Q,               \
+    return series ? launch_contract_ph<TQ, NT, true>(gp, smp, N, perm, shifts, smp_s, sh_s, Q,  \
                                                      (const double4 *)uvt, terms, cap, out,    \
                                                      series, dyn, st)                          \
-                  : launch_contract_ph<TQ, NT, false>(gp, smp, N, perm, shifts, Q,              \
-                                                      (const double4 *)uvt, terms, cap, out,   \
-                                                      series, dyn, st)
+                  : launch_contract_ph<TQ, NT, false>(gp, smp, N, perm, shifts, smp_s, sh_s,   \
+                                                      Q, (const double4 *)uvt, terms, cap,     \
+                                                      out, series, dyn, st)
         if (prec == ILE_FP64) {
             if (tu.threads == 256) ILE_PH(double, 256);
             ILE_PH(double, 512);
