@@ -342,27 +342,28 @@ def reuse_leg(n_points=8, target=1e4):
             "max_abs_d_ln_L_over_sigma": float(z)}
 
 
-def combined_leg(n_points=32, n=1_000_000, m_oracle=2000, group=256):
+def combined_leg(n_points=32, n=1_000_000, m_oracle=2000, group=256, first=0):
     """The combined form at the combined workload's per-point shape (3
     detectors, 5-21 modes, 201-1601 bins, 16384-point Q in FP32, 1e6 draws
     per point) on n_points points: a learned proposal per point (trained on
     4 concurrent streams), the draws of a group of points evaluated in one
-    batched persistent run, and the plain adaptive fallback for every point
-    whose n_eff from those draws is below 1e3.  Reports the batched
-    evaluation's throughput (HIP events around its graph), the end-to-end
-    wall time, the fallback and failure counts, and each point's final
-    ln L_marg, n_eff and sigma.  Up to 32 points: one group, with ln L_marg
+    batched persistent run, and the fallback chain (up to two learned retries
+    on fresh seeds, then the plain adaptive sampler) for every point whose
+    n_eff from those draws is below 1e3.  Reports the batched evaluation's
+    throughput (HIP events around its graph), the end-to-end wall time, the
+    fallback, retry and failure counts, the source of each final estimate,
+    and each point's final ln L_marg, n_eff and sigma.  Up to 32 points: one group, with ln L_marg
     against the FP64 oracle on the first m_oracle draws of every point (the
     device value from a batched run of those draws)."""
     import numpy as np
     from oracle import oracle as O
     from paper_1902_04934_amd import combined, synth
-    points = [synth.combined_point(p) for p in range(n_points)]
+    points = [synth.combined_point(p) for p in range(first, first + n_points)]
     work = sum(n * p["n_t"] for p in points)
     t0 = time.perf_counter()
     errs, t_orc = [], 0.0
     if n_points <= 32:
-        res, info, X, lp, lq, batch, t = combined.run_group(points, n)
+        res, info, X, lp, lq, batch, t = combined.run_group(points, n, first=first)
         times = [t]
         wall = time.perf_counter() - t0
         Xs, lps, lqs = X[:, :, :m_oracle].contiguous(), lp[:, :m_oracle].contiguous(), \
@@ -382,20 +383,25 @@ def combined_leg(n_points=32, n=1_000_000, m_oracle=2000, group=256):
         t_orc = time.perf_counter() - t_orc
         batch.close()
     else:
-        info, times = combined.run(points, n, group=group, progress=sys.stderr)
+        info, times = combined.run(points, n, group=group, progress=sys.stderr, first=first)
         wall = time.perf_counter() - t0
     graph_ms = sum(t["eval_graph_ms"] for t in times)
     fin = [i["final"] for i in info]
-    return {"workload": f"{n_points} injected points (3 detectors, 5-21 modes, 201-1601 bins, "
+    return {"workload": f"{n_points} injected points from point {first} (3 detectors, 5-21 modes, 201-1601 bins, "
                         f"Q 16384 points FP32), {n} draws per point from per-point learned "
                         f"proposals, batched evaluation in groups of up to {group} points",
-            "points": n_points, "draws_per_point": n, "groups": len(times),
+            "points": n_points, "first_point": first, "draws_per_point": n,
+            "groups": len(times),
             "eval_graph_ms": graph_ms,
             "eval_sample_bins_per_s": work / (graph_ms * 1e-3),
             "train_and_draw_s": sum(t["train_s"] for t in times),
             "fallback_s": sum(t["fallback_s"] for t in times), "wall_s": wall,
             "points_per_s": n_points / wall,
             "fell_back": sum(i["fell_back"] for i in info),
+            "probe_retrained": sum(i["attempts"] > 1 for i in info),
+            "retries": sum(i["retried"] for i in info),
+            "final_source": {k: sum(f["source"] == k for f in fin)
+                             for k in ("learned", "learned-retry", "adaptive")},
             "failed": sum(i["failed"] for i in info),
             "n_eff": [f["n_eff"] for f in fin], "ln_L_marg": [f["ln_L_marg"] for f in fin],
             "sigma_ln_L": [f["sigma_ln_L"] for f in fin],
@@ -580,6 +586,9 @@ def main():
     ap.add_argument("--combined-points", type=int, default=32,
                     help="points of the combined-form leg (4096: the full workload; above "
                          "32 in groups of 256, without the oracle subset check)")
+    ap.add_argument("--combined-first", type=int, default=0,
+                    help="global index of the combined-form leg's first point (a run of the "
+                         "4096-point workload may be split into ranges)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched form on its 256-point workload")
     ap.add_argument("--no-rom", action="store_true",
@@ -664,7 +673,8 @@ def main():
     out["rom"] = None if args.no_rom else rom_leg()
     out["batched"] = None if args.no_batched else batched_leg()
     out["reuse"] = None if args.no_reuse else reuse_leg()
-    out["combined"] = None if args.no_combined else combined_leg(args.combined_points)
+    out["combined"] = None if args.no_combined else combined_leg(args.combined_points,
+                                                                 first=args.combined_first)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, n_total, seed)
     else:
