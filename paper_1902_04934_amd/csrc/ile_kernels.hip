@@ -1499,8 +1499,9 @@ __device__ inline __amdgpu_buffer_rsrc_t q_rsrc(const TQ *Qk, int bytes)
 // result D[alpha][16 t + c] goes to X[alpha][16 t + c - dd[v]] (alpha =
 // row(lane / 16, v), dd its window start minus smin_k) when that bin is in
 // [0, Jc): stored when `add` is false, else added.  Each (alpha, bin) comes
-// from exactly one lane of one tile.
-template <typename TQ, int NU>
+// from exactly one lane of one tile.  BF: the stores without branches, into
+// X's one element past its 16 rows of xrow bins when out of range.
+template <typename TQ, int NU, bool BF>
 __device__ inline void ph_tiles(TQ *X, int xrow, const TQ *coefk, __amdgpu_buffer_rsrc_t rs,
                                 int qrow0, int nq, int KSP, int P0, const int (&t)[4],
                                 const int (&dd)[4], int Jc, bool add, int lane)
@@ -1542,25 +1543,60 @@ __device__ inline void ph_tiles(TQ *X, int xrow, const TQ *coefk, __amdgpu_buffe
 #pragma unroll
         for (int u = 0; u < NU; u++) acc[u] = M::step(a0, b0[u], acc[u]);
     }
+    if constexpr (BF) {
+        // without branches: a value whose bin is outside [0, Jc) goes to the
+        // slot past the 16 rows (never read as a bin); when adding, every
+        // load is issued before the first sum
+        int a[NU][4];
 #pragma unroll
-    for (int u = 0; u < NU; u++) {
+        for (int u = 0; u < NU; u++) {
+            const int c = 16 * t[u] + col;
 #pragma unroll
-        for (int v = 0; v < 4; v++) {
-            const int jj = 16 * t[u] + col - dd[v];
-            if (jj >= 0 && jj < Jc) {
-                TQ *x = X + M::row(row, v) * xrow + jj;
-                *x = add ? *x + (TQ)acc[u][v] : (TQ)acc[u][v];
+            for (int v = 0; v < 4; v++) {
+                const int jj = c - dd[v];
+                a[u][v] = (unsigned)jj < (unsigned)Jc ? M::row(row, v) * xrow + jj : 16 * xrow;
+            }
+        }
+        if (add) {
+            TQ o[NU][4];
+#pragma unroll
+            for (int u = 0; u < NU; u++)
+#pragma unroll
+                for (int v = 0; v < 4; v++) o[u][v] = X[a[u][v]];
+#pragma unroll
+            for (int u = 0; u < NU; u++)
+#pragma unroll
+                for (int v = 0; v < 4; v++) X[a[u][v]] = o[u][v] + (TQ)acc[u][v];
+        } else {
+#pragma unroll
+            for (int u = 0; u < NU; u++)
+#pragma unroll
+                for (int v = 0; v < 4; v++) X[a[u][v]] = (TQ)acc[u][v];
+        }
+    } else {
+        // the branch form needs fewer registers (FP32 tiles run three
+        // workgroups per CU; the series form holds more state)
+#pragma unroll
+        for (int u = 0; u < NU; u++) {
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int jj = 16 * t[u] + col - dd[v];
+                if (jj >= 0 && jj < Jc) {
+                    TQ *x = X + M::row(row, v) * xrow + jj;
+                    *x = add ? *x + (TQ)acc[u][v] : (TQ)acc[u][v];
+                }
             }
         }
     }
 }
 
 // LDS of the phased tile beyond its static arrays: coefficients
-// [nd][KSP][64], then the chunk bins X [TS][xrow] (the prologue's scratch
-// lives there first).
+// [nd][KSP][64], then the chunk bins X [TS][xrow] and one 16-byte slot that
+// takes the FP64 tiles' stores of bins outside the chunk (the prologue's
+// scratch lives there first).
 __host__ __device__ inline size_t ph_dyn_bytes(int ts, int nd, int nl, int wrow, size_t e)
 {
-    const size_t gb = (size_t)ts * wrow * e;
+    const size_t gb = (size_t)ts * wrow * e + 16;
     const size_t sb = prologue_scratch_bytes(ts, nd, nl);
     return coef_bytes<ENG_MFMA>(ts, nd, nl, e) + (gb > sb ? gb : sb);
 }
@@ -1711,6 +1747,8 @@ __device__ __forceinline__ void contract_tile_ph(
     __syncthreads();
 
     using MA = mfma_acc<TQ>;
+    // FP64 tiles store without branches (measured faster), the others with
+    constexpr bool BF = sizeof(TQ) == 8 && !DUMP;
     const int al = tid / LPS, sub = tid % LPS, row = lane >> 4;
     const bool mem = s_ok[al];
     TQ *X = G;   // [TS][wrow], the chunk's bins of every sample
@@ -1736,10 +1774,10 @@ __device__ __forceinline__ void contract_tile_ph(
                     nu += tt < T;
                 }
                 switch (__builtin_amdgcn_readfirstlane(nu)) {
-                case 4: ph_tiles<TQ, 4>(X, wrow, coefk, rs, k * RP, nq, KSP, smin + j0, t, dd, Jc, k > 0, lane); break;
-                case 3: ph_tiles<TQ, 3>(X, wrow, coefk, rs, k * RP, nq, KSP, smin + j0, t, dd, Jc, k > 0, lane); break;
-                case 2: ph_tiles<TQ, 2>(X, wrow, coefk, rs, k * RP, nq, KSP, smin + j0, t, dd, Jc, k > 0, lane); break;
-                default: ph_tiles<TQ, 1>(X, wrow, coefk, rs, k * RP, nq, KSP, smin + j0, t, dd, Jc, k > 0, lane); break;
+                case 4: ph_tiles<TQ, 4, BF>(X, wrow, coefk, rs, k * RP, nq, KSP, smin + j0, t, dd, Jc, k > 0, lane); break;
+                case 3: ph_tiles<TQ, 3, BF>(X, wrow, coefk, rs, k * RP, nq, KSP, smin + j0, t, dd, Jc, k > 0, lane); break;
+                case 2: ph_tiles<TQ, 2, BF>(X, wrow, coefk, rs, k * RP, nq, KSP, smin + j0, t, dd, Jc, k > 0, lane); break;
+                default: ph_tiles<TQ, 1, BF>(X, wrow, coefk, rs, k * RP, nq, KSP, smin + j0, t, dd, Jc, k > 0, lane); break;
                 }
             }
             __syncthreads();
@@ -2063,7 +2101,7 @@ hipError_t launch_contract_t(const ile_geom &g, const double *smp, int64_t N,
 // start in alternate halves of the 256-byte bank period.  0 if none fits.
 int ph_wrow(int nd, int nl, size_t e, size_t budget)
 {
-    const size_t fixed = coef_bytes<ENG_MFMA>(16, nd, nl, e);
+    const size_t fixed = coef_bytes<ENG_MFMA>(16, nd, nl, e) + 16;   // + the slot past X
     if (budget <= fixed) return 0;
     const int unit = (int)(128 / e);
     const int w = (int)((budget - fixed) / ((size_t)16 * e));
