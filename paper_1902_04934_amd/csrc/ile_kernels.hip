@@ -1067,11 +1067,23 @@ __device__ __forceinline__ double *terms_slot(const ile_geom &g, double *terms, 
     return terms + (r >> 4) * (16 * (int64_t)(2 + 3 * g.n_det + 2 * g.n_lm)) + (r & 15);
 }
 
+// Entry i of the triangles by vector loads at a uniform address (one cache
+// line serves the wave): unlike scalar loads, which complete out of order,
+// they can be waited for one step at a time.
+__device__ __forceinline__ double4 tri_ld(__amdgpu_buffer_rsrc_t r, int i)
+{
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    const u4 lo = __builtin_amdgcn_raw_buffer_load_b128(r, 0, i * 32, 0);
+    const u4 hi = __builtin_amdgcn_raw_buffer_load_b128(r, 0, i * 32 + 16, 0);
+    const double2 x = __builtin_bit_cast(double2, lo), y = __builtin_bit_cast(double2, hi);
+    return make_double4(x.x, x.y, y.x, y.y);
+}
+
 constexpr int kTermsT = 64;    // lanes per block
 
 // Any number of modes: a lane's harmonics are an LDS row of 64 lanes
 // (conflict free, and no lane reads another's: no barrier); the triangles
-// are read at uniform addresses (scalar loads), four entries per step.
+// are read four entries per step, one step ahead (tri_ld).
 __global__ __launch_bounds__(kTermsT) void k_terms(
     ile_geom g, const double *__restrict__ smp, int64_t N, const int32_t *__restrict__ perm,
     const int32_t *__restrict__ shifts, bool in_order, const double4 *__restrict__ uvt,
@@ -1083,6 +1095,8 @@ __global__ __launch_bounds__(kTermsT) void k_terms(
     if (r >= n) return;
     const int nd = g.n_det, nl = g.n_lm, ntri = nl * (nl + 1) / 2;
     double2 *Yl = reinterpret_cast<double2 *>(dyn_lds);   // [nl][64]
+    const __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double4 *>(uvt), (short)0, nd * ntri * (int)sizeof(double4), 0x00020000);
     double *tp = terms_slot(g, terms, r);
     TermsSample S;
     double cp[kPw], sp[kPw], er[kPw], ei[kPw];
@@ -1100,24 +1114,43 @@ __global__ __launch_bounds__(kTermsT) void k_terms(
         tp[(2 + 2 * k) * 16] = S.kap * fp;
         tp[(3 + 2 * k) * 16] = S.kap * fx;
         const double f2 = fp * fp + fx * fx, F2r = fp * fp - fx * fx, F2i = 2.0 * fp * fx;
-        const double4 *row = uvt + (int64_t)k * ntri;
+        int ro = k * ntri;   // row a's first entry (its diagonal)
         for (int a = 0; a < nl; a++) {
             double ur = 0, ui = 0, vr = 0, vi = 0;
             int b = a + 1;
-            for (; b + 3 < nl; b += 4) {
+            if (b + 3 < nl) {
+                // four entries per step, the next step's loads issued before
+                // this step's products (sums still in the order of b)
                 double2 Yb[4];
                 double4 e[4];
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
                     Yb[q] = Yl[(b + q) * kTermsT + lane];
-                    e[q] = row[b + q - a];
+                    e[q] = tri_ld(rt, ro + b + q - a);
+                }
+                for (; b + 7 < nl; b += 4) {
+                    double2 Yn[4];
+                    double4 en[4];
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        Yn[q] = Yl[(b + 4 + q) * kTermsT + lane];
+                        en[q] = tri_ld(rt, ro + b + 4 + q - a);
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; q++) terms_mac(Yb[q], e[q], ur, ui, vr, vi);
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        Yb[q] = Yn[q];
+                        e[q] = en[q];
+                    }
                 }
 #pragma unroll
                 for (int q = 0; q < 4; q++) terms_mac(Yb[q], e[q], ur, ui, vr, vi);
+                b += 4;
             }
-            for (; b < nl; b++) terms_mac(Yl[b * kTermsT + lane], row[b - a], ur, ui, vr, vi);
-            qs += terms_row(Yl[a * kTermsT + lane], row[0], ur, ui, vr, vi, f2, F2r, F2i);
-            row += nl - a;
+            for (; b < nl; b++) terms_mac(Yl[b * kTermsT + lane], uvt[ro + b - a], ur, ui, vr, vi);
+            qs += terms_row(Yl[a * kTermsT + lane], uvt[ro], ur, ui, vr, vi, f2, F2r, F2i);
+            ro += nl - a;
         }
     }
     terms_store(g, S, qs, tp);
