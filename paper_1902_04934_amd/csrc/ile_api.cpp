@@ -81,6 +81,7 @@ struct ile_ctx {
     std::vector<hipEvent_t> ev;   // pairs around contraction launches
     int n_ev_used = 0;
     double last_ms = 0.0;
+    void *hpin = nullptr;   // pinned host words: the error flag, then the 6 result fields
 };
 
 namespace {
@@ -380,9 +381,18 @@ void begin_call(ile_ctx *c)
     c->n_ev_used = 0;
 }
 
-// Wait for the stream, collect kernel times and the sticky error flag.
+// Wait for the stream, collect kernel times and the sticky error flag.  The
+// flag and the 6 result fields (whatever the call left there) come back to
+// pinned host memory with the one wait (fetched_result reads the fields).
 ile_status finish_call(ile_ctx *c)
 {
+    int32_t *hflag = (int32_t *)c->hpin;
+    if (c->errflag.p)
+        HIP_TRY(c, hipMemcpyAsync(hflag, c->errflag.p, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                  c->stream));
+    if (c->res.p)
+        HIP_TRY(c, hipMemcpyAsync((double *)c->hpin + 1, c->res.p, 6 * sizeof(double),
+                                  hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     double tot = 0.0;
     int n = 0;
@@ -394,16 +404,20 @@ ile_status finish_call(ile_ctx *c)
         }
     }
     if (n) c->last_ms = tot / n;
-    int32_t flag = 0;
     if (c->errflag.p) {
-        HIP_TRY(c, hipMemcpy(&flag, c->errflag.p, sizeof(flag), hipMemcpyDeviceToHost));
-        if (flag) {
+        if (*hflag) {
             HIP_TRY(c, hipMemset(c->errflag.p, 0, sizeof(int32_t)));
             return fail(c, ILE_E_RANGE,
                         "a device-side sample was out of range (its output is NaN)");
         }
     }
     return ILE_OK;
+}
+
+// The result fields as of the last finish_call.
+void fetched_result(const ile_ctx *c, double r[6])
+{
+    std::memcpy(r, (const double *)c->hpin + 1, 6 * sizeof(double));
 }
 
 ile_status check_ready(ile_ctx *c)
@@ -501,6 +515,11 @@ ile_status ile_create(const ile_config *cfg, ile_ctx **out)
             return ILE_E_DEVICE;
         }
         c->own_stream = true;
+    }
+    if (hipHostMalloc(&c->hpin, 64, hipHostMallocDefault) != hipSuccess) {
+        c->hpin = nullptr;
+        ile_destroy(c);
+        return ILE_E_DEVICE;
     }
     ile_geom &g = c->g;
     g.n_det = cfg->n_det;
@@ -1047,7 +1066,7 @@ ile_status ile_integrate(ile_ctx *c, const double *samples, const double *ln_p,
         return s;
     if ((s = finish_call(c))) return s;
     double r[6];
-    HIP_TRY(c, hipMemcpy(r, c->res.p, sizeof(r), hipMemcpyDeviceToHost));
+    fetched_result(c, r);
     copy_result(r, out);
     return ILE_OK;
 }
@@ -1153,7 +1172,7 @@ ile_status ile_run_prior(ile_ctx *c, uint64_t seed, int64_t N, int64_t chunk,
                                  (double *)c->res.p, c->stream));
     if ((s = finish_call(c))) return s;
     double r[6];
-    HIP_TRY(c, hipMemcpy(r, c->res.p, sizeof(r), hipMemcpyDeviceToHost));
+    fetched_result(c, r);
     copy_result(r, out);
     return ILE_OK;
 }
@@ -1442,7 +1461,7 @@ static ile_status run_learned(ile_ctx *c, const ile_run_opts *o, ile_result *out
         if (o->n_eff_target > 0 && r[1] >= o->n_eff_target) break;
     }
     if ((s = finish_call(c))) return s;
-    HIP_TRY(c, hipMemcpy(r, c->res.p, sizeof(r), hipMemcpyDeviceToHost));
+    fetched_result(c, r);
     copy_result(r, out);
     if (n_chunks_out) *n_chunks_out = ci;
     return ILE_OK;
@@ -1523,7 +1542,7 @@ ile_status ile_run(ile_ctx *c, const ile_run_opts *o, ile_result *out, int64_t *
         if (adapting && o->adapt_chunks >= 0 && ci >= o->adapt_chunks) adapting = false;
     }
     if ((s = finish_call(c))) return s;
-    HIP_TRY(c, hipMemcpy(r, c->res.p, sizeof(r), hipMemcpyDeviceToHost));
+    fetched_result(c, r);
     copy_result(r, out);
     if (n_chunks_out) *n_chunks_out = ci;
     return ILE_OK;
@@ -1603,6 +1622,7 @@ void ile_destroy(ile_ctx *c)
         release(*b);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    if (c->hpin) (void)hipHostFree(c->hpin);
     delete c;
 }
 
