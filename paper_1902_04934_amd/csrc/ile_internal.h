@@ -77,23 +77,30 @@ struct ile_point_dev {
 // ordering keys of concentrated draws fall into few buckets, where one
 // atomic per lane serializes).  Returns the lane's slot: the table value
 // before the wave's increment plus the lane's rank among the lanes with its
-// key.  Every active lane of the wave must call it.
+// key.  The groups of equal keys are found first (register work only), then
+// the first lane of every group issues its atomic, all of them in one
+// instruction, so a wave waits for one atomic round trip however many
+// distinct keys it holds.  Every active lane of the wave must call it.
 __device__ inline uint32_t wave_count_slot(uint32_t *table, uint32_t key)
 {
     uint64_t todo = __ballot(1);
     const int lane = __lane_id();
-    uint32_t slot = 0;
+    int lead = lane;
+    uint32_t rank = 0, cnt = 0;
     while (todo) {
         const int leader = __ffsll((unsigned long long)todo) - 1;
         const uint32_t k0 = __shfl(key, leader);
         const uint64_t same = __ballot(key == k0);
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&table[k0], (uint32_t)__popcll(same));
-        base = __shfl(base, leader);
-        if (key == k0) slot = base + (uint32_t)__popcll(same & ((1ull << lane) - 1));
+        if (key == k0) {
+            lead = leader;
+            rank = (uint32_t)__popcll(same & ((1ull << lane) - 1));
+            cnt = (uint32_t)__popcll(same);
+        }
         todo &= ~same;
     }
-    return slot;
+    uint32_t base = 0;
+    if (lead == lane) base = atomicAdd(&table[key], cnt);
+    return __shfl(base, lead) + rank;
 }
 
 // Ordering key of a sample: its cell (window starts of up to three
