@@ -93,3 +93,40 @@ def test_noalloc_refuses_more_than_its_limit(torch):
         a, b = _both(torch, ctx, e, np.zeros(0), np.zeros(0))
         assert np.array_equal(a, b, equal_nan=True)
         assert a[5] == 0
+
+
+def test_noalloc_under_graph_capture(torch):
+    """The allocation-free call recorded into a HIP graph (torch's graph
+    capture on the context's own stream) and replayed three times on new
+    samples written in place between the replays, with eager calls of the
+    library and synchronizations in between: every replay equals
+    ile_integrate_dev on the same samples, bit for bit."""
+    inst = synth.config1()
+    n = 20_000
+    st = torch.cuda.Stream()
+    with ile.Context(inst, stream=st.cuda_stream) as ctx:
+        S, P, Q = (_dev(torch, x) for x in _inputs(n, 7401))
+        r_g = torch.full((6,), np.nan, dtype=torch.float64, device="cuda")
+        r_ref = torch.full((6,), np.nan, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        # an eager call first: the kernels' LDS limits are set outside the capture
+        ctx.integrate_dev_noalloc(S, P, Q, n, r_g)
+        ctx.sync()
+        print("capture", flush=True)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=st, capture_error_mode="relaxed"):
+            ctx.integrate_dev_noalloc(S, P, Q, n, r_g)
+        for seed in (7402, 7403, 7404):
+            print(f"replay on the samples of seed {seed}", flush=True)
+            for dst, src in zip((S, P, Q), _inputs(n, seed)):
+                dst.copy_(_dev(torch, src))
+            r_g.fill_(np.nan)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            got = r_g.cpu().numpy()
+            ctx.integrate_dev(S, P, Q, n, r_ref)
+            ctx.sync()
+            want = r_ref.cpu().numpy()
+            assert np.all(np.isfinite(got)) and got[5] == n
+            assert np.array_equal(got, want), (seed, got, want)
