@@ -535,7 +535,8 @@ def latency_leg(calls=50):
     """The small workload as a latency: 2 detectors, 5 modes (l = 2), Q of
     4096 points at 4096 Hz, 201 bins, 1e4 prior samples per call; host wall
     time of one whole call (device prior draw, ordering, contraction,
-    reduction, result to the host) and the contraction's event time."""
+    reduction, result to the host) and the contraction's event time; then
+    the same call as a HIP graph replay (_latency_graph)."""
     import statistics
     from paper_1902_04934_amd import ile, synth
     inst = synth.config1()
@@ -550,12 +551,50 @@ def latency_leg(calls=50):
             walls.append((time.perf_counter() - t0) * 1e3)
             kms.append(ctx.last_kernel_ms())
     walls.sort()
+    graph = _latency_graph(inst, n, seed, calls, r)
     return {"workload": "2 detectors, 5 modes (l=2), Q 4096 points at 4096 Hz, "
                         f"{n} prior samples, {inst.n_t} time bins, FP64",
             "calls": calls, "wall_ms_median": statistics.median(walls),
             "wall_ms_p90": walls[int(0.9 * (calls - 1))],
             "kernel_ms_median": statistics.median(kms),
-            "ln_L_marg": r["ln_L_marg"], "n_eff": r["n_eff"]}
+            "ln_L_marg": r["ln_L_marg"], "n_eff": r["n_eff"], "graph": graph}
+
+
+def _latency_graph(inst, n, seed, calls, eager):
+    """The same call recorded once into a HIP graph (the device prior draw,
+    then the allocation-free integrate) and replayed per call; wall time of a
+    replay plus the result's copy to pinned host memory, and whether the
+    replayed result equals the eager call's."""
+    import statistics
+    import torch
+    from paper_1902_04934_amd import ile
+    st = torch.cuda.Stream()
+    with ile.Context(inst, stream=st.cuda_stream) as ctx:
+        X = torch.empty((7, n), dtype=torch.float64, device="cuda")
+        r = torch.empty(6, dtype=torch.float64, device="cuda")
+        host = torch.empty(6, dtype=torch.float64, pin_memory=True)
+        torch.cuda.synchronize()
+        ctx.draw_prior_dev(seed, 0, n, X, n)           # eager first: kernel limits set
+        ctx.integrate_dev_noalloc(X, None, None, n, r)
+        ctx.sync()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=st, capture_error_mode="relaxed"):
+            ctx.draw_prior_dev(seed, 0, n, X, n)
+            ctx.integrate_dev_noalloc(X, None, None, n, r)
+        cur = torch.cuda.current_stream()
+        walls = []
+        for i in range(5 + calls):
+            t0 = time.perf_counter()
+            g.replay()
+            host.copy_(r, non_blocking=True)
+            cur.synchronize()
+            if i >= 5:
+                walls.append((time.perf_counter() - t0) * 1e3)
+        res = host.numpy().copy()
+    walls.sort()
+    return {"wall_ms_median": statistics.median(walls),
+            "wall_ms_p90": walls[int(0.9 * (calls - 1))],
+            "equals_eager": bool(res[0] == eager["ln_L_marg"] and res[1] == eager["n_eff"])}
 
 
 def main():
