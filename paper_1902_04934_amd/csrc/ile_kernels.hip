@@ -1649,6 +1649,14 @@ __device__ __forceinline__ void ph_lphase(const TQ *X, int Jc, int o, double &m,
         if (DUMP) srow[i] = x - q;
         return x;
     };
+    // the terms e^d: FP64 tiles by exp_lse; FP32 tiles, whose bin values
+    // carry FP32 rounding already, by the single-precision exponential (its
+    // relative error, a few 1e-8, is below that of the values; the sums and
+    // the reference stay FP64)
+    const auto ex = [](double d) -> double {
+        if constexpr (sizeof(TQ) == 4) return (double)expf((float)d);
+        else return exp_lse(d);
+    };
     const auto fold = [&](double x) {
         double d = x - m;
         if (d > kLseSlack) {
@@ -1656,7 +1664,7 @@ __device__ __forceinline__ void ph_lphase(const TQ *X, int Jc, int o, double &m,
             m = x;
             d = 0.0;
         }
-        ssum += exp_lse(d);
+        ssum += ex(d);
     };
     // two bins at a time: when neither moves the reference, their exps are
     // independent (the sums are still taken in bin order, as fold would)
@@ -1668,7 +1676,7 @@ __device__ __forceinline__ void ph_lphase(const TQ *X, int Jc, int o, double &m,
             fold(x0);
             fold(x1);
         } else {
-            const double e0 = exp_lse(d0), e1 = exp_lse(d1);
+            const double e0 = ex(d0), e1 = ex(d1);
             ssum += e0;
             ssum += e1;
         }
