@@ -75,11 +75,11 @@ def run_group(points, n, *, precision="fp32", seed=51, draw_seed=7001, eps=0.1,
     """One group: train a proposal per point (points: list of
     synth.combined_point parts; global index first + p seeds point p; a
     training run whose probe falls back is repeated on a fresh seed up to
-    `retries` times; see TRAINING for the budgets), draw n samples per point, evaluate the group in one
-    batched run, then apply the fallback chain to the points whose batched
-    estimate has n_eff < n_eff_min.  Returns (batched results on the draws,
-    per-point info with the final estimate, device draws X [P][7][n], ln p,
-    ln q, the Batch, timings)."""
+    `retries` times; see TRAINING for the budgets), draw n samples per
+    point, evaluate the group in one batched run, then apply the fallback
+    chain to the points whose batched estimate has n_eff < n_eff_min.
+    Returns (batched results on the draws, per-point info with the final
+    estimate, device draws X [P][7][n], ln p, ln q, the Batch, timings)."""
     import torch
     P = len(points)
     X = torch.empty((P, 7, n), dtype=torch.float64, device="cuda")
@@ -138,7 +138,7 @@ def run_group(points, n, *, precision="fp32", seed=51, draw_seed=7001, eps=0.1,
         graph_ms = batch.last_ms()
         # fallback chain on the draws that form the estimate
         t0 = time.perf_counter()
-        fell = [p for p in range(P) if res[p]["n_eff"] < n_eff_min]
+        fell = {p for p in range(P) if res[p]["n_eff"] < n_eff_min}
         if fell:
             Xr = torch.empty((7, n), dtype=torch.float64, device="cuda")
             lpr = torch.empty(n, dtype=torch.float64, device="cuda")
