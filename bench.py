@@ -387,8 +387,9 @@ def combined_leg(n_points=32, n=1_000_000, m_oracle=2000, group=256, first=0):
         wall = time.perf_counter() - t0
     graph_ms = sum(t["eval_graph_ms"] for t in times)
     fin = [i["final"] for i in info]
-    return {"workload": f"{n_points} injected points from point {first} (3 detectors, 5-21 modes, 201-1601 bins, "
-                        f"Q 16384 points FP32), {n} draws per point from per-point learned "
+    return {"workload": f"{n_points} injected points from point {first} (3 detectors, 5-21 "
+                        f"modes, 201-1601 bins, Q 16384 points FP32), {n} draws per point "
+                        f"from per-point learned "
                         f"proposals, batched evaluation in groups of up to {group} points",
             "points": n_points, "first_point": first, "draws_per_point": n,
             "groups": len(times),
