@@ -2080,6 +2080,63 @@ __global__ __launch_bounds__(kRedT) void k_red_final(const double *tmp,
     }
 }
 
+// The same partial from one workgroup when N is small (at most
+// kRedSmallMax): the three kernels above cost more in launches and in their
+// mostly idle blocks than the work.  Same quantities, its own summation tree.
+constexpr int kRedSmallT = 1024;
+constexpr int64_t kRedSmallMax = 16384;
+
+__global__ __launch_bounds__(kRedSmallT) void k_red_small(const double *lnL, const double *lp,
+                                                           const double *lq, int64_t N,
+                                                           double *partial)
+{
+    __shared__ double sa[kRedSmallT], sb[kRedSmallT], sc[kRedSmallT];
+    const int t = threadIdx.x;
+    double M = -INFINITY, ML = -INFINITY;
+    for (int64_t i = t; i < N; i += kRedSmallT) {
+        const double w = lnw_at(lnL, lp, lq, i);
+        M = w > M ? w : M;
+        ML = lnL[i] > ML ? lnL[i] : ML;
+    }
+    sa[t] = M;
+    sc[t] = ML;
+    __syncthreads();
+    for (int h = kRedSmallT / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            sa[t] = fmax(sa[t], sa[t + h]);
+            sc[t] = fmax(sc[t], sc[t + h]);
+        }
+        __syncthreads();
+    }
+    const double Mg = sa[0];
+    __syncthreads();
+    double a = 0.0, b = 0.0;
+    if (Mg != -INFINITY) {
+        for (int64_t i = t; i < N; i += kRedSmallT) {
+            const double e = exp(lnw_at(lnL, lp, lq, i) - Mg);
+            a += e;
+            b += e * e;
+        }
+    }
+    sa[t] = a;
+    sb[t] = b;
+    __syncthreads();
+    for (int h = kRedSmallT / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            sa[t] += sa[t + h];
+            sb[t] += sb[t + h];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        partial[0] = Mg;
+        partial[1] = sa[0];
+        partial[2] = sb[0];
+        partial[3] = (double)N;
+        partial[4] = sc[0];
+    }
+}
+
 __global__ void k_finish(const double *parts, int n_part, double *res)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -2527,6 +2584,11 @@ hipError_t ile_launch_reduce(const double *lnL, const double *ln_p,
                              const double *ln_q, int64_t N, double *tmp,
                              double *partial, hipStream_t st)
 {
+    if (N <= kRedSmallMax) {
+        hipLaunchKernelGGL(k_red_small, dim3(1), dim3(kRedSmallT), 0, st, lnL, ln_p, ln_q, N,
+                           partial);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_red_max, dim3(kRedBlocks), dim3(kRedT), 0, st, lnL, ln_p,
                        ln_q, N, tmp);
     hipLaunchKernelGGL(k_red_sum, dim3(kRedBlocks), dim3(kRedT), 0, st, lnL, ln_p,
